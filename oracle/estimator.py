@@ -1,0 +1,145 @@
+"""Oracle: the binned bispectrum estimator, Eqs. (10)-(12), in FP64.
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+Definition followed (Gill et al. 2024, Sec. 2):
+    D(l_m, theta) = sum_{g in a_m} W_g V_g exp(-i l_g . theta)       Eq. (10)
+    I(l_m, theta) = sum_{g in a_m} W_g     exp(-i l_g . theta)       Eq. (11)
+    B-hat(l1,l2,l3) = (1/A) sum_theta D1 D2 D3 / sum_theta I1 I2 I3  Eq. (12)
+with l_g . theta = 2 pi g . x / n on the n x n periodic grid, so each field is a
+plain forward 2-D DFT of its masked ring (numpy.fft.fft2, FP64).
+
+Readings (also listed in the design doc):
+* the input is defined through its Hermitian part, X(g) = (W V(g) + conj(W V(-g)))/2
+  and Y(g) = (W(g) + W(-g))/2, so both fields are real; for Hermitian input this
+  is exactly the paper's sum (the imaginary part of the triple sum is zero);
+* weights: UNIT (W = 1), INV_COUNT (W = 1/N_g for N_g >= 0.5, else 0, the paper's
+  choice with N_g the gridded count) or GIVEN (W supplied);
+* reported sums are normalised per triangle: S_t = sum_theta D_i D_j D_k / n^2 and
+  N_t = sum_theta I_i I_j I_k / n^2, which equal the sums over closed triangles
+  (mod n) of X X X and Y Y Y; B_t = S_t / (A N_t).
+
+Pins: tests/test_oracle_estimator.py (brute force over closed triangles on
+n = 8, 16, 32 in cyclic and planar form, integer counts, invariants, the
+two-field Parseval special case, zero-mean Gaussian and the closed-form
+local-quadratic bispectrum of Eq. 14).
+"""
+import numpy as np
+
+UNIT, INV_COUNT, GIVEN = 0, 1, 2
+
+
+def mirror(A):
+    """A(-g) on the periodic grid: element [i, j] -> A[-i mod n, -j mod n]."""
+    n0, n1 = A.shape[-2:]
+    iy = (-np.arange(n0)) % n0
+    ix = (-np.arange(n1)) % n1
+    return A[..., iy[:, None], ix[None, :]]
+
+
+def hermitian_part(A):
+    return 0.5 * (A + np.conj(mirror(A)))
+
+
+def effective_weights(n, w, wmode):
+    """W_g of Sec. 2 (the paragraph after Eq. 10) for the three weight modes."""
+    if wmode == UNIT:
+        return np.ones((n, n), np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    if wmode == INV_COUNT:
+        out = np.zeros_like(w)
+        ok = w >= 0.5
+        out[ok] = 1.0 / w[ok]
+        return out
+    if wmode == GIVEN:
+        return w.copy()
+    raise ValueError("unknown weight mode")
+
+
+def ring_fields(Xfull, masks):
+    """Real fields sum_{g in a_m} X(g) exp(-2 pi i g.x / n) for every ring m."""
+    return np.stack([np.fft.fft2(np.where(m, Xfull, 0)).real for m in masks])
+
+
+def _pairs_of(trips):
+    pairs = sorted(set((int(i), int(j)) for i, j, _ in trips))
+    return pairs, {p: q for q, p in enumerate(pairs)}
+
+
+def triple_sums(F, trips, chunk=1 << 16, power=1):
+    """sum_theta (F_i F_j F_k)^power / n^2 per triplet, by chunked FP64 GEMM.
+
+    Pair products P_(ij)(theta) = F_i F_j are formed for a chunk of pixels and
+    multiplied against F_k; nothing is blocked beyond that.
+    """
+    trips = [tuple(int(x) for x in t) for t in trips]
+    nb = F.shape[0]
+    npix = F.shape[1] * F.shape[2]
+    Ff = F.reshape(nb, npix)
+    pairs, pidx = _pairs_of(trips)
+    acc = np.zeros((len(pairs), nb), np.float64)
+    pi = np.array([p[0] for p in pairs], dtype=np.int64)
+    pj = np.array([p[1] for p in pairs], dtype=np.int64)
+    for s in range(0, npix, chunk):
+        Fc = Ff[:, s:s + chunk]
+        if power != 1:
+            Fc = Fc ** power
+        P = Fc[pi] * Fc[pj]
+        acc += P @ Fc.T
+    out = np.array([acc[pidx[(i, j)], k] for i, j, k in trips], dtype=np.float64)
+    return out / float(npix)
+
+
+def estimate(grid, w, edges, norm, wmode=UNIT, trips=None, with_scales=False, chunk=1 << 16):
+    """Eq. (12) for one n x n gridded-visibility array.
+
+    grid  : complex [n][n], row index = v cell, column = u cell, DC at [0][0]
+    w     : counts / weights [n][n] (ignored for UNIT)
+    edges : ring edges (nb + 1, grid units)
+    norm  : the normalisation A of Eq. (12)
+    trips : (T, 3) i <= j <= k; default = plan.plan_triplets(n, edges)
+    Returns a dict with B, S, N (each length T), trips, and with_scales adds the
+    FP64 random-error scales rhoS = sqrt(sum (D D D)^2)/n^2, rhoN likewise.
+    """
+    from . import plan as _plan
+    grid = np.asarray(grid).astype(np.complex128)
+    n = grid.shape[0]
+    if trips is None:
+        trips, _ = _plan.plan_triplets(n, edges)
+    trips = np.asarray(trips, dtype=np.int64).reshape(-1, 3)
+    W = effective_weights(n, w, wmode)
+    masks = _plan.ring_masks(n, edges)
+    X = hermitian_part(W * grid)
+    Y = hermitian_part(W.astype(np.complex128))
+    D = ring_fields(X, masks)
+    I = ring_fields(Y, masks)
+    S = triple_sums(D, trips, chunk)
+    N = triple_sums(I, trips, chunk)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        B = S / (norm * N)
+    out = dict(B=B, S=S, N=N, trips=trips)
+    if with_scales:
+        out["rhoS"] = np.sqrt(np.maximum(triple_sums(D, trips, chunk, power=2), 0.0) / n ** 2)
+        out["rhoN"] = np.sqrt(np.maximum(triple_sums(I, trips, chunk, power=2), 0.0) / n ** 2)
+    return out
+
+
+def relative_error(B, ref, norm):
+    """Noise-scale-normalised error e_t = |B - B*| / max(|B*|, rho_t).
+
+    rho_t = rhoS / (A |N*|) is the FP64 random-error scale of B*_t: per-triplet
+    relative error is unbounded where the signed triangle sum cancels, so the
+    gate compares against the larger of the value and the scale of its terms.
+    ``ref`` is an ``estimate(..., with_scales=True)`` result, ``B`` the value
+    under test and ``norm`` the A of Eq. (12).
+    """
+    Bs, N = ref["B"], ref["N"]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rho = ref["rhoS"] / (norm * np.abs(N))
+        return np.abs(np.asarray(B) - Bs) / np.maximum(np.abs(Bs), rho)
+
+
+def count_error(N, ref):
+    """|N - N*| / max(|N*|, rhoN): the same normalisation for the denominator."""
+    Ns = ref["N"]
+    return np.abs(np.asarray(N) - Ns) / np.maximum(np.abs(Ns), ref["rhoN"])
