@@ -1,0 +1,172 @@
+"""Throughput of the bispectrum hot path on one MI355X.
+
+One step = gridding of nvis = n^2 visibilities for a batch of realisations of one
+MWA-shaped channel (shared baselines, Eq. 9) followed by the estimator of Eq. (12)
+for the batch (ring FFTs, triplet contraction, normalisation), with the gridded
+counts as shared INV_COUNT weights.  Inputs are resident in HBM before timing.
+
+Prints one JSON line: grids/s, bin-triplets/s, the roofline of the dominant kernel
+(the triplet contraction; its duration comes from HIP events recorded by the library
+around that launch on the call's stream) and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # MWA-shaped single channel: 1024^2 complex64, 20 log rings over 46 <= l < 1320
+    "mwa1024": dict(n=1024, nbins=20, lmin=46.0, lmax=1320.0, batch=16, cfg=1,
+                    desc="MWA-shaped single channel: 1024x1024 c64 grid, 20 log rings 46<=l<1320, "
+                         "Poisson baseline mask + SNR-5 noise, INV_COUNT weights, FP32"),
+    # precision-form shapes in FP32: 4096^2, 32 log rings, edges x4
+    "mwa4096": dict(n=4096, nbins=32, lmin=4 * 46.0, lmax=4 * 1320.0, batch=2, cfg=2,
+                    desc="4096x4096 c64 grid, 32 log rings, FP32"),
+}
+class HipEvents:
+    """Raw HIP events (the library records them on the call's stream)."""
+
+    def __init__(self, count):
+        import ctypes
+        self._c = ctypes
+        self.hip = ctypes.CDLL("libamdhip64.so.7")   # the runtime torch already loaded
+        self.ev = []
+        for _ in range(2 * count):
+            e = ctypes.c_void_p()
+            if self.hip.hipEventCreate(ctypes.byref(e)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.ev.append(e)
+
+    def pair(self, k):
+        return self.ev[2 * k], self.ev[2 * k + 1]
+
+    def elapsed_ms(self, k):
+        ms = self._c.c_float()
+        a, b = self.pair(k)
+        if self.hip.hipEventElapsedTime(self._c.byref(ms), a, b) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return ms.value
+
+    def close(self):
+        for e in self.ev:
+            self.hip.hipEventDestroy(e)
+        self.ev = []
+
+
+PEAK_VALU_FP32 = 78.6e12   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
+PEAK_HBM = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mwa1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(n, edges, trips, uv, vis, norm, budget_s):
+    """The FP64 oracle as it stands (gridding + estimator) on a bounded sample."""
+    from oracle import estimator as oest
+    from oracle import gridding as ogrid
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    done, t0 = 0, time.perf_counter()
+    while True:
+        g, w, _ = ogrid.grid_visibilities(n, 1.0, uv, vis[done % len(vis)])
+        oest.estimate(g, w, edges, norm, wmode=oest.INV_COUNT, trips=trips)
+        done += 1
+        if time.perf_counter() - t0 >= budget_s or done >= 16:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "grids/s", "cores": int(cores), "kind": "oracle",
+            "sample": "%d realisation(s): FP64 gridding of %d visibilities + estimator "
+                      "(numpy FFT, BLAS %d threads), %.1f s" % (done, len(uv), cores, dt)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py: this build measures one GPU only (--gpus 1); %d GPUs is not supported"
+              % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2412_02246_amd as A
+    import synth
+
+    W = WORKLOADS[a.workload]
+    n, nb, batch = W["n"], W["nbins"], (a.batch or W["batch"])
+    edges = (W["lmin"] / (2 * np.pi)) * ((W["lmax"] / W["lmin"]) ** (np.arange(nb + 1) / nb))
+    nvis = n * n
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    print("bench: workload %s n=%d rings=%d batch=%d nvis=%d" % (a.workload, n, nb, batch, nvis),
+          file=sys.stderr, flush=True)
+    uv, vis = synth.mwa_visibilities(n, nvis, edges[-1], synth.seed_for(W["cfg"], 0), batch=batch)
+    plan = A.Plan(n, edges, wmode=A.W_INV_COUNT, max_batch=batch).bind()
+    print("bench: plan ntrip=%d npairs=%d; inputs generated" % (plan.ntrip, plan.npairs),
+          file=sys.stderr, flush=True)
+    uv_d = torch.from_numpy(uv).to(dev)
+    vis_d = torch.from_numpy(vis).to(dev)
+
+    def step():
+        g, w, _ = plan.grid(uv_d, vis_d)
+        return plan.estimate(g, w)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    L = A._lib
+    ev = HipEvents(a.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        L.lib().abs_profile(plan.handle, L.STAGE_CONTRACT, *ev.pair(k))
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    L.lib().abs_profile(plan.handle, L.STAGE_CONTRACT, None, None)
+    con_ms = float(np.mean([ev.elapsed_ms(k) for k in range(a.steps)]))
+    ev.close()
+    ms = 1e3 * dt / a.steps
+    grids_s = batch * a.steps / dt
+    nsets = batch + 1
+    flops = float(nsets) * n * n * (plan.npairs + 2 * plan.ntrip)
+    achieved = flops / (con_ms * 1e-3)
+    out = {
+        "metric": "bispectrum grids/s at 1 GPU (gridding + estimator)",
+        "value": grids_s, "unit": "grids/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": W["desc"], "n": n, "nbins": nb, "grids_per_step": batch,
+                   "nvis_per_grid": nvis, "ntrip": int(plan.ntrip),
+                   "bin_triplets_per_s": grids_s * plan.ntrip, "parallelism": "1 GPU"},
+        "roofline": {"kernel": "abs_contract (triplet contraction)", "bound": "alu",
+                     "achieved": achieved / 1e12, "peak": PEAK_VALU_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_VALU_FP32, "traffic": None,
+                     "avg_ms": con_ms, "flops_per_launch": flops},
+    }
+    if not a.no_cpu:
+        e_sample = min(batch, 2)
+        out["cpu_baseline"] = cpu_baseline(n, edges, plan.triplets, uv, vis[:e_sample], plan.norm,
+                                           a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * abs.h -- C ABI of the MI355X (gfx950) FFT binned angular bispectrum library.
+ *
+ * The estimator is the one of Gill, Bharadwaj, Ali & Elahi (2024), "A visibility-based
+ * angular bispectrum estimator for radio-interferometric data":
+ *   - visibilities are gridded onto a uv grid of spacing dU_g (Sec. 2, Eq. 9);
+ *   - the grid is cut into annular rings a_m (Sec. 2, the ring construction);
+ *   - per ring, the data field D_m (Eq. 10) and the weight field I_m (Eq. 11) are
+ *     inverse Fourier transforms of the ring-restricted W V and W;
+ *   - for every ring triplet, B-hat = (1/A) sum_theta D1 D2 D3 / sum_theta I1 I2 I3 (Eq. 12),
+ *     the weighted average over all closed triangles with one vertex per ring.
+ *
+ * Conventions shared by every call:
+ *   - grids are n x n, row-major, row index = v cell, column index = u cell, DC at
+ *     [0][0]; index i stands for the signed cell i < n/2 ? i : i - n;
+ *   - a cell g belongs to ring m iff edges[m]^2 <= |g|^2 < edges[m+1]^2, compared as
+ *     the exact integer |g|^2 against the FP64 squares of the edges;
+ *   - the input is defined through its Hermitian part X(g) = (W V(g) + conj(W V(-g)))/2
+ *     and Y(g) = (W(g) + W(-g))/2, so every field is real;
+ *   - triplets are stored i <= j <= k (ascending ring index), so ell1 = ell_k,
+ *     ell2 = ell_j, ell3 = ell_i; a triplet is kept when its rings contain at least
+ *     one closed lattice triangle (decided exactly on the host);
+ *   - reported sums are per triangle: S_t = (1/n^2) sum_theta D_i D_j D_k equals the sum
+ *     of X(g1) X(g2) X(g3) over closed triangles, N_t likewise with Y, and
+ *     B_t = S_t / (A N_t); where N_t is exactly zero B_t is the IEEE quotient;
+ *   - device pointers are caller-owned and must stay valid until the stream work that
+ *     uses them has finished; the library never allocates device memory;
+ *   - every function returns a status code; none aborts or prints.  Launch or device
+ *     errors surface as ABS_ERR_DEVICE from the call that saw them or from abs_sync;
+ *   - `stream` arguments are hipStream_t values passed as void* (NULL = default stream).
+ */
+#ifndef ABS_H_
+#define ABS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum abs_status {
+  ABS_OK = 0,
+  ABS_ERR_INVALID = 1,  /* bad argument: null pointer, size, mode, alignment, batch */
+  ABS_ERR_ALIAS = 2,    /* rings reach |g| > n/3, where triangles wrap, without ABS_ALLOW_WRAP */
+  ABS_ERR_UNBOUND = 3,  /* the plan has no device memory yet (see abs_plan_bind) */
+  ABS_ERR_DEVICE = 4,   /* a HIP runtime call or kernel launch failed */
+  ABS_ERR_JIT = 5,      /* run-time compilation of the plan's contraction kernel failed */
+  ABS_ERR_NOMEM = 6,    /* host allocation failed, or a caller buffer is too small */
+  ABS_ERR_EMPTY = 7     /* no ring triplet contains a closed lattice triangle */
+} abs_status;
+
+/* precision of the triplet contraction (the ring FFTs are always FP32) */
+enum { ABS_FP32 = 0, ABS_BF16X3 = 1, ABS_FP16X3 = 2 };
+/* weight modes (Sec. 2, the paragraph after Eq. 10) */
+enum { ABS_W_UNIT = 0,      /* W = 1 on every ring cell                                */
+       ABS_W_INV_COUNT = 1, /* w holds gridded counts N_g: W = 1/N_g if N_g >= 0.5 else 0 */
+       ABS_W_GIVEN = 2 };   /* w holds W itself (must be symmetric, W(-g) = W(g))      */
+/* element type of the gridded visibilities passed to abs_estimate */
+enum { ABS_C64 = 0, ABS_C128 = 1 };
+/* gridding kernels (Eq. 9) */
+enum { ABS_NEAREST = 0, ABS_GAUSS7 = 1 };
+/* plan flags */
+#define ABS_ALLOW_WRAP 1u /* accept rings beyond n/3: triangles then close modulo n */
+#define ABS_ALLOW_DC 2u   /* accept edges[0] == 0, i.e. a ring holding g = 0 (tests) */
+
+typedef struct abs_plan_s* abs_plan_t;
+
+typedef struct abs_plan_desc {
+  int32_t n;            /* grid side, power of two, 16 <= n <= 8192                    */
+  int32_t nbins;        /* number of rings, 1 <= nbins <= 64                          */
+  const double* edges;  /* host, nbins + 1 strictly increasing radii in grid cells;   */
+                        /* copied by abs_plan                                         */
+  double du;            /* grid spacing dU_g in wavelengths (Eq. 9, Sec. 3); labels   */
+                        /* use ell = 2 pi du |g| and gridding uses g = rint(U / du)    */
+  double norm;          /* the A of Eq. (12); <= 0 selects pi theta0^2 / 3             */
+  double theta0;        /* Gaussian beam width of Eq. (6) in radians, for ABS_GAUSS7   */
+                        /* and the default norm; <= 0 selects 0.6 x 24.68 deg          */
+  int32_t precision;    /* ABS_FP32, ABS_BF16X3 or ABS_FP16X3                          */
+  int32_t wmode;        /* ABS_W_UNIT, ABS_W_INV_COUNT or ABS_W_GIVEN                  */
+  int32_t max_batch;    /* largest batch abs_estimate / abs_grid will be given (>= 1) */
+  uint32_t flags;       /* ABS_ALLOW_WRAP | ABS_ALLOW_DC                               */
+} abs_plan_desc;
+
+typedef struct abs_plan_info {
+  int32_t n, nbins;
+  int64_t ntrip;        /* number of ring triplets the plan evaluates                  */
+  int64_t npairs;       /* distinct (i, j) ring pairs among them                      */
+  int64_t ncols;        /* half-plane uv columns the ring FFTs touch, summed over rings */
+  int64_t plan_bytes;   /* device bytes abs_plan_bind needs                           */
+  double norm;          /* the A actually used                                        */
+} abs_plan_info;
+
+/* Build a plan on the host: rings (Sec. 2), the triplet list with an exact lattice
+ * test (Sec. 3, "every possible combination of three annular rings"), per-triplet
+ * labels and the device tables.  No HIP call is made.
+ * Errors: ABS_ERR_INVALID (n not a power of two in [16, 8192], nbins out of range,
+ * edges not strictly increasing or negative, edges[0] == 0 without ABS_ALLOW_DC,
+ * bad mode, max_batch < 1), ABS_ERR_ALIAS (edges[nbins] > n/3 without ABS_ALLOW_WRAP,
+ * or any ring reaching |g| >= n/2), ABS_ERR_EMPTY, ABS_ERR_NOMEM. */
+abs_status abs_plan(const abs_plan_desc* desc, abs_plan_t* out);
+
+/* Sizes and counts of a plan (host only). */
+abs_status abs_plan_info_get(abs_plan_t plan, abs_plan_info* out);
+
+/* Host copies of the triplet list, labels and ring radii; any pointer may be NULL.
+ *   ijk      int32  [ntrip][3]  ring indices i <= j <= k
+ *   labels   double [ntrip][5]  (ell1, ell2, ell3, mu, t) from the rings' mean radii,
+ *                               ell = 2 pi du <|g|>, mu = (l1^2 + l2^2 - l3^2) / (2 l1 l2),
+ *                               t = l2 / l1 (Sec. 2, below Eq. 3 and after Eq. 12)
+ *   radius   double [nbins]     unweighted mean |g| of each ring's lattice cells */
+abs_status abs_plan_triplets(abs_plan_t plan, int32_t* ijk, double* labels, double* radius);
+
+/* Compile the plan's contraction kernel for gfx950 (host only, no device needed).
+ * abs_plan_bind calls it when it has not been called.  Errors: ABS_ERR_JIT. */
+abs_status abs_plan_compile(abs_plan_t plan);
+
+/* Attach caller-owned device memory of at least plan_bytes bytes (256-byte aligned)
+ * to the plan, upload its tables on `stream` and load the compiled kernel on the
+ * current device.  The memory must outlive the plan's use.  Errors: ABS_ERR_INVALID,
+ * ABS_ERR_NOMEM (bytes too small), ABS_ERR_JIT, ABS_ERR_DEVICE. */
+abs_status abs_plan_bind(abs_plan_t plan, void* plan_mem, size_t bytes, void* stream);
+
+/* Device workspace needed by abs_estimate for `batch` grids, when the weights are
+ * per grid (w_batched = 1), shared (0), or replaced by cached counts (n_given != NULL,
+ * pass have_counts = 1). */
+abs_status abs_estimate_workspace(abs_plan_t plan, int32_t batch, int32_t w_batched,
+                                  int32_t have_counts, size_t* bytes);
+
+/* Device workspace needed by abs_grid for `batch` realisations. */
+abs_status abs_grid_workspace(abs_plan_t plan, int32_t batch, size_t* bytes);
+
+/* Gridding, Eq. (9): each visibility goes to the cell g = rint(U / du) (round half to
+ * even, FP64) and, because the sky is real (Eq. 4), its conjugate goes to -g.
+ * Visibilities with any |g| component >= n/2 are dropped and counted.
+ *   nvis     number of visibilities (baselines), >= 0
+ *   batch    realisations sharing the baselines, 1 <= batch <= max_batch
+ *   uv       device double [nvis][2]  (u, v) in wavelengths
+ *   vis      device float  [batch][nvis][2]  (re, im)
+ *   vis_w    device float  [nvis] per-visibility weights, or NULL for 1
+ *   kernel   ABS_NEAREST (w~ = 1 at the nearest cell) or ABS_GAUSS7
+ *            (w~ = exp(-pi^2 theta0^2 |U_g - U|^2) on the 7 x 7 cells around it)
+ *   work     device workspace of abs_grid_workspace bytes
+ *   grid     device float  [batch][n][n][2]  V_g, overwritten
+ *   wsum     device float  [n][n]  N_g = sum of w~ x vis_w, overwritten; may be NULL
+ *   dropped  device int64  [1]  number of dropped visibilities, overwritten; may be NULL
+ * Sums are accumulated in 64-bit fixed point, so results do not depend on the order
+ * of the atomic updates (bitwise reproducible).  Errors: ABS_ERR_INVALID,
+ * ABS_ERR_UNBOUND, ABS_ERR_NOMEM, ABS_ERR_DEVICE. */
+abs_status abs_grid(abs_plan_t plan, int64_t nvis, int32_t batch, const double* uv,
+                    const float* vis, const float* vis_w, int32_t kernel, void* work,
+                    size_t work_bytes, float* grid, float* wsum, int64_t* dropped,
+                    void* stream);
+
+/* The estimator, Eqs. (10)-(12), for `batch` gridded-visibility arrays.
+ *   batch      1 <= batch <= max_batch
+ *   dtype      ABS_C64 (float pairs) or ABS_C128 (double pairs, rounded to FP32 on load)
+ *   grids      device [batch][n][n] complex
+ *   w          device float [n][n] (w_batched = 0) or [batch][n][n] (w_batched = 1),
+ *              interpreted by the plan's wmode; may be NULL only for ABS_W_UNIT
+ *   n_given    device double [ntrip] weighted triangle counts N_t previously returned
+ *              for these same weights (abs_counts), or NULL; when given, the weight
+ *              fields are not recomputed (requires w_batched = 0)
+ *   work       device workspace of abs_estimate_workspace bytes
+ *   B          device double [batch][ntrip]  B_t = S_t / (A N_t), overwritten
+ *   N          device double [batch][ntrip]  N_t, overwritten; may be NULL
+ * Asynchronous on `stream`.  Errors: ABS_ERR_INVALID, ABS_ERR_UNBOUND, ABS_ERR_NOMEM,
+ * ABS_ERR_DEVICE. */
+abs_status abs_estimate(abs_plan_t plan, int32_t batch, int32_t dtype, const void* grids,
+                        const float* w, int32_t w_batched, const double* n_given,
+                        void* work, size_t work_bytes, double* B, double* N, void* stream);
+
+/* Weighted triangle counts N_t (the denominator of Eq. 12 per triangle) for one
+ * weight array, for reuse as abs_estimate's n_given.  work: abs_estimate_workspace
+ * (plan, 0, 0, 0) bytes.  N: device double [ntrip]. */
+abs_status abs_counts(abs_plan_t plan, const float* w, void* work, size_t work_bytes,
+                      double* N, void* stream);
+
+/* Timing hook: record the caller's HIP events (hipEvent_t passed as void*) on the
+ * call's stream immediately before and after the launches of one stage in every later
+ * abs_estimate / abs_counts / abs_grid call, until replaced (NULL clears a stage).
+ * Stages: ABS_STAGE_CONTRACT (triplet contraction), ABS_STAGE_COLPASS (column FFT
+ * pass), ABS_STAGE_ROWPASS (row FFT pass), ABS_STAGE_GRID (gridding scatter).
+ * The events must outlive those calls.  Errors: ABS_ERR_INVALID. */
+enum { ABS_STAGE_CONTRACT = 0, ABS_STAGE_COLPASS = 1, ABS_STAGE_ROWPASS = 2, ABS_STAGE_GRID = 3 };
+abs_status abs_profile(abs_plan_t plan, int32_t stage, void* ev_begin, void* ev_end);
+
+/* Wait for `stream` and report any device error seen so far. */
+abs_status abs_sync(abs_plan_t plan, void* stream);
+
+/* Free the plan's host state (never the caller's device memory). NULL is allowed. */
+abs_status abs_destroy(abs_plan_t plan);
+
+/* Static text for a status code. */
+const char* abs_status_str(abs_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ABS_H_ */

@@ -1,0 +1,100 @@
+// Internal state of an abs plan and the launch helpers shared by the HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/abs.h"
+
+namespace abs_impl {
+
+constexpr int kBlock = 256;          // threads per workgroup for every kernel here
+constexpr int kLdsComplex = 8192;    // complex FP32 values staged in LDS per FFT block (64 KiB)
+constexpr int kMaxBins = 64;
+constexpr int kMaxN = 8192;
+
+// One contiguous run of uv columns gx0 .. gx0 + ncols - 1 of ring m, transformed
+// together by one workgroup of the column pass.
+struct ColTile {
+  int32_t m, gx0, ncols, pad;
+};
+
+// Per-ring constants on the device.
+struct BinDev {
+  double lo2, hi2;    // squared edges, compared against the exact integer |g|^2
+  int32_t h;          // largest |gx| of any cell of the ring (columns 0..h are used)
+  int32_t cols;       // h + 1, or 0 for a ring without lattice cells
+  int64_t zoff;       // offset (complex elements) of the ring's column-pass output in one set
+};
+
+// Offsets (bytes) of the tables inside the caller's plan memory.
+struct DevLayout {
+  size_t tw, tw64, bins, tiles, tiles64, total;
+};
+
+// Offsets (bytes) of the buffers inside the abs_estimate workspace.
+struct WorkLayout {
+  int nsets;          // D sets (one per grid) followed by I sets
+  int nisets;
+  size_t zd, zi, fd, fi, part, total;
+  int64_t zset;       // complex elements per set of column-pass output
+  int64_t fset;       // values per set of fields (nbins * n * n)
+  int64_t partset;    // doubles per set of contraction partials (nblk * ntrip)
+};
+
+}  // namespace abs_impl
+
+struct abs_plan_s {
+  // descriptor
+  int n = 0, nb = 0, log2n = 0;
+  double du = 1.0, norm = 0.0, theta0 = 0.0;
+  int precision = 0, wmode = 0, max_batch = 1;
+  uint32_t flags = 0;
+  std::vector<double> edges, lo2, hi2;
+  // rings
+  std::vector<int> h, cols;
+  std::vector<int64_t> zoff;     // complex elements, per ring, within one set
+  int64_t ncols = 0;             // sum of cols
+  std::vector<double> radius;    // mean |g| per ring
+  // triplets, ascending (i, j, k)
+  std::vector<int32_t> trips;    // 3 * ntrip
+  std::vector<double> labels;    // 5 * ntrip
+  int64_t ntrip = 0, npairs = 0;
+  // FFT tiling
+  int ct = 0, ct64 = 0;          // columns per column-pass block (FP32 / FP64 passes)
+  int rb = 0, rb64 = 0;          // row pairs per row-pass block
+  std::vector<abs_impl::ColTile> tiles, tiles64;
+  // contraction kernel (compiled at run time for this triplet list)
+  int ngroups = 0;               // wave groups of the FP32 kernel; one wave per group
+  int ngroups64 = 0;             // wave groups of the FP64 kernel (weight fields)
+  int pix_per_block = 0;         // pixels per contraction workgroup
+  int nblk = 0;                  // contraction workgroups per set
+  std::string jit_src;
+  std::vector<char> jit_code;
+  bool compiled = false;
+  // device binding
+  abs_impl::DevLayout dl{};
+  void* dev = nullptr;
+  int device = -1;
+  hipModule_t module = nullptr;
+  hipFunction_t contract = nullptr;     // FP32 data fields
+  hipFunction_t contract64 = nullptr;   // FP64 weight fields
+  // timing hook: events recorded around one stage's launches (see abs_profile)
+  hipEvent_t prof[4][2] = {};
+};
+
+namespace abs_impl {
+// plan.cpp
+bool build_jit_source(abs_plan_s* p);
+abs_status compile_jit(abs_plan_s* p);
+WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_counts);
+inline void prof_begin(const abs_plan_s* p, int stage, hipStream_t st) {
+  if (p->prof[stage][0]) (void)hipEventRecord(p->prof[stage][0], st);
+}
+inline void prof_end(const abs_plan_s* p, int stage, hipStream_t st) {
+  if (p->prof[stage][1]) (void)hipEventRecord(p->prof[stage][1], st);
+}
+}  // namespace abs_impl

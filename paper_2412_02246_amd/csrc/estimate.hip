@@ -1,0 +1,234 @@
+// abs_plan_bind, abs_estimate, abs_counts and abs_sync: the estimator of Eq. (12) of
+// Gill et al. (2024) as a sequence of launches on the caller's stream:
+//   column pass -> row pass (ring fields D_m and I_m, Eqs. 10-11)
+//   -> triplet contraction (sum_theta of the triple products, per workgroup)
+//   -> finaliser (FP64 sum over workgroups, per-triangle normalisation, B = S / (A N)).
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+#include "abs_internal.h"
+
+namespace abs_impl {
+hipError_t launch_colpass_data(const abs_plan_s* p, const void* grids, int dtype, const float* w,
+                               int w_batched, int batch, float2* Z, long long zset, hipStream_t st);
+hipError_t launch_colpass_weight(const abs_plan_s* p, const float* w, int w_batched, int nsets,
+                                 double2* Z, long long zset, hipStream_t st);
+hipError_t launch_rowpass_f32(const abs_plan_s* p, int nsets, const float2* Z, long long zset,
+                              float* F, long long fset, hipStream_t st);
+hipError_t launch_rowpass_f64(const abs_plan_s* p, int nsets, const double2* Z, long long zset,
+                              double* F, long long fset, hipStream_t st);
+
+// B[b][t] = S / (A N), S and N the per-triangle sums: workgroup partials are added
+// in FP64 in a fixed order and divided by n^2 (the sum over pixels of a product of
+// three DFTs counts every closed triangle n^2 times).
+__global__ void __launch_bounds__(kBlock)
+finalize_kernel(const double* __restrict__ part, long long partset, int nblk, int ntrip,
+                int batch, int nisets, const double* __restrict__ n_given, double inv_npix,
+                double norm, double* __restrict__ B, double* __restrict__ N) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (t >= ntrip) return;
+  const double* ps = part + (long long)b * partset;
+  double s = 0.0;
+  for (int k = 0; k < nblk; ++k) s += ps[(long long)k * ntrip + t];
+  s *= inv_npix;
+  double nn;
+  if (nisets == 0) {
+    nn = n_given[t];
+  } else {
+    const int is = batch + (nisets > 1 ? b : 0);
+    const double* pn = part + (long long)is * partset;
+    nn = 0.0;
+    for (int k = 0; k < nblk; ++k) nn += pn[(long long)k * ntrip + t];
+    nn *= inv_npix;
+  }
+  B[(long long)b * ntrip + t] = s / (norm * nn);
+  if (N) N[(long long)b * ntrip + t] = nn;
+}
+
+// abs_counts: N_t alone from the weight-set partials.
+__global__ void __launch_bounds__(kBlock)
+counts_kernel(const double* __restrict__ part, int nblk, int ntrip, double inv_npix,
+              double* __restrict__ N) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntrip) return;
+  double nn = 0.0;
+  for (int k = 0; k < nblk; ++k) nn += part[(long long)k * ntrip + t];
+  N[t] = nn * inv_npix;
+}
+
+abs_status ensure_device(abs_plan_s* p) {
+  if (!p->dev) return ABS_ERR_UNBOUND;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return ABS_ERR_DEVICE;
+  if (cur != p->device) return ABS_ERR_INVALID;  // the plan is bound to another device
+  return ABS_OK;
+}
+
+abs_status launch_contract(hipFunction_t fn, int ngroups, const void* F, long long fset,
+                           long long npix, int ppb, int nblk, int ntrip, int nsets, double* part,
+                           hipStream_t st) {
+  void* Fp = const_cast<void*>(F);
+  void* args[] = {&Fp, &fset, &npix, &ppb, &part, &nblk, &ntrip};
+  const unsigned gz = (unsigned)((ngroups + 3) / 4);
+  return hipModuleLaunchKernel(fn, (unsigned)nblk, (unsigned)nsets, gz, kBlock, 1, 1, 0, st, args,
+                               nullptr) == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
+}
+
+// Data sets (FP32) for `batch` grids, then `nisets` weight sets (FP64); partials of
+// the data sets first, weight sets after them.
+abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batch, int dtype,
+                                   const void* grids, const float* w, int w_batched, char* work,
+                                   hipStream_t st) {
+  double* part = reinterpret_cast<double*>(work + wl.part);
+  const long long npix = (long long)p->n * p->n;
+  if (batch > 0) {
+    float2* Z = reinterpret_cast<float2*>(work + wl.zd);
+    float* F = reinterpret_cast<float*>(work + wl.fd);
+    prof_begin(p, ABS_STAGE_COLPASS, st);
+    if (launch_colpass_data(p, grids, dtype, w, w_batched, batch, Z, wl.zset, st) != hipSuccess)
+      return ABS_ERR_DEVICE;
+    prof_end(p, ABS_STAGE_COLPASS, st);
+    prof_begin(p, ABS_STAGE_ROWPASS, st);
+    if (launch_rowpass_f32(p, batch, Z, wl.zset, F, wl.fset, st) != hipSuccess)
+      return ABS_ERR_DEVICE;
+    prof_end(p, ABS_STAGE_ROWPASS, st);
+    prof_begin(p, ABS_STAGE_CONTRACT, st);
+    const abs_status s = launch_contract(p->contract, p->ngroups, F, wl.fset, npix,
+                                         p->pix_per_block, p->nblk, (int)p->ntrip, batch, part, st);
+    prof_end(p, ABS_STAGE_CONTRACT, st);
+    if (s != ABS_OK) return s;
+  }
+  if (wl.nisets > 0) {
+    double2* Z = reinterpret_cast<double2*>(work + wl.zi);
+    double* F = reinterpret_cast<double*>(work + wl.fi);
+    if (launch_colpass_weight(p, w, w_batched, wl.nisets, Z, wl.zset, st) != hipSuccess)
+      return ABS_ERR_DEVICE;
+    if (launch_rowpass_f64(p, wl.nisets, Z, wl.zset, F, wl.fset, st) != hipSuccess)
+      return ABS_ERR_DEVICE;
+    return launch_contract(p->contract64, p->ngroups64, F, wl.fset, npix, p->pix_per_block,
+                           p->nblk, (int)p->ntrip, wl.nisets, part + (long long)batch * wl.partset,
+                           st);
+  }
+  return ABS_OK;
+}
+
+}  // namespace abs_impl
+
+using namespace abs_impl;
+
+extern "C" {
+
+abs_status abs_plan_bind(abs_plan_t p, void* mem, size_t bytes, void* stream) {
+  if (!p || !mem) return ABS_ERR_INVALID;
+  if (reinterpret_cast<uintptr_t>(mem) & 255) return ABS_ERR_INVALID;
+  if (bytes < p->dl.total) return ABS_ERR_NOMEM;
+  abs_status s = compile_jit(p);
+  if (s != ABS_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return ABS_ERR_DEVICE;
+  if (p->module) {
+    (void)hipModuleUnload(p->module);
+    p->module = nullptr;
+    p->contract = nullptr;
+  }
+  if (hipModuleLoadData(&p->module, p->jit_code.data()) != hipSuccess) {
+    p->module = nullptr;
+    return ABS_ERR_JIT;
+  }
+  if (hipModuleGetFunction(&p->contract, p->module, "abs_contract") != hipSuccess ||
+      hipModuleGetFunction(&p->contract64, p->module, "abs_contract64") != hipSuccess)
+    return ABS_ERR_JIT;
+  // host image of the tables
+  std::vector<char> img(p->dl.total, 0);
+  float2* tw = reinterpret_cast<float2*>(img.data() + p->dl.tw);
+  double2* tw64 = reinterpret_cast<double2*>(img.data() + p->dl.tw64);
+  for (int k = 0; k < p->n; ++k) {
+    const double a = -2.0 * M_PI * (double)k / (double)p->n;  // forward DFT sign
+    tw64[k] = make_double2(std::cos(a), std::sin(a));
+    tw[k] = make_float2((float)tw64[k].x, (float)tw64[k].y);
+  }
+  BinDev* bins = reinterpret_cast<BinDev*>(img.data() + p->dl.bins);
+  for (int m = 0; m < p->nb; ++m) {
+    bins[m].lo2 = p->lo2[m];
+    bins[m].hi2 = p->hi2[m];
+    bins[m].h = p->h[m];
+    bins[m].cols = p->cols[m];
+    bins[m].zoff = p->zoff[m];
+  }
+  std::memcpy(img.data() + p->dl.tiles, p->tiles.data(), p->tiles.size() * sizeof(ColTile));
+  std::memcpy(img.data() + p->dl.tiles64, p->tiles64.data(), p->tiles64.size() * sizeof(ColTile));
+  if (hipMemcpyAsync(mem, img.data(), img.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+    return ABS_ERR_DEVICE;
+  // the host image is a local: wait for the copy before it goes out of scope
+  if (hipStreamSynchronize(st) != hipSuccess) return ABS_ERR_DEVICE;
+  p->dev = mem;
+  p->device = dev;
+  return ABS_OK;
+}
+
+abs_status abs_estimate(abs_plan_t p, int32_t batch, int32_t dtype, const void* grids,
+                        const float* w, int32_t w_batched, const double* n_given, void* work,
+                        size_t work_bytes, double* B, double* N, void* stream) {
+  if (!p) return ABS_ERR_INVALID;
+  abs_status s = ensure_device(p);
+  if (s != ABS_OK) return s;
+  if (batch < 1 || batch > p->max_batch) return ABS_ERR_INVALID;
+  if (dtype != ABS_C64 && dtype != ABS_C128) return ABS_ERR_INVALID;
+  if (!grids || !work || !B) return ABS_ERR_INVALID;
+  if (!w && p->wmode != ABS_W_UNIT) return ABS_ERR_INVALID;
+  if (n_given && w_batched) return ABS_ERR_INVALID;
+  if ((reinterpret_cast<uintptr_t>(grids) | reinterpret_cast<uintptr_t>(work)) & 15) return ABS_ERR_INVALID;
+  const WorkLayout wl = work_layout(p, batch, w_batched, n_given != nullptr);
+  if (work_bytes < wl.total) return ABS_ERR_NOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  char* wk = static_cast<char*>(work);
+  s = run_fields_and_contract(p, wl, batch, dtype, grids, w, w_batched, wk, st);
+  if (s != ABS_OK) return s;
+  const double* part = reinterpret_cast<const double*>(wk + wl.part);
+  const double inv = 1.0 / ((double)p->n * (double)p->n);
+  const dim3 g((unsigned)((p->ntrip + kBlock - 1) / kBlock), (unsigned)batch);
+  finalize_kernel<<<g, kBlock, 0, st>>>(part, wl.partset, p->nblk, (int)p->ntrip, batch,
+                                        wl.nisets, n_given, inv, p->norm, B, N);
+  return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
+}
+
+abs_status abs_counts(abs_plan_t p, const float* w, void* work, size_t work_bytes, double* N,
+                      void* stream) {
+  if (!p) return ABS_ERR_INVALID;
+  abs_status s = ensure_device(p);
+  if (s != ABS_OK) return s;
+  if (!work || !N || (!w && p->wmode != ABS_W_UNIT)) return ABS_ERR_INVALID;
+  if (reinterpret_cast<uintptr_t>(work) & 15) return ABS_ERR_INVALID;
+  const WorkLayout wl = work_layout(p, 0, 0, 0);
+  if (work_bytes < wl.total) return ABS_ERR_NOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  char* wk = static_cast<char*>(work);
+  // batch 0: the single set is the weight set
+  s = run_fields_and_contract(p, wl, 0, ABS_C64, nullptr, w, 0, wk, st);
+  if (s != ABS_OK) return s;
+  const double inv = 1.0 / ((double)p->n * (double)p->n);
+  counts_kernel<<<(unsigned)((p->ntrip + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+      reinterpret_cast<const double*>(wk + wl.part), p->nblk, (int)p->ntrip, inv, N);
+  return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
+}
+
+abs_status abs_profile(abs_plan_t p, int32_t stage, void* ev_begin, void* ev_end) {
+  if (!p || stage < 0 || stage > 3) return ABS_ERR_INVALID;
+  p->prof[stage][0] = static_cast<hipEvent_t>(ev_begin);
+  p->prof[stage][1] = static_cast<hipEvent_t>(ev_end);
+  return ABS_OK;
+}
+
+abs_status abs_sync(abs_plan_t p, void* stream) {
+  (void)p;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return ABS_ERR_DEVICE;
+  return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
+}
+
+}  // extern "C"

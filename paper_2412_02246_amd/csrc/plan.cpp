@@ -1,0 +1,564 @@
+// Host side of an abs plan: rings, the exact lattice test for ring triplets, labels,
+// FFT tiling, the run-time generated contraction kernel and workspace layouts.
+//
+// Rings and triplets follow Gill et al. (2024): Sec. 2 divides the uv plane into
+// annular rings a_m; Sec. 3 evaluates Eq. (12) for every combination of three rings,
+// each estimate averaging all closed triangles with one vertex per ring.
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <set>
+
+#include "abs_internal.h"
+
+using namespace abs_impl;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Ring membership: lo2 <= r2 < hi2 with r2 the exact integer |g|^2 (as a double,
+// exact below 2^53) and lo2, hi2 the FP64 squares of the edges.
+inline bool in_ring(long long r2, double lo2, double hi2) {
+  const double d = static_cast<double>(r2);
+  return d >= lo2 && d < hi2;
+}
+
+// For column offset x (any sign), the non-negative y with lo2 <= x^2 + y^2 < hi2
+// form the integer range [ya, yb] (empty when ya > yb).
+void y_range(long long x, double lo2, double hi2, long long& ya, long long& yb) {
+  const long long x2 = x * x;
+  const double t = hi2 - static_cast<double>(x2);
+  ya = 1;
+  yb = 0;
+  if (t <= 0.0) return;
+  long long y = static_cast<long long>(std::floor(std::sqrt(t)));
+  while (y >= 0 && !(static_cast<double>(x2 + y * y) < hi2)) --y;
+  while (static_cast<double>(x2 + (y + 1) * (y + 1)) < hi2) ++y;
+  if (y < 0) return;
+  const double u = lo2 - static_cast<double>(x2);
+  long long z = u <= 0.0 ? 0 : static_cast<long long>(std::ceil(std::sqrt(u)));
+  while (z > 0 && static_cast<double>(x2 + (z - 1) * (z - 1)) >= lo2) --z;
+  while (z <= y && static_cast<double>(x2 + z * z) < lo2) ++z;
+  ya = z;
+  yb = y;
+}
+
+struct RingRows {
+  long long H = -1;                 // largest |x| holding a cell
+  std::vector<long long> ya, yb;    // indexed by |x|, 0..H
+};
+
+RingRows ring_rows(double lo2, double hi2) {
+  RingRows r;
+  long long X = static_cast<long long>(std::floor(std::sqrt(std::max(hi2, 0.0)))) + 1;
+  r.ya.resize(X + 1);
+  r.yb.resize(X + 1);
+  for (long long x = 0; x <= X; ++x) {
+    y_range(x, lo2, hi2, r.ya[x], r.yb[x]);
+    if (r.ya[x] <= r.yb[x]) r.H = x;
+  }
+  r.ya.resize(r.H + 1);
+  r.yb.resize(r.H + 1);
+  return r;
+}
+
+inline bool intervals_meet(long long a0, long long a1, long long b0, long long b1) {
+  return std::max(a0, b0) <= std::min(a1, b1);
+}
+
+// Does the planar lattice hold g1 in ring i, g2 in ring j with g1 + g2 in ring k?
+// (Then g3 = -(g1 + g2) lies in ring k as well, the rings being symmetric.)
+// The configuration is invariant under the 8 symmetries of the square lattice, so g1
+// is restricted to 0 <= y1 <= x1; each candidate g2 column x2 is tested in O(1)
+// against the two annulus constraints written as intervals in y2.
+bool has_planar_triangle(const RingRows& Ri, const RingRows& Rj, const RingRows& Rk,
+                         double lok, double hij) {
+  if (Ri.H < 0 || Rj.H < 0 || Rk.H < 0) return false;
+  // |g1| must exceed lo_k - hi_j, since |g1 + g2| < |g1| + hi_j.
+  const double need = lok - hij;
+  const double need2 = need > 0 ? need * need : -1.0;
+  for (long long x1 = Ri.H; x1 >= 0; --x1) {
+    const long long ya = Ri.ya[x1], yb = std::min(Ri.yb[x1], x1);
+    for (long long y1 = yb; y1 >= ya; --y1) {
+      if (need2 > 0 && static_cast<double>(x1 * x1 + y1 * y1) <= need2) continue;
+      for (long long x2 = -Rj.H; x2 <= Rj.H; ++x2) {
+        const long long ax2 = x2 < 0 ? -x2 : x2;
+        const long long s = x1 + x2, as = s < 0 ? -s : s;
+        if (as > Rk.H) continue;
+        const long long ja = Rj.ya[ax2], jb = Rj.yb[ax2];
+        const long long ka = Rk.ya[as], kb = Rk.yb[as];
+        if (ja > jb || ka > kb) continue;
+        // y2 in [-jb, -ja] u [ja, jb]  and  y1 + y2 in [-kb, -ka] u [ka, kb]
+        const long long J[2][2] = {{-jb, -ja}, {ja, jb}};
+        const long long K[2][2] = {{-kb - y1, -ka - y1}, {ka - y1, kb - y1}};
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b)
+            if (intervals_meet(J[a][0], J[a][1], K[b][0], K[b][1])) return true;
+      }
+    }
+  }
+  return false;
+}
+
+// Cyclic closure (modulo n), by direct search; used only for ABS_ALLOW_WRAP plans.
+bool has_cyclic_triangle(int n, const std::vector<std::pair<int, int>>& ci,
+                         const std::vector<std::pair<int, int>>& cj, double lo2k, double hi2k) {
+  auto wrap = [n](long long v) {
+    long long r = ((v % n) + n) % n;
+    return r < n / 2 ? r : r - n;
+  };
+  for (auto& a : ci)
+    for (auto& b : cj) {
+      const long long x = wrap(-(long long)a.first - b.first);
+      const long long y = wrap(-(long long)a.second - b.second);
+      if (in_ring(x * x + y * y, lo2k, hi2k)) return true;
+    }
+  return false;
+}
+
+std::vector<std::pair<int, int>> cells_of(const RingRows& R) {
+  std::vector<std::pair<int, int>> c;
+  for (long long x = -R.H; x <= R.H; ++x) {
+    const long long ax = x < 0 ? -x : x;
+    for (long long y = R.ya[ax]; y <= R.yb[ax]; ++y) {
+      c.emplace_back((int)x, (int)y);
+      if (y != 0) c.emplace_back((int)x, (int)-y);
+    }
+  }
+  return c;
+}
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+}  // namespace
+
+namespace abs_impl {
+
+WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_counts) {
+  WorkLayout w{};
+  w.nisets = have_counts ? 0 : ((w_batched && p->wmode != ABS_W_UNIT) ? batch : 1);
+  w.nsets = batch + w.nisets;
+  const int64_t n = p->n;
+  w.zset = n * p->ncols;
+  w.fset = (int64_t)p->nb * n * n;
+  w.partset = (int64_t)p->nblk * p->ntrip;
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  size_t off = 0;
+  w.zd = off;
+  off = al(off + (size_t)batch * w.zset * 8);
+  w.zi = off;
+  off = al(off + (size_t)w.nisets * w.zset * 16);
+  w.fd = off;
+  off = al(off + (size_t)batch * w.fset * 4);
+  w.fi = off;
+  off = al(off + (size_t)w.nisets * w.fset * 8);
+  w.part = off;
+  off = al(off + (size_t)w.nsets * w.partset * 8);
+  w.total = off;
+  return w;
+}
+
+// The triplet contraction sum_theta F_i F_j F_k (Eq. 12: the numerator with the data
+// fields, the denominator with the weight fields) specialised to this plan's triplet
+// list: every wave owns a fixed group of triplets, holds one accumulator per triplet
+// in registers, and walks its workgroup's pixels with one pixel per lane; the field
+// values of a pixel are loaded once (coalesced across lanes, prefetched one
+// iteration ahead) and every pair product F_i F_j is formed once per pixel.
+// Accumulators are summed across the wave with lane shuffles and written in FP64
+// per workgroup; the finaliser adds workgroups in a fixed order.
+// Two kernels are emitted: abs_contract (FP32 fields, FP32 accumulators) and
+// abs_contract64 (FP64 fields and accumulators, for the weight fields).
+namespace {
+
+// Split ntrip triplets into G (a multiple of 4) contiguous groups whose register
+// estimate, rw * (slots + 2 * bins used), stays within the budget.
+std::vector<int> split_groups(const abs_plan_s* p, int rw) {
+  const int T = (int)p->ntrip;
+  const int kBudget = 212;
+  auto cost_ok = [&](int t0, int t1) {
+    std::set<int> bins;
+    for (int t = t0; t < t1; ++t)
+      for (int q = 0; q < 3; ++q) bins.insert(p->trips[3 * t + q]);
+    return rw * ((t1 - t0) + 2 * (int)bins.size()) <= kBudget;
+  };
+  for (int G = 4; G <= 16384; G += 4) {
+    std::vector<int> start(G + 1);
+    bool ok = true;
+    for (int g = 0; g <= G; ++g) start[g] = (int)((int64_t)T * g / G);
+    for (int g = 0; g < G && ok; ++g) ok = cost_ok(start[g], start[g + 1]);
+    if (ok) return start;
+  }
+  return {};
+}
+
+void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, const char* name,
+                 const char* R, std::string& s) {
+  char buf[1024];
+  const int G = (int)start.size() - 1;
+  std::snprintf(buf, sizeof buf,
+                "extern \"C\" __global__ void __launch_bounds__(256) %s(\n"
+                "    const %s* __restrict__ F, long long set_stride, long long npix, int ppb,\n"
+                "    double* __restrict__ part, int nblk, int ntrip) {\n", name, R);
+  s += buf;
+  std::snprintf(buf, sizeof buf,
+                "  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;\n"
+                "  const int grp = blockIdx.z * 4 + wave;\n"
+                "  const long long set = blockIdx.y;\n"
+                "  const %s* __restrict__ Fs = F + set * set_stride;\n"
+                "  const long long p0 = (long long)blockIdx.x * ppb;\n"
+                "  const long long p1 = (p0 + ppb < npix) ? p0 + ppb : npix;\n"
+                "  double* __restrict__ out = part + (set * nblk + blockIdx.x) * (long long)ntrip;\n"
+                "  switch (grp) {\n", R);
+  s += buf;
+  for (int g = 0; g < G; ++g) {
+    const int t0 = start[g], t1 = start[g + 1];
+    if (t1 <= t0) continue;
+    std::set<int> bins;
+    for (int t = t0; t < t1; ++t)
+      for (int q = 0; q < 3; ++q) bins.insert(p->trips[3 * t + q]);
+    std::snprintf(buf, sizeof buf, "  case %d: {\n", g);
+    s += buf;
+    for (int t = t0; t < t1; ++t) {
+      std::snprintf(buf, sizeof buf, "    %s a%d = 0;\n", R, t - t0);
+      s += buf;
+    }
+    for (int m : bins) {
+      std::snprintf(buf, sizeof buf,
+                    "    const %s* __restrict__ q%d = Fs + %dLL * npix;\n    %s n%d = 0;\n", R, m,
+                    m, R, m);
+      s += buf;
+    }
+    s += "    long long p = p0 + lane;\n    if (p < p1) {\n";
+    for (int m : bins) {
+      std::snprintf(buf, sizeof buf, "      n%d = q%d[p];\n", m, m);
+      s += buf;
+    }
+    s += "    }\n    for (; p < p1; p += 64) {\n";
+    for (int m : bins) {
+      std::snprintf(buf, sizeof buf, "      const %s d%d = n%d;\n", R, m, m);
+      s += buf;
+    }
+    s += "      const long long pn = p + 64;\n      if (pn < p1) {\n";
+    for (int m : bins) {
+      std::snprintf(buf, sizeof buf, "        n%d = q%d[pn];\n", m, m);
+      s += buf;
+    }
+    std::snprintf(buf, sizeof buf, "      }\n      %s t;\n", R);
+    s += buf;
+    int ci = -1, cj = -1;
+    for (int t = t0; t < t1; ++t) {
+      const int i = p->trips[3 * t], j = p->trips[3 * t + 1], k = p->trips[3 * t + 2];
+      if (i != ci || j != cj) {
+        std::snprintf(buf, sizeof buf, "      t = d%d * d%d;\n", i, j);
+        s += buf;
+        ci = i;
+        cj = j;
+      }
+      std::snprintf(buf, sizeof buf, "      a%d = abs_fma(t, d%d, a%d);\n", t - t0, k, t - t0);
+      s += buf;
+    }
+    s += "    }\n";
+    // reduce and store one accumulator at a time: keeps the register peak at the loop's
+    for (int t = t0; t < t1; ++t) {
+      std::snprintf(buf, sizeof buf,
+                    "    { const %s v = abs_wsum(a%d); if (lane == 0) out[%d] = (double)v; }\n", R,
+                    t - t0, t);
+      s += buf;
+    }
+    s += "  } break;\n";
+  }
+  s += "  default: break;\n  }\n}\n";
+}
+
+}  // namespace
+
+bool build_jit_source(abs_plan_s* p) {
+  const std::vector<int> g32 = split_groups(p, 1), g64 = split_groups(p, 2);
+  if (g32.empty() || g64.empty()) return false;
+  p->ngroups = (int)g32.size() - 1;
+  p->ngroups64 = (int)g64.size() - 1;
+  std::string s;
+  s.reserve(400000);
+  s += "// generated: triplet contraction for one ring-triplet list\n";
+  s += "__device__ __forceinline__ float abs_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }\n"
+       "__device__ __forceinline__ double abs_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }\n"
+       "template <typename T> __device__ __forceinline__ T abs_wsum(T v) {\n"
+       "  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);\n  return v;\n}\n";
+  emit_kernel(p, g32, "abs_contract", "float", s);
+  emit_kernel(p, g64, "abs_contract64", "double", s);
+  p->jit_src.swap(s);
+  return true;
+}
+
+abs_status compile_jit(abs_plan_s* p) {
+  if (p->compiled) return ABS_OK;
+  if (p->jit_src.empty() && !build_jit_source(p)) return ABS_ERR_JIT;
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, p->jit_src.c_str(), "abs_contract.hip", 0, nullptr, nullptr) !=
+      HIPRTC_SUCCESS)
+    return ABS_ERR_JIT;
+  // Packed FP32 instructions are disabled for every kernel of this library.
+  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature",
+                        "-Xclang", "-packed-fp32-ops"};
+  const hiprtcResult r = hiprtcCompileProgram(prog, 6, opts);
+  if (r != HIPRTC_SUCCESS) {
+    hiprtcDestroyProgram(&prog);
+    return ABS_ERR_JIT;
+  }
+  size_t sz = 0;
+  if (hiprtcGetCodeSize(prog, &sz) != HIPRTC_SUCCESS || sz == 0) {
+    hiprtcDestroyProgram(&prog);
+    return ABS_ERR_JIT;
+  }
+  p->jit_code.resize(sz);
+  const bool ok = hiprtcGetCode(prog, p->jit_code.data()) == HIPRTC_SUCCESS;
+  hiprtcDestroyProgram(&prog);
+  if (!ok) return ABS_ERR_JIT;
+  // ABS_JIT_DUMP=<directory>: keep the generated source and code object for inspection.
+  if (const char* dir = std::getenv("ABS_JIT_DUMP")) {
+    const std::string base = std::string(dir) + "/abs_contract_n" + std::to_string(p->n) + "_t" +
+                             std::to_string(p->ntrip);
+    if (FILE* f = std::fopen((base + ".hip").c_str(), "wb")) {
+      std::fwrite(p->jit_src.data(), 1, p->jit_src.size(), f);
+      std::fclose(f);
+    }
+    if (FILE* f = std::fopen((base + ".co").c_str(), "wb")) {
+      std::fwrite(p->jit_code.data(), 1, p->jit_code.size(), f);
+      std::fclose(f);
+    }
+  }
+  p->compiled = true;
+  return ABS_OK;
+}
+
+}  // namespace abs_impl
+
+extern "C" {
+
+const char* abs_status_str(abs_status s) {
+  switch (s) {
+    case ABS_OK: return "ok";
+    case ABS_ERR_INVALID: return "invalid argument";
+    case ABS_ERR_ALIAS: return "rings reach beyond n/3 (triangles would wrap); set ABS_ALLOW_WRAP";
+    case ABS_ERR_UNBOUND: return "plan is not bound to device memory";
+    case ABS_ERR_DEVICE: return "HIP runtime or kernel error";
+    case ABS_ERR_JIT: return "run-time compilation of the contraction kernel failed";
+    case ABS_ERR_NOMEM: return "out of host memory or caller buffer too small";
+    case ABS_ERR_EMPTY: return "no ring triplet contains a closed lattice triangle";
+  }
+  return "unknown status";
+}
+
+abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
+  if (!d || !out) return ABS_ERR_INVALID;
+  *out = nullptr;
+  const int n = d->n, nb = d->nbins;
+  if (n < 16 || n > kMaxN || (n & (n - 1))) return ABS_ERR_INVALID;
+  if (nb < 1 || nb > kMaxBins || !d->edges) return ABS_ERR_INVALID;
+  if (d->max_batch < 1 || d->max_batch > 65535) return ABS_ERR_INVALID;
+  if (d->wmode < ABS_W_UNIT || d->wmode > ABS_W_GIVEN) return ABS_ERR_INVALID;
+  if (d->precision != ABS_FP32) return ABS_ERR_INVALID;
+  if (!(d->du > 0.0) || !std::isfinite(d->du)) return ABS_ERR_INVALID;
+  for (int m = 0; m <= nb; ++m)
+    if (!std::isfinite(d->edges[m]) || d->edges[m] < 0.0) return ABS_ERR_INVALID;
+  for (int m = 0; m < nb; ++m)
+    if (!(d->edges[m + 1] > d->edges[m])) return ABS_ERR_INVALID;
+  if (d->edges[0] == 0.0 && !(d->flags & ABS_ALLOW_DC)) return ABS_ERR_INVALID;
+  if (d->edges[nb] > 0.5 * n) return ABS_ERR_ALIAS;
+  if (d->edges[nb] > n / 3.0 && !(d->flags & ABS_ALLOW_WRAP)) return ABS_ERR_ALIAS;
+
+  abs_plan_s* p = new (std::nothrow) abs_plan_s;
+  if (!p) return ABS_ERR_NOMEM;
+  p->n = n;
+  p->nb = nb;
+  p->log2n = ilog2(n);
+  p->du = d->du;
+  p->theta0 = d->theta0 > 0 ? d->theta0 : 0.6 * 24.68 * kPi / 180.0;
+  p->norm = d->norm > 0 ? d->norm : kPi * p->theta0 * p->theta0 / 3.0;
+  p->precision = d->precision;
+  p->wmode = d->wmode;
+  p->max_batch = d->max_batch;
+  p->flags = d->flags;
+  p->edges.assign(d->edges, d->edges + nb + 1);
+  for (int m = 0; m < nb; ++m) {
+    p->lo2.push_back(p->edges[m] * p->edges[m]);
+    p->hi2.push_back(p->edges[m + 1] * p->edges[m + 1]);
+  }
+
+  // rings: columns used by the FFT and mean radii for the labels
+  std::vector<RingRows> rows(nb);
+  p->h.resize(nb);
+  p->cols.resize(nb);
+  p->zoff.resize(nb);
+  p->radius.resize(nb);
+  int64_t acc = 0;
+  for (int m = 0; m < nb; ++m) {
+    rows[m] = ring_rows(p->lo2[m], p->hi2[m]);
+    p->h[m] = (int)rows[m].H;
+    p->cols[m] = rows[m].H >= 0 ? (int)rows[m].H + 1 : 0;
+    p->zoff[m] = acc * n;
+    acc += p->cols[m];
+    double sr = 0.0;
+    long long cnt = 0;
+    for (long long x = -rows[m].H; x <= rows[m].H; ++x) {
+      const long long ax = x < 0 ? -x : x;
+      for (long long y = rows[m].ya[ax]; y <= rows[m].yb[ax]; ++y) {
+        const double r = std::sqrt((double)(x * x + y * y));
+        sr += (y == 0) ? r : 2.0 * r;
+        cnt += (y == 0) ? 1 : 2;
+      }
+    }
+    p->radius[m] = cnt ? sr / (double)cnt : std::nan("");
+  }
+  p->ncols = acc;
+
+  // triplets i <= j <= k with at least one closed lattice triangle
+  const bool wrap = (p->flags & ABS_ALLOW_WRAP) && p->edges[nb] > n / 3.0;
+  std::vector<std::vector<std::pair<int, int>>> cells;
+  if (wrap) {
+    cells.resize(nb);
+    for (int m = 0; m < nb; ++m) cells[m] = cells_of(rows[m]);
+  }
+  for (int i = 0; i < nb; ++i)
+    for (int j = i; j < nb; ++j)
+      for (int k = j; k < nb; ++k) {
+        bool ok;
+        if (wrap) {
+          ok = has_cyclic_triangle(n, cells[i], cells[j], p->lo2[k], p->hi2[k]);
+        } else {
+          if (!(p->edges[k] < p->edges[i + 1] + p->edges[j + 1])) continue;  // triangle inequality
+          ok = has_planar_triangle(rows[i], rows[j], rows[k], p->edges[k], p->edges[j + 1]);
+        }
+        if (!ok) continue;
+        p->trips.push_back(i);
+        p->trips.push_back(j);
+        p->trips.push_back(k);
+      }
+  p->ntrip = (int64_t)p->trips.size() / 3;
+  if (p->ntrip == 0) {
+    delete p;
+    return ABS_ERR_EMPTY;
+  }
+  {
+    std::set<std::pair<int, int>> pairs;
+    for (int64_t t = 0; t < p->ntrip; ++t) pairs.insert({p->trips[3 * t], p->trips[3 * t + 1]});
+    p->npairs = (int64_t)pairs.size();
+  }
+  p->labels.resize(5 * p->ntrip);
+  for (int64_t t = 0; t < p->ntrip; ++t) {
+    const double l3 = 2 * kPi * p->du * p->radius[p->trips[3 * t]];
+    const double l2 = 2 * kPi * p->du * p->radius[p->trips[3 * t + 1]];
+    const double l1 = 2 * kPi * p->du * p->radius[p->trips[3 * t + 2]];
+    double* L = &p->labels[5 * t];
+    L[0] = l1;
+    L[1] = l2;
+    L[2] = l3;
+    L[3] = (l1 * l1 + l2 * l2 - l3 * l3) / (2.0 * l1 * l2);
+    L[4] = l2 / l1;
+  }
+
+  // FFT tiling: a block stages 64 KiB of complex values in LDS (FP32: kLdsComplex,
+  // FP64: half as many), and at least one whole sequence
+  p->ct = std::max(1, std::min(32, kLdsComplex / n));
+  p->rb = std::max(1, kLdsComplex / n);
+  p->ct64 = std::max(1, std::min(32, kLdsComplex / 2 / n));
+  p->rb64 = std::max(1, kLdsComplex / 2 / n);
+  for (int m = 0; m < nb; ++m) {
+    for (int g0 = 0; g0 < p->cols[m]; g0 += p->ct)
+      p->tiles.push_back({m, g0, std::min(p->ct, p->cols[m] - g0), 0});
+    for (int g0 = 0; g0 < p->cols[m]; g0 += p->ct64)
+      p->tiles64.push_back({m, g0, std::min(p->ct64, p->cols[m] - g0), 0});
+  }
+  const int64_t npix = (int64_t)n * n;
+  p->pix_per_block = (int)std::min<int64_t>(16384, std::max<int64_t>(1024, npix / 64));
+  p->nblk = (int)((npix + p->pix_per_block - 1) / p->pix_per_block);
+
+  // device layout of the plan tables
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  size_t off = 0;
+  p->dl.tw = off;
+  off = al(off + (size_t)n * 8);
+  p->dl.tw64 = off;
+  off = al(off + (size_t)n * 16);
+  p->dl.bins = off;
+  off = al(off + (size_t)nb * sizeof(BinDev));
+  p->dl.tiles = off;
+  off = al(off + p->tiles.size() * sizeof(ColTile));
+  p->dl.tiles64 = off;
+  off = al(off + p->tiles64.size() * sizeof(ColTile));
+  p->dl.total = off;
+
+  if (!build_jit_source(p)) {
+    delete p;
+    return ABS_ERR_JIT;
+  }
+  *out = p;
+  return ABS_OK;
+}
+
+abs_status abs_plan_info_get(abs_plan_t p, abs_plan_info* o) {
+  if (!p || !o) return ABS_ERR_INVALID;
+  o->n = p->n;
+  o->nbins = p->nb;
+  o->ntrip = p->ntrip;
+  o->npairs = p->npairs;
+  o->ncols = p->ncols;
+  o->plan_bytes = (int64_t)p->dl.total;
+  o->norm = p->norm;
+  return ABS_OK;
+}
+
+abs_status abs_plan_triplets(abs_plan_t p, int32_t* ijk, double* labels, double* radius) {
+  if (!p) return ABS_ERR_INVALID;
+  if (ijk) std::memcpy(ijk, p->trips.data(), p->trips.size() * sizeof(int32_t));
+  if (labels) std::memcpy(labels, p->labels.data(), p->labels.size() * sizeof(double));
+  if (radius) std::memcpy(radius, p->radius.data(), p->radius.size() * sizeof(double));
+  return ABS_OK;
+}
+
+abs_status abs_plan_compile(abs_plan_t p) {
+  if (!p) return ABS_ERR_INVALID;
+  return compile_jit(p);
+}
+
+abs_status abs_estimate_workspace(abs_plan_t p, int32_t batch, int32_t w_batched,
+                                  int32_t have_counts, size_t* bytes) {
+  if (!p || !bytes || batch < 0 || batch > p->max_batch) return ABS_ERR_INVALID;
+  *bytes = work_layout(p, batch, w_batched, have_counts).total;
+  return ABS_OK;
+}
+
+abs_status abs_grid_workspace(abs_plan_t p, int32_t batch, size_t* bytes) {
+  if (!p || !bytes || batch < 1 || batch > p->max_batch) return ABS_ERR_INVALID;
+  const size_t cells = (size_t)p->n * p->n;
+  *bytes = 256 + (size_t)(2 * batch + 1) * cells * 8;
+  return ABS_OK;
+}
+
+abs_status abs_destroy(abs_plan_t p) {
+  if (!p) return ABS_OK;
+  if (p->module) {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && p->device >= 0 && cur != p->device) {
+      (void)hipSetDevice(p->device);
+      (void)hipModuleUnload(p->module);
+      (void)hipSetDevice(cur);
+    } else {
+      (void)hipModuleUnload(p->module);
+    }
+  }
+  delete p;
+  return ABS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+"""Python face of the C ABI: a Plan owns an abs plan handle, its device tables (a
+torch uint8 tensor) and a reusable workspace.  Methods only check and marshal
+arguments; the work is done by libabs.so on the caller's current torch stream."""
+import ctypes
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Plan:
+    """A bispectrum plan for one grid size and ring set.
+
+    n, edges    grid side and ring edges in grid cells (Sec. 2 rings)
+    du          uv grid spacing in wavelengths (labels, gridding)
+    norm        the A of Eq. (12); 0 selects pi theta0^2 / 3
+    wmode       W_UNIT, W_INV_COUNT or W_GIVEN
+    max_batch   largest batch of grids per call
+    flags       ALLOW_WRAP | ALLOW_DC
+    """
+
+    def __init__(self, n, edges, du=1.0, norm=0.0, theta0=0.0, precision=L.FP32,
+                 wmode=L.W_UNIT, max_batch=1, flags=0):
+        lib = L.lib()
+        e = np.ascontiguousarray(edges, dtype=np.float64)
+        self._edges = e
+        d = L.PlanDesc(n=int(n), nbins=len(e) - 1,
+                       edges=e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                       du=float(du), norm=float(norm), theta0=float(theta0),
+                       precision=int(precision), wmode=int(wmode), max_batch=int(max_batch),
+                       flags=int(flags))
+        h = ctypes.c_void_p()
+        L.check(lib.abs_plan(ctypes.byref(d), ctypes.byref(h)), "abs_plan")
+        self.handle = h
+        info = L.PlanInfo()
+        L.check(lib.abs_plan_info_get(h, ctypes.byref(info)), "abs_plan_info_get")
+        self.n, self.nbins = info.n, info.nbins
+        self.ntrip, self.npairs, self.ncols = info.ntrip, info.npairs, info.ncols
+        self.plan_bytes, self.norm = info.plan_bytes, info.norm
+        self.wmode, self.max_batch = int(wmode), int(max_batch)
+        ijk = np.zeros((self.ntrip, 3), np.int32)
+        lab = np.zeros((self.ntrip, 5), np.float64)
+        rad = np.zeros(self.nbins, np.float64)
+        L.check(lib.abs_plan_triplets(h, ijk.ctypes.data_as(ctypes.c_void_p),
+                                      lab.ctypes.data_as(ctypes.c_void_p),
+                                      rad.ctypes.data_as(ctypes.c_void_p)), "abs_plan_triplets")
+        self.triplets, self.labels, self.radius = ijk, lab, rad
+        self._mem = None
+        self._work = None
+
+    # -- lifetime -------------------------------------------------------------
+    def compile(self):
+        L.check(L.lib().abs_plan_compile(self.handle), "abs_plan_compile")
+        return self
+
+    def bind(self, device=None, stream=None):
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        with torch.cuda.device(dev):
+            self._mem = torch.empty(self.plan_bytes + 256, dtype=torch.uint8, device=dev)
+            off = (-self._mem.data_ptr()) % 256
+            ptr = ctypes.c_void_p(self._mem.data_ptr() + off)
+            L.check(L.lib().abs_plan_bind(self.handle, ptr, self.plan_bytes, _stream(stream)),
+                    "abs_plan_bind")
+        self.device = dev
+        return self
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            L.lib().abs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- workspaces -------------------------------------------------------------
+    def estimate_workspace(self, batch, w_batched=False, have_counts=False):
+        b = ctypes.c_size_t()
+        L.check(L.lib().abs_estimate_workspace(self.handle, int(batch), int(bool(w_batched)),
+                                               int(bool(have_counts)), ctypes.byref(b)),
+                "abs_estimate_workspace")
+        return b.value
+
+    def grid_workspace(self, batch):
+        b = ctypes.c_size_t()
+        L.check(L.lib().abs_grid_workspace(self.handle, int(batch), ctypes.byref(b)), "abs_grid_workspace")
+        return b.value
+
+    def _workspace(self, nbytes):
+        import torch
+        if self._work is None or self._work.numel() < nbytes:
+            self._work = None
+            self._work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self._work
+
+    # -- calls ----------------------------------------------------------------
+    def estimate(self, grids, w=None, w_batched=False, n_given=None, out=None, stream=None):
+        """B (and N) for a batch of gridded visibilities.
+
+        grids: torch complex64 / complex128 [batch][n][n] (or [n][n]) on the plan's device
+        w:     torch float32 [n][n] or [batch][n][n] (w_batched), per the plan's wmode
+        n_given: torch float64 [ntrip] counts from counts() for the same shared weights
+        Returns (B, N), torch float64 [batch][ntrip].
+        """
+        import torch
+        if grids.dim() == 2:
+            grids = grids.unsqueeze(0)
+        if grids.dtype == torch.complex64:
+            dtype = L.C64
+        elif grids.dtype == torch.complex128:
+            dtype = L.C128
+        else:
+            raise TypeError("grids must be complex64 or complex128")
+        if not grids.is_contiguous():
+            raise ValueError("grids must be contiguous")
+        batch = grids.shape[0]
+        if tuple(grids.shape[1:]) != (self.n, self.n):
+            raise ValueError("grids must be [batch][%d][%d]" % (self.n, self.n))
+        if w is not None:
+            if w.dtype != torch.float32 or not w.is_contiguous():
+                raise TypeError("w must be a contiguous float32 tensor")
+            want = (batch, self.n, self.n) if w_batched else (self.n, self.n)
+            if tuple(w.shape) != want:
+                raise ValueError("w must have shape %s" % (want,))
+        if n_given is not None and (n_given.dtype != torch.float64 or n_given.numel() != self.ntrip):
+            raise ValueError("n_given must be float64 [ntrip]")
+        nbytes = self.estimate_workspace(batch, w_batched, n_given is not None)
+        work = self._workspace(nbytes)
+        if out is None:
+            B = torch.empty((batch, self.ntrip), dtype=torch.float64, device=grids.device)
+            N = torch.empty((batch, self.ntrip), dtype=torch.float64, device=grids.device)
+        else:
+            B, N = out
+        L.check(L.lib().abs_estimate(self.handle, batch, dtype, _ptr(grids), _ptr(w),
+                                     int(bool(w_batched)), _ptr(n_given), _ptr(work),
+                                     work.numel(), _ptr(B), _ptr(N), _stream(stream)),
+                "abs_estimate")
+        return B, N
+
+    def counts(self, w=None, stream=None):
+        import torch
+        work = self._workspace(self.estimate_workspace(0))
+        N = torch.empty(self.ntrip, dtype=torch.float64, device=self.device)
+        L.check(L.lib().abs_counts(self.handle, _ptr(w), _ptr(work), work.numel(), _ptr(N),
+                                   _stream(stream)), "abs_counts")
+        return N
+
+    def grid(self, uv, vis, vis_w=None, kernel=L.NEAREST, stream=None):
+        """Grid visibilities (Eq. 9).  uv: float64 [nvis][2] (wavelengths);
+        vis: complex64 [batch][nvis] or [nvis].  Returns (grid complex64 [batch][n][n],
+        wsum float32 [n][n], dropped int64 [1])."""
+        import torch
+        if vis.dim() == 1:
+            vis = vis.unsqueeze(0)
+        if uv.dtype != torch.float64 or vis.dtype != torch.complex64:
+            raise TypeError("uv must be float64 and vis complex64")
+        nvis = uv.shape[0]
+        if vis.shape[1] != nvis or not (uv.is_contiguous() and vis.is_contiguous()):
+            raise ValueError("vis must be contiguous [batch][nvis] matching uv [nvis][2]")
+        batch = vis.shape[0]
+        work = self._workspace(self.grid_workspace(batch))
+        grid = torch.empty((batch, self.n, self.n), dtype=torch.complex64, device=uv.device)
+        wsum = torch.empty((self.n, self.n), dtype=torch.float32, device=uv.device)
+        dropped = torch.empty(1, dtype=torch.int64, device=uv.device)
+        L.check(L.lib().abs_grid(self.handle, nvis, batch, _ptr(uv), _ptr(vis), _ptr(vis_w),
+                                 int(kernel), _ptr(work), work.numel(), _ptr(grid), _ptr(wsum),
+                                 _ptr(dropped), _stream(stream)), "abs_grid")
+        return grid, wsum, dropped
+
+    def sync(self, stream=None):
+        L.check(L.lib().abs_sync(self.handle, _stream(stream)), "abs_sync")

@@ -124,3 +124,26 @@ def visibility_stream(nvis, rmax, U0, du, seed, batch=1):
     uv = np.stack([r * np.cos(phi), r * np.sin(phi)], axis=1) * du
     vis = (rng.standard_normal((batch, nvis)) + 1j * rng.standard_normal((batch, nvis))).astype(np.complex64)
     return uv, vis
+
+
+def mwa_visibilities(n, nvis, rmax, seed, batch=1, du=1.0, f_ng=0.17, U0=None, snr=5.0):
+    """Visibilities of an MWA-shaped channel on one shared baseline set: ``batch``
+    independent sky realisations (the paper's C_l, local quadratic with f = f_NG/sigma_T)
+    sampled at the cell nearest to each baseline, plus thermal noise per visibility
+    at amplitude SNR ``snr``.  Baselines: density proportional to exp(-|U|/U0) inside
+    |U| < rmax, U0 = n/8 by default.  Returns (uv float64 [nvis][2], vis complex64
+    [batch][nvis])."""
+    U0 = n / 8.0 if U0 is None else U0
+    uv, _ = visibility_stream(nvis, rmax, U0, du, seed, batch=1)
+    rng = np.random.default_rng(seed + 7919)
+    C = paper_spectrum(n, du)
+    sigma = np.sqrt(field_variance(C))
+    gx = np.rint(uv[:, 0] / du).astype(np.int64) % n
+    gy = np.rint(uv[:, 1] / du).astype(np.int64) % n
+    amp = np.sqrt(n ** 2 * C[gy, gx]) / snr
+    vis = np.empty((batch, nvis), np.complex64)
+    for b in range(batch):
+        S = nongaussian_grid(C, f_ng / sigma, rng)
+        noise = (rng.standard_normal(nvis) + 1j * rng.standard_normal(nvis)) * (amp / np.sqrt(2.0))
+        vis[b] = (S[gy, gx] + noise).astype(np.complex64)
+    return uv, vis

@@ -1,0 +1,111 @@
+"""Host-side checks of libabs.so that need no GPU: exported symbols, the plan's
+triplet list and labels against the oracle, error codes, and run-time compilation
+of the contraction kernel (hiprtc needs no device)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import plan as oplan
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "abs.h")
+
+
+def _A():
+    import paper_2412_02246_amd as A
+    return A
+
+
+def test_library_exports_every_declared_symbol():
+    A = _A()
+    text = open(HDR).read()
+    decl = set(re.findall(r"^\s*(?:abs_status|const char\*)\s+(abs_\w+)\s*\(", text, re.M))
+    assert {"abs_plan", "abs_grid", "abs_estimate", "abs_destroy", "abs_status_str"} <= decl
+    L = ctypes.CDLL(A._lib.LIB_PATH)
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+CASES = {
+    "c1_128_8log": (128, oplan.log_edges(2.0, 42.0, 8)),
+    "c2_1024_20log": (1024, oplan.log_edges(46 / (2 * np.pi), 1320 / (2 * np.pi), 20)),
+    "paper_22_rings": (1024, oplan.paper_ring_edges()),
+    "small_odd": (32, [1.2, 2.0, 3.3, 5.1, 7.0, 10.5]),
+    "thin_rings": (64, [1.0, 1.1, 2.3, 2.9, 3.0, 6.2, 9.9, 13.0, 21.0]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_plan_triplets_match_oracle(name):
+    A = _A()
+    n, e = CASES[name]
+    p = A.Plan(n, e)
+    trips, _ = oplan.plan_triplets(n, e)
+    assert p.ntrip == len(trips)
+    assert np.array_equal(p.triplets, trips)
+    assert np.allclose(p.radius, oplan.mean_radius(n, e), equal_nan=True)
+    assert np.allclose(p.labels, oplan.labels(n, e, trips, 1.0), rtol=1e-12, equal_nan=True)
+    assert p.npairs == len({(int(a), int(b)) for a, b, _ in trips})
+
+
+def test_wrap_plan_matches_cyclic_oracle():
+    A = _A()
+    n, e = 32, [1.5, 4.0, 7.0, 11.5, 15.0]
+    with pytest.raises(A.AbsError) as ei:
+        A.Plan(n, e)
+    assert ei.value.status == 2          # ABS_ERR_ALIAS
+    p = A.Plan(n, e, flags=A.ALLOW_WRAP)
+    trips, _ = oplan.plan_triplets(n, e)  # the oracle's FFT counts close triangles mod n
+    assert np.array_equal(p.triplets, trips)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=100, edges=[1, 2, 3]), 1),          # not a power of two
+    (dict(n=32, edges=[2, 2, 3]), 1),           # edges not increasing
+    (dict(n=32, edges=[0, 2, 3]), 1),           # DC ring without ALLOW_DC
+    (dict(n=32, edges=[1, 2, 11]), 2),          # beyond n/3
+    (dict(n=32, edges=[1, 2, 17], flags=1), 2),  # beyond n/2 even with ALLOW_WRAP
+    (dict(n=32, edges=[1.1, 1.2]), 7),          # a ring without lattice cells
+    (dict(n=32, edges=[1, 2, 3], max_batch=0), 1),
+    (dict(n=32, edges=[1, 2, 3], wmode=7), 1),
+])
+def test_plan_errors(kw, status):
+    A = _A()
+    with pytest.raises(A.AbsError) as ei:
+        A.Plan(**kw)
+    assert ei.value.status == status
+
+
+def test_dc_ring_allowed_with_flag():
+    A = _A()
+    p = A.Plan(16, [0.0, 0.5, 2.0, 3.5, 5.0], flags=A.ALLOW_DC)
+    trips, _ = oplan.plan_triplets(16, [0.0, 0.5, 2.0, 3.5, 5.0])
+    assert np.array_equal(p.triplets, trips)
+
+
+def test_runtime_compilation_without_device():
+    A = _A()
+    p = A.Plan(128, oplan.log_edges(2.0, 42.0, 8))
+    p.compile()   # hiprtc for gfx950 on the host
+
+
+def test_workspace_sizes():
+    A = _A()
+    n, e = CASES["c2_1024_20log"]
+    p = A.Plan(n, e, max_batch=4, wmode=A.W_INV_COUNT)
+    shared = p.estimate_workspace(4, False)
+    per = p.estimate_workspace(4, True)
+    cached = p.estimate_workspace(4, False, True)
+    assert cached < shared < per
+    # fields dominate: nbins n^2 values per set, FP32 for the 4 data sets and FP64 for
+    # the weight sets (one shared, or one per grid)
+    f = 20 * n * n * 4
+    assert 6 * f < shared < 6 * f * 1.2
+    assert 12 * f < per < 12 * f * 1.2
+    assert 4 * f < cached < 4 * f * 1.2
+    assert p.grid_workspace(2) == 256 + 5 * n * n * 8
+    with pytest.raises(A.AbsError):
+        p.estimate_workspace(5)
