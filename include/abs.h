@@ -127,8 +127,9 @@ abs_status abs_plan_bind(abs_plan_t plan, void* plan_mem, size_t bytes, void* st
 abs_status abs_estimate_workspace(abs_plan_t plan, int32_t batch, int32_t w_batched,
                                   int32_t have_counts, size_t* bytes);
 
-/* Device workspace needed by abs_grid for `batch` realisations. */
-abs_status abs_grid_workspace(abs_plan_t plan, int32_t batch, size_t* bytes);
+/* Device workspace needed by abs_grid for `nvis` baselines and `batch` realisations
+ * (nvis < 2^31). */
+abs_status abs_grid_workspace(abs_plan_t plan, int64_t nvis, int32_t batch, size_t* bytes);
 
 /* Gridding, Eq. (9): each visibility goes to the cell g = rint(U / du) (round half to
  * even, FP64) and, because the sky is real (Eq. 4), its conjugate goes to -g.
@@ -144,8 +145,8 @@ abs_status abs_grid_workspace(abs_plan_t plan, int32_t batch, size_t* bytes);
  *   grid     device float  [batch][n][n][2]  V_g, overwritten
  *   wsum     device float  [n][n]  N_g = sum of w~ x vis_w, overwritten; may be NULL
  *   dropped  device int64  [1]  number of dropped visibilities, overwritten; may be NULL
- * Sums are accumulated in 64-bit fixed point, so results do not depend on the order
- * of the atomic updates (bitwise reproducible).  Errors: ABS_ERR_INVALID,
+ * The visibilities are sorted by nearest cell and every cell gathers its own sum in
+ * 64-bit fixed point, so results are bitwise reproducible.  Errors: ABS_ERR_INVALID,
  * ABS_ERR_UNBOUND, ABS_ERR_NOMEM, ABS_ERR_DEVICE. */
 abs_status abs_grid(abs_plan_t plan, int64_t nvis, int32_t batch, const double* uv,
                     const float* vis, const float* vis_w, int32_t kernel, void* work,

@@ -58,7 +58,7 @@ def lib():
         "abs_plan_compile": [_P],
         "abs_plan_bind": [_P, _P, sz, _P],
         "abs_estimate_workspace": [_P, i32, i32, i32, ctypes.POINTER(sz)],
-        "abs_grid_workspace": [_P, i32, ctypes.POINTER(sz)],
+        "abs_grid_workspace": [_P, i64, i32, ctypes.POINTER(sz)],
         "abs_grid": [_P, i64, i32, _P, _P, _P, i32, _P, sz, _P, _P, _P, _P],
         "abs_estimate": [_P, i32, i32, _P, _P, i32, _P, _P, sz, _P, _P, _P],
         "abs_counts": [_P, _P, _P, sz, _P, _P],

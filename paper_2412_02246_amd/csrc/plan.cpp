@@ -538,13 +538,6 @@ abs_status abs_estimate_workspace(abs_plan_t p, int32_t batch, int32_t w_batched
   return ABS_OK;
 }
 
-abs_status abs_grid_workspace(abs_plan_t p, int32_t batch, size_t* bytes) {
-  if (!p || !bytes || batch < 1 || batch > p->max_batch) return ABS_ERR_INVALID;
-  const size_t cells = (size_t)p->n * p->n;
-  *bytes = 256 + (size_t)(2 * batch + 1) * cells * 8;
-  return ABS_OK;
-}
-
 abs_status abs_destroy(abs_plan_t p) {
   if (!p) return ABS_OK;
   if (p->module) {

@@ -94,9 +94,10 @@ class Plan:
                 "abs_estimate_workspace")
         return b.value
 
-    def grid_workspace(self, batch):
+    def grid_workspace(self, nvis, batch):
         b = ctypes.c_size_t()
-        L.check(L.lib().abs_grid_workspace(self.handle, int(batch), ctypes.byref(b)), "abs_grid_workspace")
+        L.check(L.lib().abs_grid_workspace(self.handle, int(nvis), int(batch), ctypes.byref(b)),
+                "abs_grid_workspace")
         return b.value
 
     def _workspace(self, nbytes):
@@ -171,7 +172,7 @@ class Plan:
         if vis.shape[1] != nvis or not (uv.is_contiguous() and vis.is_contiguous()):
             raise ValueError("vis must be contiguous [batch][nvis] matching uv [nvis][2]")
         batch = vis.shape[0]
-        work = self._workspace(self.grid_workspace(batch))
+        work = self._workspace(self.grid_workspace(nvis, batch))
         grid = torch.empty((batch, self.n, self.n), dtype=torch.complex64, device=uv.device)
         wsum = torch.empty((self.n, self.n), dtype=torch.float32, device=uv.device)
         dropped = torch.empty(1, dtype=torch.int64, device=uv.device)
