@@ -12,7 +12,6 @@
 namespace abs_impl {
 
 constexpr int kBlock = 256;          // threads per workgroup for every kernel here
-constexpr int kLdsComplex = 8192;    // complex FP32 values staged in LDS per FFT block (64 KiB)
 constexpr int kMaxBins = 64;
 constexpr int kMaxN = 8192;
 
@@ -32,7 +31,7 @@ struct BinDev {
 
 // Offsets (bytes) of the tables inside the caller's plan memory.
 struct DevLayout {
-  size_t tw, tw64, bins, tiles, tiles64, total;
+  size_t tw, tw64, bins, tiles, total;
 };
 
 // Offsets (bytes) of the buffers inside the abs_estimate workspace.
@@ -64,9 +63,8 @@ struct abs_plan_s {
   std::vector<double> labels;    // 5 * ntrip
   int64_t ntrip = 0, npairs = 0;
   // FFT tiling
-  int ct = 0, ct64 = 0;          // columns per column-pass block (FP32 / FP64 passes)
-  int rb = 0, rb64 = 0;          // row pairs per row-pass block
-  std::vector<abs_impl::ColTile> tiles, tiles64;
+  int ct = 0;                    // columns per column-pass block
+  std::vector<abs_impl::ColTile> tiles;
   // contraction kernel (compiled at run time for this triplet list)
   int ngroups = 0;               // wave groups of the FP32 kernel; one wave per group
   int ngroups64 = 0;             // wave groups of the FP64 kernel (weight fields)

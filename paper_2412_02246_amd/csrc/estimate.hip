@@ -160,7 +160,6 @@ abs_status abs_plan_bind(abs_plan_t p, void* mem, size_t bytes, void* stream) {
     bins[m].zoff = p->zoff[m];
   }
   std::memcpy(img.data() + p->dl.tiles, p->tiles.data(), p->tiles.size() * sizeof(ColTile));
-  std::memcpy(img.data() + p->dl.tiles64, p->tiles64.data(), p->tiles64.size() * sizeof(ColTile));
   if (hipMemcpyAsync(mem, img.data(), img.size(), hipMemcpyHostToDevice, st) != hipSuccess)
     return ABS_ERR_DEVICE;
   // the host image is a local: wait for the copy before it goes out of scope

@@ -467,18 +467,12 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
     L[4] = l2 / l1;
   }
 
-  // FFT tiling: a block stages 64 KiB of complex values in LDS (FP32: kLdsComplex,
-  // FP64: half as many), and at least one whole sequence
-  p->ct = std::max(1, std::min(32, kLdsComplex / n));
-  p->rb = std::max(1, kLdsComplex / n);
-  p->ct64 = std::max(1, std::min(32, kLdsComplex / 2 / n));
-  p->rb64 = std::max(1, kLdsComplex / 2 / n);
-  for (int m = 0; m < nb; ++m) {
+  // FFT tiling: a column-pass block transforms ct columns of one ring at once, one
+  // transform per n/16 threads (a whole block of kBlock threads from n = 4096 on)
+  p->ct = kBlock / std::min(kBlock, std::max(1, n / 16));
+  for (int m = 0; m < nb; ++m)
     for (int g0 = 0; g0 < p->cols[m]; g0 += p->ct)
       p->tiles.push_back({m, g0, std::min(p->ct, p->cols[m] - g0), 0});
-    for (int g0 = 0; g0 < p->cols[m]; g0 += p->ct64)
-      p->tiles64.push_back({m, g0, std::min(p->ct64, p->cols[m] - g0), 0});
-  }
   const int64_t npix = (int64_t)n * n;
   p->pix_per_block = (int)std::min<int64_t>(16384, std::max<int64_t>(1024, npix / 64));
   p->nblk = (int)((npix + p->pix_per_block - 1) / p->pix_per_block);
@@ -494,8 +488,6 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
   off = al(off + (size_t)nb * sizeof(BinDev));
   p->dl.tiles = off;
   off = al(off + p->tiles.size() * sizeof(ColTile));
-  p->dl.tiles64 = off;
-  off = al(off + p->tiles64.size() * sizeof(ColTile));
   p->dl.total = off;
 
   if (!build_jit_source(p)) {
