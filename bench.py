@@ -25,10 +25,10 @@ WORKLOADS = {
     # MWA-shaped single channel: 1024^2 complex64, 20 log rings over 46 <= l < 1320
     "mwa1024": dict(n=1024, nbins=20, lmin=46.0, lmax=1320.0, batch=16, cfg=1,
                     desc="MWA-shaped single channel: 1024x1024 c64 grid, 20 log rings 46<=l<1320, "
-                         "Poisson baseline mask + SNR-5 noise, INV_COUNT weights, FP32"),
+                         "Poisson baseline mask + SNR-5 noise, INV_COUNT weights"),
     # precision-form shapes in FP32: 4096^2, 32 log rings, edges x4
     "mwa4096": dict(n=4096, nbins=32, lmin=4 * 46.0, lmax=4 * 1320.0, batch=2, cfg=2,
-                    desc="4096x4096 c64 grid, 32 log rings, FP32"),
+                    desc="MWA-shaped 4096x4096 c64 grid, 32 log rings 4x(46<=l<1320), INV_COUNT weights"),
 }
 class HipEvents:
     """Raw HIP events (the library records them on the call's stream)."""
@@ -60,7 +60,8 @@ class HipEvents:
         self.ev = []
 
 
-PEAK_VALU_FP32 = 78.6e12   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
+PEAK_VALU_FP32 = 78.6e12
+PEAK_MFMA_16BIT = 2.5e15   # dense BF16 / FP16 matrix peak   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
 PEAK_HBM = 8.0e12
 
 
@@ -71,6 +72,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mwa1024", choices=sorted(WORKLOADS))
     ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
@@ -118,7 +120,8 @@ def main():
     print("bench: workload %s n=%d rings=%d batch=%d nvis=%d" % (a.workload, n, nb, batch, nvis),
           file=sys.stderr, flush=True)
     uv, vis = synth.mwa_visibilities(n, nvis, edges[-1], synth.seed_for(W["cfg"], 0), batch=batch)
-    plan = A.Plan(n, edges, wmode=A.W_INV_COUNT, max_batch=batch).bind()
+    prec = {"fp32": A.FP32, "bf16x3": A.BF16X3, "fp16x3": A.FP16X3}[a.precision]
+    plan = A.Plan(n, edges, wmode=A.W_INV_COUNT, max_batch=batch, precision=prec).bind()
     print("bench: plan ntrip=%d npairs=%d; inputs generated" % (plan.ntrip, plan.npairs),
           file=sys.stderr, flush=True)
     uv_d = torch.from_numpy(uv).to(dev)
@@ -145,21 +148,32 @@ def main():
     ev.close()
     ms = 1e3 * dt / a.steps
     grids_s = batch * a.steps / dt
-    nsets = batch + 1
+    nsets = batch  # the contraction launch timed is the data-set one (the weight set runs in FP64)
     flops = float(nsets) * n * n * (plan.npairs + 2 * plan.ntrip)
     achieved = flops / (con_ms * 1e-3)
+    if a.precision == "fp32":
+        roof = {"kernel": "abs_contract (plan-specialised FP32 triplet contraction)", "bound": "alu",
+                "achieved": achieved / 1e12, "peak": PEAK_VALU_FP32 / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_VALU_FP32, "traffic": None, "avg_ms": con_ms,
+                "flops_per_launch": flops}
+    else:
+        issued = float(nsets) * n * n * plan.mfma_tiles * 3 * 512   # 3 split MFMAs per tile
+        roof = {"kernel": "mfma_contract_kernel (%s triplet contraction)" % a.precision, "bound": "mfma",
+                "achieved": achieved / 1e12, "peak": PEAK_MFMA_16BIT / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_MFMA_16BIT, "traffic": None, "avg_ms": con_ms,
+                "flops_per_launch": flops,
+                "mfma_issued_tflops": issued / (con_ms * 1e-3) / 1e12,
+                "mfma_issued_frac": issued / (con_ms * 1e-3) / PEAK_MFMA_16BIT}
     out = {
         "metric": "bispectrum grids/s at 1 GPU (gridding + estimator)",
         "value": grids_s, "unit": "grids/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": {"fp32": "f32", "bf16x3": "bf16x3 (f32 acc)", "fp16x3": "fp16x3 (f32 acc)"}[a.precision],
+        "data": "synthetic",
         "config": {"workload": W["desc"], "n": n, "nbins": nb, "grids_per_step": batch,
-                   "nvis_per_grid": nvis, "ntrip": int(plan.ntrip),
+                   "nvis_per_grid": nvis, "ntrip": int(plan.ntrip), "precision": a.precision,
                    "bin_triplets_per_s": grids_s * plan.ntrip, "parallelism": "1 GPU"},
-        "roofline": {"kernel": "abs_contract (triplet contraction)", "bound": "alu",
-                     "achieved": achieved / 1e12, "peak": PEAK_VALU_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_VALU_FP32, "traffic": None,
-                     "avg_ms": con_ms, "flops_per_launch": flops},
+        "roofline": roof,
     }
     if not a.no_cpu:
         e_sample = min(batch, 2)

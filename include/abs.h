@@ -89,6 +89,7 @@ typedef struct abs_plan_info {
   int64_t ncols;        /* half-plane uv columns the ring FFTs touch, summed over rings */
   int64_t plan_bytes;   /* device bytes abs_plan_bind needs                           */
   double norm;          /* the A actually used                                        */
+  int64_t mfma_tiles;   /* 16 x 16 output tiles of the precision-form contraction     */
 } abs_plan_info;
 
 /* Build a plan on the host: rings (Sec. 2), the triplet list with an exact lattice

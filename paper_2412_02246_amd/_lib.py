@@ -27,7 +27,8 @@ class PlanDesc(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nbins", ctypes.c_int32), ("ntrip", ctypes.c_int64),
                 ("npairs", ctypes.c_int64), ("ncols", ctypes.c_int64),
-                ("plan_bytes", ctypes.c_int64), ("norm", ctypes.c_double)]
+                ("plan_bytes", ctypes.c_int64), ("norm", ctypes.c_double),
+                ("mfma_tiles", ctypes.c_int64)]
 
 
 class AbsError(RuntimeError):

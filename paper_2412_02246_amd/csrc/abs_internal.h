@@ -13,6 +13,7 @@ namespace abs_impl {
 
 constexpr int kBlock = 256;          // threads per workgroup for every kernel here
 constexpr int kMaxBins = 64;
+constexpr int kTilesPerWave = 16;    // MFMA output tiles owned by one wave (precision form)
 constexpr int kMaxN = 8192;
 
 // One contiguous run of uv columns gx0 .. gx0 + ncols - 1 of ring m, transformed
@@ -31,14 +32,16 @@ struct BinDev {
 
 // Offsets (bytes) of the tables inside the caller's plan memory.
 struct DevLayout {
-  size_t tw, tw64, bins, tiles, total;
+  size_t tw, tw64, bins, tiles;
+  size_t pt_pairs, mt_ptile, mt_bins, mt_trip, wave_tiles;   // precision-form tables
+  size_t total;
 };
 
 // Offsets (bytes) of the buffers inside the abs_estimate workspace.
 struct WorkLayout {
   int nsets;          // D sets (one per grid) followed by I sets
   int nisets;
-  size_t zd, zi, fd, fi, part, total;
+  size_t zd, zi, fd, fi, part, fmax, total;
   int64_t zset;       // complex elements per set of column-pass output
   int64_t fset;       // values per set of fields (nbins * n * n)
   int64_t partset;    // doubles per set of contraction partials (nblk * ntrip)
@@ -65,6 +68,13 @@ struct abs_plan_s {
   // FFT tiling
   int ct = 0;                    // columns per column-pass block
   std::vector<abs_impl::ColTile> tiles;
+  // precision form: 16-pair row tiles, 16 x 16 MFMA tiles and their owner waves
+  std::vector<int> pt_pairs;     // 2 * 16 per row tile: (i, j), padding rows (nb, nb)
+  std::vector<int> mt_ptile;     // row tile of each MFMA tile
+  std::vector<int> mt_bins;      // 16 ring columns per MFMA tile, padding nb
+  std::vector<int> mt_trip;      // 256 per MFMA tile: triplet index or -1
+  std::vector<int> wave_tiles;   // 2 per wave: first tile, count
+  int mfma_groups = 0;           // workgroups (of 8 waves) per pixel block and set
   // contraction kernel (compiled at run time for this triplet list)
   int ngroups = 0;               // wave groups of the FP32 kernel; one wave per group
   int ngroups64 = 0;             // wave groups of the FP64 kernel (weight fields)
@@ -89,6 +99,7 @@ namespace abs_impl {
 bool build_jit_source(abs_plan_s* p);
 abs_status compile_jit(abs_plan_s* p);
 WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_counts);
+void build_mfma_tables(abs_plan_s* p);
 inline void prof_begin(const abs_plan_s* p, int stage, hipStream_t st) {
   if (p->prof[stage][0]) (void)hipEventRecord(p->prof[stage][0], st);
 }

@@ -16,7 +16,14 @@ hipError_t launch_colpass_data(const abs_plan_s* p, const void* grids, int dtype
 hipError_t launch_colpass_weight(const abs_plan_s* p, const float* w, int w_batched, int nsets,
                                  double2* Z, long long zset, hipStream_t st);
 hipError_t launch_rowpass_f32(const abs_plan_s* p, int nsets, const float2* Z, long long zset,
-                              float* F, long long fset, hipStream_t st);
+                              float* F, long long fset, unsigned* fmax_bits, hipStream_t st);
+hipError_t launch_mfma_contract(const abs_plan_s* p, const float* F, long long fset, int nsets,
+                                double* part, const unsigned* fmax_bits, hipStream_t st);
+
+__global__ void fill_u32_kernel(unsigned* __restrict__ a, int n, unsigned v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
 hipError_t launch_rowpass_f64(const abs_plan_s* p, int nsets, const double2* Z, long long zset,
                               double* F, long long fset, hipStream_t st);
 
@@ -91,13 +98,25 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
     if (launch_colpass_data(p, grids, dtype, w, w_batched, batch, Z, wl.zset, st) != hipSuccess)
       return ABS_ERR_DEVICE;
     prof_end(p, ABS_STAGE_COLPASS, st);
+    // FP16 splits need a power-of-two scale per (grid, ring): the row pass records max |F|
+    unsigned* fmax = nullptr;
+    if (p->precision == ABS_FP16X3) {
+      fmax = reinterpret_cast<unsigned*>(work + wl.fmax);
+      const int cnt = batch * p->nb;
+      fill_u32_kernel<<<(cnt + kBlock - 1) / kBlock, kBlock, 0, st>>>(fmax, cnt, 0u);
+    }
     prof_begin(p, ABS_STAGE_ROWPASS, st);
-    if (launch_rowpass_f32(p, batch, Z, wl.zset, F, wl.fset, st) != hipSuccess)
+    if (launch_rowpass_f32(p, batch, Z, wl.zset, F, wl.fset, fmax, st) != hipSuccess)
       return ABS_ERR_DEVICE;
     prof_end(p, ABS_STAGE_ROWPASS, st);
     prof_begin(p, ABS_STAGE_CONTRACT, st);
-    const abs_status s = launch_contract(p->contract, p->ngroups, F, wl.fset, npix,
-                                         p->pix_per_block, p->nblk, (int)p->ntrip, batch, part, st);
+    abs_status s;
+    if (p->precision == ABS_FP32)
+      s = launch_contract(p->contract, p->ngroups, F, wl.fset, npix, p->pix_per_block, p->nblk,
+                          (int)p->ntrip, batch, part, st);
+    else
+      s = launch_mfma_contract(p, F, wl.fset, batch, part, fmax, st) == hipSuccess ? ABS_OK
+                                                                                  : ABS_ERR_DEVICE;
     prof_end(p, ABS_STAGE_CONTRACT, st);
     if (s != ABS_OK) return s;
   }
@@ -139,7 +158,9 @@ abs_status abs_plan_bind(abs_plan_t p, void* mem, size_t bytes, void* stream) {
     p->module = nullptr;
     return ABS_ERR_JIT;
   }
-  if (hipModuleGetFunction(&p->contract, p->module, "abs_contract") != hipSuccess ||
+  p->contract = nullptr;
+  if ((p->precision == ABS_FP32 &&
+       hipModuleGetFunction(&p->contract, p->module, "abs_contract") != hipSuccess) ||
       hipModuleGetFunction(&p->contract64, p->module, "abs_contract64") != hipSuccess)
     return ABS_ERR_JIT;
   // host image of the tables
@@ -160,6 +181,14 @@ abs_status abs_plan_bind(abs_plan_t p, void* mem, size_t bytes, void* stream) {
     bins[m].zoff = p->zoff[m];
   }
   std::memcpy(img.data() + p->dl.tiles, p->tiles.data(), p->tiles.size() * sizeof(ColTile));
+  auto put = [&](size_t off, const std::vector<int>& v) {
+    std::memcpy(img.data() + off, v.data(), v.size() * sizeof(int));
+  };
+  put(p->dl.pt_pairs, p->pt_pairs);
+  put(p->dl.mt_ptile, p->mt_ptile);
+  put(p->dl.mt_bins, p->mt_bins);
+  put(p->dl.mt_trip, p->mt_trip);
+  put(p->dl.wave_tiles, p->wave_tiles);
   if (hipMemcpyAsync(mem, img.data(), img.size(), hipMemcpyHostToDevice, st) != hipSuccess)
     return ABS_ERR_DEVICE;
   // the host image is a local: wait for the copy before it goes out of scope

@@ -285,7 +285,8 @@ template <typename R, int U>
 __global__ void __launch_bounds__(kBlock)
 rowpass_kernel(int n, int log2n, int iters, const BinDev* __restrict__ bins,
                const typename Cx<R>::T* __restrict__ tw, const typename Cx<R>::T* __restrict__ Z,
-               long long zset, R* __restrict__ F, long long fset) {
+               long long zset, R* __restrict__ F, long long fset, unsigned* __restrict__ fmax_bits,
+               int nb) {
   using T = typename Cx<R>::T;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const FftGeom geo = fft_geom(n);
@@ -303,6 +304,7 @@ rowpass_kernel(int n, int log2n, int iters, const BinDev* __restrict__ bins,
   T* lds = reinterpret_cast<T*>(lds_raw);
   const int L = fft_lds_elems(n);
   const int span = 2 * H + 1;
+  R vmax = R(0);   // largest |F| written by this thread (recorded when fmax_bits is given)
   for (int it = 0; it < iters; ++it) {
     const int pair0 = blk * per_block + it * geo.G;
     const int pair = pair0 + g;
@@ -312,6 +314,7 @@ rowpass_kernel(int n, int log2n, int iters, const BinDev* __restrict__ bins,
       if (active) {
         fs[(long long)ya * n + k] = v.x;
         fs[(long long)(ya + 1) * n + k] = v.y;
+        vmax = fmax(vmax, fmax(fabs(v.x), fabs(v.y)));
       }
     };
     if (cols == 0) {   // ring without lattice cells: its field is zero
@@ -335,6 +338,12 @@ rowpass_kernel(int n, int log2n, int iters, const BinDev* __restrict__ bins,
     __syncthreads();
     stockham_fft<R, U>(buf, n, log2n, t, geo.Tg, tw, out);
     __syncthreads();   // the staging area is refilled by the next iteration
+  }
+  if (fmax_bits) {
+    float v = (float)vmax;
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    // non-negative floats order like their bit patterns
+    if ((threadIdx.x & 63) == 0) atomicMax(&fmax_bits[(long long)set * nb + m], __float_as_uint(v));
   }
 }
 
@@ -395,7 +404,7 @@ hipError_t launch_colpass_weight(const abs_plan_s* p, const float* w, int w_batc
 
 template <typename R>
 hipError_t launch_rowpass(const abs_plan_s* p, int nsets, const typename Cx<R>::T* Z,
-                          long long zset, R* F, long long fset, hipStream_t st) {
+                          long long zset, R* F, long long fset, unsigned* fmax_bits, hipStream_t st) {
   const char* base = static_cast<const char*>(p->dev);
   const BinDev* bins = reinterpret_cast<const BinDev*>(base + p->dl.bins);
   const bool f64 = sizeof(R) == 8;
@@ -410,23 +419,23 @@ hipError_t launch_rowpass(const abs_plan_s* p, int nsets, const typename Cx<R>::
     auto k = rowpass_kernel<R, 2>;
     hipError_t e = allow_lds(k, lds);
     if (e != hipSuccess) return e;
-    k<<<grid, kBlock, lds, st>>>(p->n, p->log2n, iters, bins, tw, Z, zset, F, fset);
+    k<<<grid, kBlock, lds, st>>>(p->n, p->log2n, iters, bins, tw, Z, zset, F, fset, fmax_bits, p->nb);
   } else {
     auto k = rowpass_kernel<R, 1>;
     hipError_t e = allow_lds(k, lds);
     if (e != hipSuccess) return e;
-    k<<<grid, kBlock, lds, st>>>(p->n, p->log2n, iters, bins, tw, Z, zset, F, fset);
+    k<<<grid, kBlock, lds, st>>>(p->n, p->log2n, iters, bins, tw, Z, zset, F, fset, fmax_bits, p->nb);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_rowpass_f32(const abs_plan_s* p, int nsets, const float2* Z, long long zset,
-                              float* F, long long fset, hipStream_t st) {
-  return launch_rowpass<float>(p, nsets, Z, zset, F, fset, st);
+                              float* F, long long fset, unsigned* fmax_bits, hipStream_t st) {
+  return launch_rowpass<float>(p, nsets, Z, zset, F, fset, fmax_bits, st);
 }
 hipError_t launch_rowpass_f64(const abs_plan_s* p, int nsets, const double2* Z, long long zset,
                               double* F, long long fset, hipStream_t st) {
-  return launch_rowpass<double>(p, nsets, Z, zset, F, fset, st);
+  return launch_rowpass<double>(p, nsets, Z, zset, F, fset, nullptr, st);
 }
 
 }  // namespace abs_impl

@@ -1,0 +1,240 @@
+// Precision form of the triplet contraction (Eq. 12 numerator) on the gfx950 matrix cores.
+//
+// For a chunk of K pixels the sums S_(ij)k = sum_theta P_ij(theta) D_k(theta), with pair
+// products P_ij = D_i D_j, form a (pairs x K) by (K x rings) matrix product.  Both
+// operands are split into two 16-bit halves, x = hi + lo (BF16, or FP16 after scaling every
+// ring by a power of two so its largest value is below 1), and each 16 x 16 output tile
+// accumulates hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_{bf16,f16} in FP32; the lo*lo term
+// is below the split's own rounding.  Each chunk's products start from zero and are then
+// added to the tile's running FP32 sum (long FP32 accumulation chains, not the split,
+// otherwise dominate the error); tile sums over a workgroup's pixels are written as FP64
+// partials per triplet, in the same layout as the FP32 path, so the FP64 finaliser is
+// shared.
+//
+// Tiles are block-sparse: pairs are ordered by (j, i) and cut into tiles of 16 rows; each
+// row tile only multiplies against the rings that close a triangle with one of its pairs
+// (16 columns per MFMA tile; absent rows / columns point at a zero row of LDS).  Output
+// entries that are not plan triplets are computed and dropped.
+//
+// Workgroup: 8 waves; blockIdx.x = pixel block, blockIdx.y = set, blockIdx.z = wave
+// group.  Per chunk of kChunk pixels the workgroup stages the rings' FP32 values and their
+// hi/lo halves in LDS; each wave then evaluates its MFMA tiles (at most kTilesPerWave,
+// accumulators in registers across the whole pixel block).  Every MFMA tile has its own
+// row tile (a row tile whose rings need more than 16 columns is repeated), so the A
+// operand (the pair products, split) is formed per tile and k-step, just in time.
+#include "abs_internal.h"
+
+namespace abs_impl {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaThreads = 512;
+constexpr int kChunk = 128;                 // pixels staged per step (4 MFMA k-steps of 32)
+constexpr int kRow32 = kChunk + 4;          // padded LDS row lengths (elements)
+constexpr int kRow16 = kChunk + 8;
+// FP16 scaling: every ring is scaled by a power of two to a largest |value| in
+// [2^(kF16Exp-1), 2^kF16Exp); pair products then stay below 2^14 < 65504 and their low
+// halves stay clear of the FP16 subnormal range for all but negligible terms.
+constexpr int kF16Exp = 7;
+
+template <bool F16> struct Half;
+template <> struct Half<false> {
+  using T = __bf16;
+  using V = bf16x8;
+  static __device__ __forceinline__ f32x4 mma(V a, V b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Half<true> {
+  using T = _Float16;
+  using V = f16x8;
+  static __device__ __forceinline__ f32x4 mma(V a, V b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+size_t mfma_lds_bytes(int nb) {
+  return (size_t)(nb + 1) * (kRow32 * 4 + 2 * kRow16 * 2);
+}
+
+template <bool F16>
+__global__ void __launch_bounds__(kMfmaThreads)
+mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long long npix, int ppb,
+                     double* __restrict__ part, int nblk, int ntrip, int nb,
+                     const int2* __restrict__ pt_pairs, const int* __restrict__ mt_ptile,
+                     const int* __restrict__ mt_bins, const int* __restrict__ mt_trip,
+                     const int2* __restrict__ wave_tiles, const unsigned* __restrict__ fmax_bits) {
+  using H = Half<F16>;
+  using HT = typename H::T;
+  using HV = typename H::V;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  float* d32 = reinterpret_cast<float*>(lds_raw);
+  HT* dhi = reinterpret_cast<HT*>(lds_raw + (size_t)(nb + 1) * kRow32 * 4);
+  HT* dlo = dhi + (size_t)(nb + 1) * kRow16;
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = lane & 15, quad = lane >> 4;
+  const long long set = blockIdx.y;
+  const float* __restrict__ Fs = F + set * set_stride;
+  const long long p0 = (long long)blockIdx.x * ppb;
+  const long long p1 = (p0 + ppb < npix) ? p0 + ppb : npix;
+  const int2 wr = wave_tiles[blockIdx.z * (kMfmaThreads / 64) + wave];
+
+  // power-of-two scale per ring (FP16 only), from max |F_m| recorded by the row pass:
+  // sexp[m] = e with max |F_m| < 2^e (0 for an all-zero ring)
+  __shared__ int sexp[kMaxBins + 1];
+  const bool scaled = F16 && fmax_bits != nullptr;
+  if (threadIdx.x <= nb) {
+    int e = 0;
+    if (scaled && threadIdx.x < nb) {
+      const unsigned b = fmax_bits[set * nb + threadIdx.x];
+      e = b ? (int)((b >> 23) & 0xffu) - 126 : 0;
+    }
+    sexp[threadIdx.x] = e;
+  }
+
+  // the zero row
+  for (int q = threadIdx.x; q < kRow32; q += blockDim.x) d32[nb * kRow32 + q] = 0.f;
+  for (int q = threadIdx.x; q < kRow16; q += blockDim.x) {
+    dhi[nb * kRow16 + q] = (HT)0.f;
+    dlo[nb * kRow16 + q] = (HT)0.f;
+  }
+
+  f32x4 acc[kTilesPerWave];
+#pragma unroll
+  for (int s = 0; s < kTilesPerWave; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // The chunk's global loads are issued one chunk ahead (registers), so their latency
+  // overlaps the matrix work on the previous chunk.  Thread q stages the values
+  // (m, x) = divmod(threadIdx.x + kMfmaThreads * u, kChunk), u < kStage.
+  constexpr int kStage = (kMaxBins * kChunk) / kMfmaThreads;
+  const int nstage = (nb * kChunk + kMfmaThreads - 1) / kMfmaThreads;
+  float pre[kStage];
+  auto load_chunk = [&](long long c0) {
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int q = threadIdx.x + kMfmaThreads * u;
+      const int m = q / kChunk, x = q - m * kChunk;
+      const long long p = c0 + x;
+      pre[u] = (u < nstage && m < nb && p < p1) ? Fs[(long long)m * npix + p] : 0.f;
+    }
+  };
+  if (p0 < p1) load_chunk(p0);
+  for (long long c0 = p0; c0 < p1; c0 += kChunk) {
+    // stage the chunk: FP32 values (scaled for FP16) and their hi / lo halves
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int q = threadIdx.x + kMfmaThreads * u;
+      const int m = q / kChunk, x = q - m * kChunk;
+      if (u < nstage && m < nb) {
+        float v = pre[u];
+        if (scaled) v = ldexpf(v, kF16Exp - sexp[m]);
+        const HT h = (HT)v;
+        const HT l = (HT)(v - (float)h);
+        d32[m * kRow32 + x] = v;
+        dhi[m * kRow16 + x] = h;
+        dlo[m * kRow16 + x] = l;
+      }
+    }
+    __syncthreads();
+    if (c0 + kChunk < p1) load_chunk(c0 + kChunk);
+#pragma unroll
+    for (int s = 0; s < kTilesPerWave; ++s) {
+      if (s < wr.y) {
+        const int tile = wr.x + s;
+        const int2 ij = pt_pairs[mt_ptile[tile] * 16 + row];
+        const float* di = d32 + ij.x * kRow32;
+        const float* dj = d32 + ij.y * kRow32;
+        const int bin = mt_bins[tile * 16 + row];
+        // one chunk's three split products in fresh accumulators (three independent
+        // chains of kChunk/32 steps), then one FP32 add into the tile's running sum: keeps
+        // every FP32 accumulation chain short (kChunk/32 steps within a chunk, one add per
+        // chunk across the pixel block)
+        f32x4 chh = {0.f, 0.f, 0.f, 0.f}, chl = chh, clh = chh;
+#pragma unroll
+        for (int ks = 0; ks < kChunk / 32; ++ks) {
+          const int x0 = ks * 32 + quad * 8;
+          // A operand: the pair products of this lane's row and 8 pixels, split
+          HV ahi, alo;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const float pv = di[x0 + q] * dj[x0 + q];
+            const HT h = (HT)pv;
+            ahi[q] = h;
+            alo[q] = (HT)(pv - (float)h);
+          }
+          const HV bh = *reinterpret_cast<const HV*>(dhi + bin * kRow16 + x0);
+          const HV bl = *reinterpret_cast<const HV*>(dlo + bin * kRow16 + x0);
+          chh = H::mma(ahi, bh, chh);
+          chl = H::mma(ahi, bl, chl);
+          clh = H::mma(alo, bh, clh);
+        }
+        acc[s] += chh + (chl + clh);
+      }
+    }
+    __syncthreads();
+  }
+
+  // lane holds C[4 * quad + q][row] of each of its tiles
+  double* __restrict__ out = part + (set * nblk + blockIdx.x) * (long long)ntrip;
+#pragma unroll
+  for (int s = 0; s < kTilesPerWave; ++s) {
+    if (s < wr.y) {
+      const int tile = wr.x + s;
+      const int pt = mt_ptile[tile];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 4 * quad + q;
+        const int t = mt_trip[tile * 256 + r * 16 + row];
+        if (t >= 0) {
+          double v = (double)acc[s][q];
+          if (scaled) {
+            const int2 ij = pt_pairs[pt * 16 + r];
+            const int k = mt_bins[tile * 16 + row];
+            v = ldexp(v, sexp[ij.x] + sexp[ij.y] + sexp[k] - 3 * kF16Exp);
+          }
+          out[t] = v;
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_mfma_contract(const abs_plan_s* p, const float* F, long long fset, int nsets,
+                                double* part, const unsigned* fmax_bits, hipStream_t st) {
+  const char* base = static_cast<const char*>(p->dev);
+  const int2* pt_pairs = reinterpret_cast<const int2*>(base + p->dl.pt_pairs);
+  const int* mt_ptile = reinterpret_cast<const int*>(base + p->dl.mt_ptile);
+  const int* mt_bins = reinterpret_cast<const int*>(base + p->dl.mt_bins);
+  const int* mt_trip = reinterpret_cast<const int*>(base + p->dl.mt_trip);
+  const int2* wave_tiles = reinterpret_cast<const int2*>(base + p->dl.wave_tiles);
+  const size_t lds = mfma_lds_bytes(p->nb);
+  const dim3 grid((unsigned)p->nblk, (unsigned)nsets, (unsigned)p->mfma_groups);
+  const long long npix = (long long)p->n * p->n;
+  if (p->precision == ABS_FP16X3) {
+    auto k = mfma_contract_kernel<true>;
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    k<<<grid, kMfmaThreads, lds, st>>>(F, fset, npix, p->pix_per_block, part, p->nblk, (int)p->ntrip,
+                                       p->nb, pt_pairs, mt_ptile, mt_bins, mt_trip, wave_tiles,
+                                       fmax_bits);
+  } else {
+    auto k = mfma_contract_kernel<false>;
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    k<<<grid, kMfmaThreads, lds, st>>>(F, fset, npix, p->pix_per_block, part, p->nblk, (int)p->ntrip,
+                                       p->nb, pt_pairs, mt_ptile, mt_bins, mt_trip, wave_tiles,
+                                       nullptr);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace abs_impl

@@ -164,6 +164,8 @@ WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_c
   off = al(off + (size_t)w.nisets * w.fset * 8);
   w.part = off;
   off = al(off + (size_t)w.nsets * w.partset * 8);
+  w.fmax = off;
+  off = al(off + (size_t)batch * p->nb * 4);
   w.total = off;
   return w;
 }
@@ -294,7 +296,8 @@ bool build_jit_source(abs_plan_s* p) {
        "__device__ __forceinline__ double abs_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }\n"
        "template <typename T> __device__ __forceinline__ T abs_wsum(T v) {\n"
        "  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);\n  return v;\n}\n";
-  emit_kernel(p, g32, "abs_contract", "float", s);
+  // the FP32 kernel serves the FP32 data path; the weight fields always use FP64
+  if (p->precision == ABS_FP32) emit_kernel(p, g32, "abs_contract", "float", s);
   emit_kernel(p, g64, "abs_contract64", "double", s);
   p->jit_src.swap(s);
   return true;
@@ -341,6 +344,81 @@ abs_status compile_jit(abs_plan_s* p) {
   return ABS_OK;
 }
 
+// Precision-form tiling: pairs (i, j) of the triplet list ordered by (j, i), cut into
+// row tiles of 16; each row tile multiplies against the union of the rings k that close
+// triangles with its pairs, 16 rings per MFMA tile.  Tiles are dealt to waves in
+// contiguous, balanced runs of at most kTilesPerWave.
+void build_mfma_tables(abs_plan_s* p) {
+  const int nb = p->nb;
+  std::vector<std::vector<int>> kset(nb * nb);
+  std::vector<int> tindex(nb * nb * nb, -1);
+  for (int64_t t = 0; t < p->ntrip; ++t) {
+    const int i = p->trips[3 * t], j = p->trips[3 * t + 1], k = p->trips[3 * t + 2];
+    kset[i * nb + j].push_back(k);
+    tindex[(i * nb + j) * nb + k] = (int)t;
+  }
+  std::vector<std::pair<int, int>> pairs;   // (j, i)
+  for (int i = 0; i < nb; ++i)
+    for (int j = i; j < nb; ++j)
+      if (!kset[i * nb + j].empty()) pairs.push_back({j, i});
+  std::sort(pairs.begin(), pairs.end());
+  p->pt_pairs.clear();
+  p->mt_ptile.clear();
+  p->mt_bins.clear();
+  p->mt_trip.clear();
+  const int npt = (int)((pairs.size() + 15) / 16);
+  std::vector<std::vector<int>> kvs(npt);
+  for (int pt = 0; pt < npt; ++pt) {
+    std::set<int> ks;
+    for (int r = 0; r < 16; ++r) {
+      const size_t q = (size_t)pt * 16 + r;
+      if (q < pairs.size()) {
+        const int i = pairs[q].second, j = pairs[q].first;
+        p->pt_pairs.push_back(i);
+        p->pt_pairs.push_back(j);
+        for (int k : kset[i * nb + j]) ks.insert(k);
+      } else {
+        p->pt_pairs.push_back(nb);
+        p->pt_pairs.push_back(nb);
+      }
+    }
+    kvs[pt].assign(ks.begin(), ks.end());
+  }
+  for (int pt = 0; pt < npt; ++pt) {
+    const std::vector<int>& kv = kvs[pt];
+    for (size_t c0 = 0; c0 < kv.size(); c0 += 16) {
+      // one row tile per MFMA tile: repeat the rows (appended after the npt originals)
+      // when the rings need more than 16 columns
+      int tpt = pt;
+      if (c0 > 0) {
+        tpt = (int)(p->pt_pairs.size() / 32);
+        for (int r = 0; r < 32; ++r) p->pt_pairs.push_back(p->pt_pairs[32 * pt + r]);
+      }
+      p->mt_ptile.push_back(tpt);
+      int cols[16];
+      for (int c = 0; c < 16; ++c) cols[c] = c0 + c < kv.size() ? kv[c0 + c] : nb;
+      for (int c = 0; c < 16; ++c) p->mt_bins.push_back(cols[c]);
+      for (int r = 0; r < 16; ++r) {
+        const int i = p->pt_pairs[2 * (pt * 16 + r)], j = p->pt_pairs[2 * (pt * 16 + r) + 1];
+        for (int c = 0; c < 16; ++c) {
+          const int k = cols[c];
+          p->mt_trip.push_back(i < nb && k < nb ? tindex[(i * nb + j) * nb + k] : -1);
+        }
+      }
+    }
+  }
+  const int T = (int)p->mt_ptile.size();
+  int waves = std::max(8, (T + kTilesPerWave - 1) / kTilesPerWave);
+  waves = (waves + 7) / 8 * 8;
+  p->mfma_groups = waves / 8;
+  p->wave_tiles.assign(2 * waves, 0);
+  for (int w = 0; w < waves; ++w) {
+    const int a = (int)((int64_t)T * w / waves), b = (int)((int64_t)T * (w + 1) / waves);
+    p->wave_tiles[2 * w] = a;
+    p->wave_tiles[2 * w + 1] = b - a;
+  }
+}
+
 }  // namespace abs_impl
 
 extern "C" {
@@ -367,7 +445,7 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
   if (nb < 1 || nb > kMaxBins || !d->edges) return ABS_ERR_INVALID;
   if (d->max_batch < 1 || d->max_batch > 65535) return ABS_ERR_INVALID;
   if (d->wmode < ABS_W_UNIT || d->wmode > ABS_W_GIVEN) return ABS_ERR_INVALID;
-  if (d->precision != ABS_FP32) return ABS_ERR_INVALID;
+  if (d->precision < ABS_FP32 || d->precision > ABS_FP16X3) return ABS_ERR_INVALID;
   if (!(d->du > 0.0) || !std::isfinite(d->du)) return ABS_ERR_INVALID;
   for (int m = 0; m <= nb; ++m)
     if (!std::isfinite(d->edges[m]) || d->edges[m] < 0.0) return ABS_ERR_INVALID;
@@ -488,6 +566,17 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
   off = al(off + (size_t)nb * sizeof(BinDev));
   p->dl.tiles = off;
   off = al(off + p->tiles.size() * sizeof(ColTile));
+  build_mfma_tables(p);
+  p->dl.pt_pairs = off;
+  off = al(off + p->pt_pairs.size() * 4);
+  p->dl.mt_ptile = off;
+  off = al(off + p->mt_ptile.size() * 4);
+  p->dl.mt_bins = off;
+  off = al(off + p->mt_bins.size() * 4);
+  p->dl.mt_trip = off;
+  off = al(off + p->mt_trip.size() * 4);
+  p->dl.wave_tiles = off;
+  off = al(off + p->wave_tiles.size() * 4);
   p->dl.total = off;
 
   if (!build_jit_source(p)) {
@@ -507,6 +596,7 @@ abs_status abs_plan_info_get(abs_plan_t p, abs_plan_info* o) {
   o->ncols = p->ncols;
   o->plan_bytes = (int64_t)p->dl.total;
   o->norm = p->norm;
+  o->mfma_tiles = (int64_t)p->mt_ptile.size();
   return ABS_OK;
 }
 

@@ -47,6 +47,8 @@ class Plan:
         self.n, self.nbins = info.n, info.nbins
         self.ntrip, self.npairs, self.ncols = info.ntrip, info.npairs, info.ncols
         self.plan_bytes, self.norm = info.plan_bytes, info.norm
+        self.mfma_tiles = info.mfma_tiles
+        self.precision = int(precision)
         self.wmode, self.max_batch = int(wmode), int(max_batch)
         ijk = np.zeros((self.ntrip, 3), np.int32)
         lab = np.zeros((self.ntrip, 5), np.float64)

@@ -1,0 +1,50 @@
+"""GPU parity at full size: 4096 x 4096 MWA-shaped grid, 32 log rings over
+4 x (46 <= l < 1320), INV_COUNT weights, in FP32 and in the two precision forms.
+The oracle computes a sample of the triplets one by one: every plan triplet whose
+three rings lie in a fixed subset of 9 rings, each compared element by element."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import estimator as oest
+from oracle import plan as oplan
+
+pytestmark = pytest.mark.gpu
+
+N = 4096
+EDGES = oplan.log_edges(4 * 46 / (2 * np.pi), 4 * 1320 / (2 * np.pi), 32)
+SUBSET = {0, 4, 8, 12, 16, 20, 24, 28, 31}
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "fp16x3": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def c3():
+    import paper_2412_02246_amd as A
+    V, counts = synth.mwa_like(N, synth.seed_for(2, 0), U0=N / 8)
+    V = V.astype(np.complex64)
+    host = A.Plan(N, EDGES)          # the triplet list only (host, exact)
+    idx = np.array([q for q, t in enumerate(host.triplets) if set(t.tolist()) <= SUBSET])
+    print("C3 sample: %d of %d triplets" % (len(idx), host.ntrip), flush=True)
+    ref = oest.estimate_subset(V, counts, EDGES, host.norm, host.triplets[idx], wmode=oest.INV_COUNT)
+    return V, counts, idx, ref, host.triplets
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
+def test_c3_full_size(c3, prec):
+    import torch
+    import paper_2412_02246_amd as A
+    V, counts, idx, ref, trips = c3
+    P = {"fp32": A.FP32, "bf16x3": A.BF16X3, "fp16x3": A.FP16X3}[prec]
+    p = A.Plan(N, EDGES, wmode=A.W_INV_COUNT, precision=P).bind()
+    assert np.array_equal(p.triplets, trips)
+    B, Nn = p.estimate(torch.from_numpy(V).cuda(), torch.from_numpy(counts.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    B = B[0].cpu().numpy()[idx]
+    Nn = Nn[0].cpu().numpy()[idx]
+    e = oest.relative_error(B, ref, p.norm)
+    en = oest.count_error(Nn, ref)
+    print("C3 %s: e_t median %.3g max %.3g, e_N max %.3g over %d sampled triplets"
+          % (prec, np.median(e), e.max(), en.max(), len(idx)), flush=True)
+    assert np.all(np.isfinite(B))
+    assert e.max() <= TOL[prec]
+    assert en.max() <= 1e-5

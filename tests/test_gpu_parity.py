@@ -201,3 +201,45 @@ def test_argument_errors():
     q = A.Plan(64, [2.0, 4.0, 8.0], wmode=A.W_INV_COUNT).bind()
     with pytest.raises(A.AbsError):
         q.estimate(g)                         # weights required
+
+
+# ---- precision form: BF16 / FP16 hi+lo split products on MFMA, FP32 accumulation ----
+PREC_TOL = 1e-4
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+def test_precision_form_c2(prec):
+    """1024 x 1024 MWA-shaped grids, 20 rings, INV_COUNT weights shared by 2 grids:
+    e_t <= 1e-4 on every triplet (FP64 weights, FP32 FFTs, split-precision contraction)."""
+    A = _A()
+    n = 1024
+    e = oplan.log_edges(46 / (2 * np.pi), 1320 / (2 * np.pi), 20)
+    grids, counts = _mwa_inputs(n, 2, 1, seed0=200)
+    P = {"bf16x3": A.BF16X3, "fp16x3": A.FP16X3}[prec]
+    p = A.Plan(n, e, wmode=A.W_INV_COUNT, max_batch=2, precision=P).bind()
+    B, N = _run(p, grids.astype(np.complex64), counts)
+    for b in range(2):
+        ref = oest.estimate(grids[b].astype(np.complex64), counts, e, p.norm, wmode=1,
+                            trips=p.triplets, with_scales=True)
+        err = oest.relative_error(B[b], ref, p.norm)
+        rel = np.abs(B[b] / ref["B"] - 1)
+        print("%s C2[%d]: e_t median %.3g p99 %.3g max %.3g | raw rel median %.3g p99 %.3g"
+              % (prec, b, np.median(err), np.quantile(err, 0.99), err.max(), np.median(rel),
+                 np.quantile(rel, 0.99)), flush=True)
+        _check(B[b], N[b], ref, p.norm, tol=PREC_TOL, label="%s C2[%d]" % (prec, b))
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("n,edges,flags", [SMALL[1], SMALL[2], SMALL[4], SMALL[3]])
+def test_precision_form_small(prec, n, edges, flags):
+    A = _A()
+    rng = np.random.default_rng(7 * n + flags)
+    # a large dynamic range between rings exercises the per-ring FP16 scaling
+    V = (rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n))) * 1e3
+    w = synth.symmetrize(rng.uniform(0.1, 2.0, (n, n)))
+    P = {"bf16x3": A.BF16X3, "fp16x3": A.FP16X3}[prec]
+    p = A.Plan(n, edges, norm=1.0, wmode=A.W_GIVEN, max_batch=2, flags=flags, precision=P).bind()
+    B, N = _run(p, V, w)
+    for b in range(2):
+        ref = oest.estimate(V[b], w, edges, 1.0, wmode=2, trips=p.triplets, with_scales=True)
+        _check(B[b], N[b], ref, 1.0, tol=PREC_TOL, label="%s n%d[%d]" % (prec, n, b))

@@ -145,3 +145,14 @@ def test_noise_scale_metric_is_zero_for_exact_values():
     assert np.all(estimator.relative_error(ref["B"], ref, 2.5) == 0)
     e = estimator.relative_error(ref["B"] * (1 + 1e-6), ref, 2.5)
     assert np.all(e <= 1.0000001e-6)
+
+
+def test_subset_estimate_matches_full():
+    n, edges = 32, [1.5, 2.7, 4.1, 6.0, 8.2, 10.6]
+    V, W = _random_case(n, 31, hermitian=True)
+    trips, _ = plan.plan_triplets(n, edges)
+    full = estimator.estimate(V, W, edges, 2.0, wmode=GIVEN, trips=trips, with_scales=True)
+    sub = trips[::3]
+    part = estimator.estimate_subset(V, W, edges, 2.0, sub, wmode=GIVEN)
+    for key in ("S", "N", "B", "rhoS", "rhoN"):
+        assert np.allclose(part[key], full[key][::3], rtol=1e-10, atol=1e-12), key
