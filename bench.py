@@ -70,7 +70,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mwa1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="mwa1024", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--requests", type=int, default=512, help="serve: number of requests")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="serve: admission budget")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -100,12 +102,107 @@ def cpu_baseline(n, edges, trips, uv, vis, norm, budget_s):
                       "(numpy FFT, BLAS %d threads), %.1f s" % (done, len(uv), cores, dt)}
 
 
+def serve_bench(a):
+    """Serving form: a Poisson stream of requests, each one channel or one realisation,
+    grid sizes uniform over {512, 1024, 2048, 4096}^2 complex64 with 16..32 log rings
+    (46 <= l < 1320, radii scaled by n/1024); half the requests are realisations sharing
+    their channel's weights (cached triangle counts), half channels with their own.
+    The saturated rate mu is measured first (all requests at t = 0), then streams at
+    rho mu, rho in {0.5, 0.8, 0.95}, report p50/p99 latency and grids/s."""
+    import torch
+
+    import paper_2412_02246_amd as A
+    from paper_2412_02246_amd.serve import GpuExecutor, Request, Scheduler, latency_stats, run_stream
+
+    rng = np.random.default_rng(4242)
+    sizes = [512, 1024, 2048, 4096]
+    specs = []
+    for k in range(a.requests):
+        n = int(rng.choice(sizes))
+        nb = int(rng.integers(16, 33))
+        s = n / 1024.0
+        edges = tuple((46.0 * s / (2 * np.pi)) * (1320.0 / 46.0) ** (np.arange(nb + 1) / nb))
+        specs.append((n, edges, bool(rng.random() < 0.5)))
+    prec = {"fp32": A.FP32, "bf16x3": A.BF16X3, "fp16x3": A.FP16X3}[a.precision]
+    slots, max_batch = 4, 8
+    # compile every plan in worker processes before the GPU is touched
+    from paper_2412_02246_amd.jit import compile_plans
+    keys = list(dict.fromkeys((n, e) for n, e, _ in specs))
+    kw = dict(wmode=A.W_INV_COUNT, precision=prec, max_batch=max_batch)
+    t0 = time.perf_counter()
+    plans = [A.Plan(n, e, **kw) for n, e in keys]
+    compile_plans(plans, [(n, e, kw) for n, e in keys], workers=16)
+    print("serve: %d plans compiled in %.1f s" % (len(plans), time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    ex = GpuExecutor(A.W_INV_COUNT, precision=prec, max_batch=max_batch, slots=slots)
+    for k, p in zip(keys, plans):
+        ex.plans[k] = p.bind(0)
+    # device-resident inputs: 4 grids per size, one shared (channel) mask per size and 4
+    # per-request masks per size
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(4242)
+    pool, chan, own = {}, {}, {}
+    for n in sizes:
+        g = torch.arange(n, device=dev)
+        g = torch.where(g < n // 2, g, g - n).double()
+        r = torch.sqrt(g[:, None] ** 2 + g[None, :] ** 2)
+        lam = 4.0 * torch.exp(-r / (n / 8.0))
+        pool[n] = [torch.randn((n, n), dtype=torch.complex64, device=dev, generator=gen) for _ in range(4)]
+        chan[n] = torch.poisson(lam, generator=gen).float()
+        own[n] = [torch.poisson(lam, generator=gen).float() for _ in range(4)]
+    torch.cuda.synchronize()
+
+    def requests(arrivals):
+        out = []
+        for k, ((n, e, shared), t) in enumerate(zip(specs, arrivals)):
+            grid = pool[n][k % 4]
+            if shared:
+                out.append(Request(k, n, e, grid, chan[n], ("chan", n), t))
+            else:
+                out.append(Request(k, n, e, grid, own[n][k % 4], None, t))
+        return out
+
+    budget = int(a.budget_gib * (1 << 30))
+    # warm-up pass (first launches, cached counts), then the saturated rate
+    run_stream(Scheduler(ex, budget, max_batch, slots), requests(np.zeros(len(specs)))[:32])
+    torch.cuda.synchronize()
+    sat = latency_stats(run_stream(Scheduler(ex, budget, max_batch, slots),
+                                   requests(np.zeros(len(specs)))))
+    mu = sat["grids_per_s"]
+    print("serve: saturated %.1f grids/s" % mu, file=sys.stderr, flush=True)
+    loads = {}
+    for rho in (0.5, 0.8, 0.95):
+        arr = np.cumsum(rng.exponential(1.0 / (rho * mu), len(specs)))
+        sch = Scheduler(ex, budget, max_batch, slots)
+        st = latency_stats(run_stream(sch, requests(arr)))
+        st["peak_budget_gib"] = sch.peak_used / (1 << 30)
+        st["rejected"] = len(sch.rejected)
+        loads["rho=%.2f" % rho] = st
+        print("serve: rho %.2f -> %s" % (rho, st), file=sys.stderr, flush=True)
+    out = {
+        "metric": "bispectrum grids/s at 1 GPU (serving, continuous batching)",
+        "value": mu, "unit": "grids/s", "n_gpus": 1, "steps": len(specs), "warmup": 32,
+        "ms_per_step": 1e3 / mu, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16x3": "bf16x3 (f32 acc)", "fp16x3": "fp16x3 (f32 acc)"}[a.precision],
+        "data": "synthetic",
+        "config": {"workload": "serving: %d requests, n in {512,1024,2048,4096}, 16-32 log rings, "
+                               "50%% shared-mask realisations / 50%% channels, budget %.0f GiB"
+                               % (len(specs), a.budget_gib),
+                   "slots": slots, "max_batch": max_batch, "saturated": sat, "poisson": loads},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); %d GPUs is not supported"
               % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if a.workload == "serve":
+        return serve_bench(a)
     import torch
 
     import paper_2412_02246_amd as A

@@ -116,6 +116,20 @@ abs_status abs_plan_triplets(abs_plan_t plan, int32_t* ijk, double* labels, doub
  * abs_plan_bind calls it when it has not been called.  Errors: ABS_ERR_JIT. */
 abs_status abs_plan_compile(abs_plan_t plan);
 
+/* The plan's compiled contraction code object, for caching or for compiling plans in
+ * several processes (run-time compilation is serialised within one process).
+ *   key    out: identifies the generated source and compile options (may be NULL)
+ *   dst    NULL: compile if needed and return the size in *bytes; otherwise copy the code
+ *          object into dst (host, *bytes long) and set *bytes to its size
+ * Errors: ABS_ERR_INVALID (dst given before compilation), ABS_ERR_NOMEM (*bytes too
+ * small), ABS_ERR_JIT. */
+abs_status abs_plan_code(abs_plan_t plan, uint64_t* key, void* dst, size_t* bytes);
+
+/* Install a code object obtained from abs_plan_code of an identical plan (same key);
+ * abs_plan_bind then loads it instead of compiling.  The bytes are copied.
+ * Errors: ABS_ERR_INVALID (null, empty or key mismatch). */
+abs_status abs_plan_set_code(abs_plan_t plan, uint64_t key, const void* src, size_t bytes);
+
 /* Attach caller-owned device memory of at least plan_bytes bytes (256-byte aligned)
  * to the plan, upload its tables on `stream` and load the compiled kernel on the
  * current device.  The memory must outlive the plan's use.  Errors: ABS_ERR_INVALID,

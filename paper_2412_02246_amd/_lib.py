@@ -57,6 +57,8 @@ def lib():
         "abs_plan_info_get": [_P, ctypes.POINTER(PlanInfo)],
         "abs_plan_triplets": [_P, _P, _P, _P],
         "abs_plan_compile": [_P],
+        "abs_plan_code": [_P, ctypes.POINTER(ctypes.c_uint64), _P, ctypes.POINTER(sz)],
+        "abs_plan_set_code": [_P, ctypes.c_uint64, _P, sz],
         "abs_plan_bind": [_P, _P, sz, _P],
         "abs_estimate_workspace": [_P, i32, i32, i32, ctypes.POINTER(sz)],
         "abs_grid_workspace": [_P, i64, i32, ctypes.POINTER(sz)],

@@ -98,6 +98,7 @@ namespace abs_impl {
 // plan.cpp
 bool build_jit_source(abs_plan_s* p);
 abs_status compile_jit(abs_plan_s* p);
+uint64_t jit_key(const abs_plan_s* p);
 WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_counts);
 void build_mfma_tables(abs_plan_s* p);
 inline void prof_begin(const abs_plan_s* p, int stage, hipStream_t st) {

@@ -176,8 +176,8 @@ WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_c
 // in registers, and walks its workgroup's pixels with one pixel per lane; the field
 // values of a pixel are loaded once (coalesced across lanes, prefetched one
 // iteration ahead) and every pair product F_i F_j is formed once per pixel.
-// Accumulators are summed across the wave with lane shuffles and written in FP64
-// per workgroup; the finaliser adds workgroups in a fixed order.
+// Accumulators are summed across the wave through LDS in FP64 and written per
+// workgroup; the finaliser adds workgroups in a fixed order.
 // Two kernels are emitted: abs_contract (FP32 fields, FP32 accumulators) and
 // abs_contract64 (FP64 fields and accumulators, for the weight fields).
 namespace {
@@ -220,7 +220,10 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, const char*
                 "  const long long p0 = (long long)blockIdx.x * ppb;\n"
                 "  const long long p1 = (p0 + ppb < npix) ? p0 + ppb : npix;\n"
                 "  double* __restrict__ out = part + (set * nblk + blockIdx.x) * (long long)ntrip;\n"
-                "  switch (grp) {\n", R);
+                "  __shared__ %s red_all[4 * %d * 65];\n"
+                "  %s* red = red_all + wave * %d * 65;\n"
+                "  switch (grp) {\n", R, R, std::strcmp(R, "double") == 0 ? 16 : 32, R,
+                std::strcmp(R, "double") == 0 ? 16 : 32);
   s += buf;
   for (int g = 0; g < G; ++g) {
     const int t0 = start[g], t1 = start[g + 1];
@@ -270,11 +273,24 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, const char*
       s += buf;
     }
     s += "    }\n";
-    // reduce and store one accumulator at a time: keeps the register peak at the loop's
-    for (int t = t0; t < t1; ++t) {
+    // Cross-lane sums through LDS, kRed accumulators at a time: every lane stores its
+    // values as one row per accumulator, then lane l < kRed adds row l in FP64.  One
+    // store per accumulator keeps the generated code (and its compile time) small.
+    const int kRed = std::strcmp(R, "double") == 0 ? 16 : 32;
+    for (int c0 = t0; c0 < t1; c0 += kRed) {
+      const int c1 = std::min(t1, c0 + kRed);
+      for (int t = c0; t < c1; ++t) {
+        std::snprintf(buf, sizeof buf, "    red[%d * 65 + lane] = a%d;\n", t - c0, t - t0);
+        s += buf;
+      }
       std::snprintf(buf, sizeof buf,
-                    "    { const %s v = abs_wsum(a%d); if (lane == 0) out[%d] = (double)v; }\n", R,
-                    t - t0, t);
+                    "    abs_wave_sync();\n"
+                    "    if (lane < %d) {\n"
+                    "      double v = 0.0;\n"
+                    "      for (int q = 0; q < 64; ++q) v += (double)red[lane * 65 + q];\n"
+                    "      out[%d + lane] = v;\n"
+                    "    }\n"
+                    "    abs_wave_sync();\n", c1 - c0, c0);
       s += buf;
     }
     s += "  } break;\n";
@@ -294,13 +310,30 @@ bool build_jit_source(abs_plan_s* p) {
   s += "// generated: triplet contraction for one ring-triplet list\n";
   s += "__device__ __forceinline__ float abs_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }\n"
        "__device__ __forceinline__ double abs_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }\n"
-       "template <typename T> __device__ __forceinline__ T abs_wsum(T v) {\n"
-       "  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);\n  return v;\n}\n";
+       "// orders a wave's LDS stores before its loads from other lanes\n"
+       "__device__ __forceinline__ void abs_wave_sync() {\n"
+       "  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, \"wavefront\");\n"
+       "  __builtin_amdgcn_wave_barrier();\n}\n";
   // the FP32 kernel serves the FP32 data path; the weight fields always use FP64
   if (p->precision == ABS_FP32) emit_kernel(p, g32, "abs_contract", "float", s);
   emit_kernel(p, g64, "abs_contract64", "double", s);
   p->jit_src.swap(s);
   return true;
+}
+
+// FNV-1a of the generated source and the compile options: identifies a code object.
+uint64_t jit_key(const abs_plan_s* p) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const char* d, size_t n) {
+    for (size_t i = 0; i < n; ++i) {
+      h ^= (unsigned char)d[i];
+      h *= 1099511628211ull;
+    }
+  };
+  mix(p->jit_src.data(), p->jit_src.size());
+  const char tag[] = "gfx950 -O3 -packed-fp32-ops";
+  mix(tag, sizeof tag);
+  return h;
 }
 
 abs_status compile_jit(abs_plan_s* p) {
@@ -611,6 +644,32 @@ abs_status abs_plan_triplets(abs_plan_t p, int32_t* ijk, double* labels, double*
 abs_status abs_plan_compile(abs_plan_t p) {
   if (!p) return ABS_ERR_INVALID;
   return compile_jit(p);
+}
+
+abs_status abs_plan_code(abs_plan_t p, uint64_t* key, void* dst, size_t* bytes) {
+  if (!p || !bytes) return ABS_ERR_INVALID;
+  if (key) *key = jit_key(p);
+  if (!dst) {
+    if (!p->compiled) {
+      const abs_status s = compile_jit(p);
+      if (s != ABS_OK) return s;
+    }
+    *bytes = p->jit_code.size();
+    return ABS_OK;
+  }
+  if (!p->compiled) return ABS_ERR_INVALID;
+  if (*bytes < p->jit_code.size()) return ABS_ERR_NOMEM;
+  std::memcpy(dst, p->jit_code.data(), p->jit_code.size());
+  *bytes = p->jit_code.size();
+  return ABS_OK;
+}
+
+abs_status abs_plan_set_code(abs_plan_t p, uint64_t key, const void* src, size_t bytes) {
+  if (!p || !src || bytes == 0) return ABS_ERR_INVALID;
+  if (key != jit_key(p)) return ABS_ERR_INVALID;   // compiled for another triplet list
+  p->jit_code.assign(static_cast<const char*>(src), static_cast<const char*>(src) + bytes);
+  p->compiled = true;
+  return ABS_OK;
 }
 
 abs_status abs_estimate_workspace(abs_plan_t p, int32_t batch, int32_t w_batched,

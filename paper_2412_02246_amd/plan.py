@@ -65,6 +65,21 @@ class Plan:
         L.check(L.lib().abs_plan_compile(self.handle), "abs_plan_compile")
         return self
 
+    def code(self):
+        """(key, bytes) of the compiled contraction code object (compiles if needed)."""
+        key, n = ctypes.c_uint64(), ctypes.c_size_t()
+        L.check(L.lib().abs_plan_code(self.handle, ctypes.byref(key), None, ctypes.byref(n)),
+                "abs_plan_code")
+        buf = ctypes.create_string_buffer(n.value)
+        L.check(L.lib().abs_plan_code(self.handle, None, buf, ctypes.byref(n)), "abs_plan_code")
+        return key.value, buf.raw[:n.value]
+
+    def set_code(self, key, blob):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        L.check(L.lib().abs_plan_set_code(self.handle, ctypes.c_uint64(key), buf, len(blob)),
+                "abs_plan_set_code")
+        return self
+
     def bind(self, device=None, stream=None):
         import torch
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -110,7 +125,7 @@ class Plan:
         return self._work
 
     # -- calls ----------------------------------------------------------------
-    def estimate(self, grids, w=None, w_batched=False, n_given=None, out=None, stream=None):
+    def estimate(self, grids, w=None, w_batched=False, n_given=None, out=None, stream=None, work=None):
         """B (and N) for a batch of gridded visibilities.
 
         grids: torch complex64 / complex128 [batch][n][n] (or [n][n]) on the plan's device
@@ -141,7 +156,10 @@ class Plan:
         if n_given is not None and (n_given.dtype != torch.float64 or n_given.numel() != self.ntrip):
             raise ValueError("n_given must be float64 [ntrip]")
         nbytes = self.estimate_workspace(batch, w_batched, n_given is not None)
-        work = self._workspace(nbytes)
+        if work is None:
+            work = self._workspace(nbytes)
+        elif work.numel() < nbytes:
+            raise ValueError("workspace too small: %d < %d bytes" % (work.numel(), nbytes))
         if out is None:
             B = torch.empty((batch, self.ntrip), dtype=torch.float64, device=grids.device)
             N = torch.empty((batch, self.ntrip), dtype=torch.float64, device=grids.device)
@@ -153,9 +171,10 @@ class Plan:
                 "abs_estimate")
         return B, N
 
-    def counts(self, w=None, stream=None):
+    def counts(self, w=None, stream=None, work=None):
         import torch
-        work = self._workspace(self.estimate_workspace(0))
+        if work is None:
+            work = self._workspace(self.estimate_workspace(0))
         N = torch.empty(self.ntrip, dtype=torch.float64, device=self.device)
         L.check(L.lib().abs_counts(self.handle, _ptr(w), _ptr(work), work.numel(), _ptr(N),
                                    _stream(stream)), "abs_counts")
