@@ -1,7 +1,8 @@
 """Compiling many plans at once.  Run-time compilation is serialised inside one
 process, so the contraction kernels of several plans are compiled in worker
-processes (started with 'spawn', before or independently of any GPU use; they make no
-HIP device call) and installed in the parent's plans with Plan.set_code."""
+processes (started with 'spawn'; they make no HIP device call) and installed in the
+parent's plans with Plan.set_code.  Call it before the parent process first uses the
+GPU."""
 import multiprocessing
 from concurrent.futures import ProcessPoolExecutor
 

@@ -163,7 +163,7 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
         self.free_streams = list(range(slots))
         self.plans = {}
-        self.counts = {}             # weights_key -> (N tensor, event)
+        self.counts = {}             # (plan_key, weights_key) -> (N tensor, event)
         self.jobs = {}
         self._next = 0
 
@@ -177,9 +177,10 @@ class GpuExecutor:
             self.plans[key] = p
         return p
 
-    def prepare(self, keys, workers=8):
-        """Create the plans for these keys, compile their kernels in worker processes,
-        and bind them to the device."""
+    def prepare(self, keys, workers=1):
+        """Create the plans for these keys, compile their kernels (in `workers` worker
+        processes when > 1; start those before this process first uses the GPU), and
+        bind them to the device."""
         from .jit import compile_plans
         from .plan import Plan
         keys = [k for k in dict.fromkeys(keys) if k not in self.plans]
@@ -194,7 +195,7 @@ class GpuExecutor:
         shared = group[0].weights_key is not None
         have_counts = shared
         work = p.estimate_workspace(len(group), w_batched=not shared, have_counts=have_counts)
-        if shared and group[0].weights_key not in self.counts:
+        if shared and (group[0].plan_key, group[0].weights_key) not in self.counts:
             work = max(work, p.estimate_workspace(0))
         n2 = p.n * p.n
         stacked = len(group) * n2 * 8 + (0 if shared else len(group) * n2 * 4)
@@ -215,7 +216,7 @@ class GpuExecutor:
             grids = torch.stack([r.grid for r in group])
             n_given = None
             if shared:
-                key = group[0].weights_key
+                key = (group[0].plan_key, group[0].weights_key)   # counts belong to a plan
                 w = group[0].weights
                 if key not in self.counts:
                     N0 = p.counts(w, work=work)

@@ -35,10 +35,18 @@ def _run(plan, grids, w=None, w_batched=False, dtype=None, n_given=None):
 
 
 def _check(B, N, ref, norm, tol=TOL, label=""):
-    e = oest.relative_error(B, ref, norm)
+    # A triplet whose rings close triangles only through zero-weight cells has an empty
+    # weighted set: N_t = 0 exactly, so both sides hold rounding noise there and B_t is
+    # not defined (any real triangle contributes at least w_min^3 > 0 to N_t).  Such
+    # triplets must be empty on the GPU too; B is compared on the others.
+    empty = np.abs(ref["N"]) <= 1e-9 * np.maximum(ref["rhoN"], 1e-300)
+    assert np.all(np.abs(N[empty]) <= 1e-9 * ref["rhoN"][empty]), label
+    keep = ~empty
+    e = oest.relative_error(B, ref, norm)[keep]
     en = oest.count_error(N, ref)
-    print("%s max e_t %.3g  median %.3g  max e_N %.3g  ntrip %d" % (label, e.max(), np.median(e), en.max(), len(e)), flush=True)
-    assert np.all(np.isfinite(B))
+    print("%s max e_t %.3g  median %.3g  max e_N %.3g  ntrip %d (%d empty)"
+          % (label, e.max(), np.median(e), en.max(), len(B), int(empty.sum())), flush=True)
+    assert np.all(np.isfinite(B[keep]))
     assert e.max() <= tol, (label, e.max(), int(np.argmax(e)))
     assert en.max() <= tol, (label, en.max())
 
