@@ -60,9 +60,15 @@ class HipEvents:
         self.ev = []
 
 
-PEAK_VALU_FP32 = 78.6e12
-PEAK_MFMA_16BIT = 2.5e15   # dense BF16 / FP16 matrix peak   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
+PEAK_VALU_FP32 = 78.6e12   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
+PEAK_MFMA_16BIT = 2.5e15   # dense BF16 / FP16 matrix peak
 PEAK_HBM = 8.0e12
+
+# HBM bytes per launch of the timed contraction kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes scaled by a 1 GiB copy (2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE), for the
+# kernel as it stands in this tree (profiles/counters_mwa1024_batch16.md); a workload or
+# precision without an entry reports null.
+MEASURED_TRAFFIC = {("mwa1024", "fp32"): 2225.4e6}
 
 
 def parse():
@@ -70,7 +76,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mwa1024", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--workload", default="mwa1024", choices=sorted(WORKLOADS) + ["serve", "copy"])
     ap.add_argument("--requests", type=int, default=512, help="serve: number of requests")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serve: admission budget")
     ap.add_argument("--batch", type=int, default=0)
@@ -100,6 +106,21 @@ def cpu_baseline(n, edges, trips, uv, vis, norm, budget_s):
     return {"value": done / dt, "unit": "grids/s", "cores": int(cores), "kind": "oracle",
             "sample": "%d realisation(s): FP64 gridding of %d visibilities + estimator "
                       "(numpy FFT, BLAS %d threads), %.1f s" % (done, len(uv), cores, dt)}
+
+
+def copy_probe(a):
+    """A plain device copy of a known size (1 GiB read + 1 GiB written per launch), run
+    under the same rocprofv3 counters as the kernels to calibrate FETCH_SIZE and
+    WRITE_SIZE against bytes actually moved."""
+    import torch
+    torch.cuda.set_device(0)
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(a.warmup + a.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_per_launch": 2 * src.numel() * 4,
+                      "launches": a.warmup + a.steps}), flush=True)
 
 
 def serve_bench(a):
@@ -203,6 +224,8 @@ def main():
         sys.exit(2)
     if a.workload == "serve":
         return serve_bench(a)
+    if a.workload == "copy":
+        return copy_probe(a)
     import torch
 
     import paper_2412_02246_amd as A
@@ -251,13 +274,15 @@ def main():
     if a.precision == "fp32":
         roof = {"kernel": "abs_contract (plan-specialised FP32 triplet contraction)", "bound": "alu",
                 "achieved": achieved / 1e12, "peak": PEAK_VALU_FP32 / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_VALU_FP32, "traffic": None, "avg_ms": con_ms,
+                "frac": achieved / PEAK_VALU_FP32, "avg_ms": con_ms,
+                "traffic": MEASURED_TRAFFIC.get((a.workload, a.precision)) if batch == W["batch"] else None,
                 "flops_per_launch": flops}
     else:
         issued = float(nsets) * n * n * plan.mfma_tiles * 3 * 512   # 3 split MFMAs per tile
         roof = {"kernel": "mfma_contract_kernel (%s triplet contraction)" % a.precision, "bound": "mfma",
                 "achieved": achieved / 1e12, "peak": PEAK_MFMA_16BIT / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_MFMA_16BIT, "traffic": None, "avg_ms": con_ms,
+                "frac": achieved / PEAK_MFMA_16BIT, "avg_ms": con_ms,
+                "traffic": MEASURED_TRAFFIC.get((a.workload, a.precision)) if batch == W["batch"] else None,
                 "flops_per_launch": flops,
                 "mfma_issued_tflops": issued / (con_ms * 1e-3) / 1e12,
                 "mfma_issued_frac": issued / (con_ms * 1e-3) / PEAK_MFMA_16BIT}
