@@ -194,6 +194,221 @@ __device__ void stockham_fft(typename Cx<R>::T* buf, int n, int log2n, int t, in
   }
 }
 
+// ---------------------------------------------------------------------------------
+// Compile-time-length engine (used by the row pass).  With n fixed every LDS address is
+// the thread's base plus a constant, each thread's twiddles are fixed for the kernel's
+// lifetime (kept in registers when they are few) and the first pass reads its inputs
+// straight from global memory, skipping all-zero slabs of the pruned input.
+template <int LOG2N>
+struct Fft {
+  static constexpr int N = 1 << LOG2N;
+  static constexpr int U = N > 4096 ? 2 : 1;                  // radix-16 butterflies per thread
+  static constexpr int TG = N / 16 / U < kBlock ? N / 16 / U : kBlock;   // threads per transform
+  static constexpr int G = kBlock / TG;                       // transforms per block
+  static constexpr int NP16 = LOG2N / 4, LREST = LOG2N % 4;
+  static constexpr int NPASS = NP16 + (LREST ? 1 : 0);
+  static constexpr int L = N + N / 16;                        // padded LDS elements
+  static constexpr bool WAVE = TG <= 64;                      // one wave holds whole transforms
+  static constexpr int lrp(int p) { return p < NP16 ? 4 : LREST; }
+  static constexpr int nb(int p) { return 16 * U / (1 << lrp(p)); }
+  // twiddles of passes 1 .. p - 1 (pass 0 has none)
+  static constexpr int tw_before(int p) {
+    int c = 0;
+    for (int q = 1; q < p; ++q) c += nb(q) * ((1 << lrp(q)) - 1);
+    return c;
+  }
+  static constexpr int NTW = tw_before(NPASS);
+};
+
+// Orders a transform's LDS traffic between passes: a wave-level fence when one wave
+// holds whole transforms (LDS serves one wave's operations in order), else a barrier.
+template <bool WAVE>
+__device__ __forceinline__ void fft_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Per-thread twiddles: REG keeps all of them in registers, otherwise they are read from
+// the table when used.
+template <typename R, int LOG2N, bool REG>
+struct Twiddles;
+template <typename R, int LOG2N>
+struct Twiddles<R, LOG2N, true> {
+  using T = typename Cx<R>::T;
+  using F = Fft<LOG2N>;
+  T w[F::NTW > 0 ? F::NTW : 1];
+  __device__ __forceinline__ void load(const T* __restrict__ tw, int t) {
+    load_from<1>(tw, t);
+  }
+  template <int P>
+  __device__ __forceinline__ void load_from(const T* __restrict__ tw, int t) {
+    if constexpr (P < F::NPASS) {
+      constexpr int LRP = F::lrp(P), RP = 1 << LRP, LNS = 4 * P, SH = LOG2N - LNS - LRP;
+#pragma unroll
+      for (int j = 0; j < F::nb(P); ++j) {
+        const int m = (t + F::TG * j) & ((1 << LNS) - 1);
+#pragma unroll
+        for (int r = 1; r < RP; ++r) w[F::tw_before(P) + j * (RP - 1) + r - 1] = tw[(r * m) << SH];
+      }
+      load_from<P + 1>(tw, t);
+    }
+  }
+  template <int P>
+  __device__ __forceinline__ T get(const T* __restrict__, int, int j, int r) const {
+    return w[F::tw_before(P) + j * ((1 << F::lrp(P)) - 1) + r - 1];
+  }
+};
+template <typename R, int LOG2N>
+struct Twiddles<R, LOG2N, false> {
+  using T = typename Cx<R>::T;
+  using F = Fft<LOG2N>;
+  __device__ __forceinline__ void load(const T* __restrict__, int) {}
+  template <int P>
+  __device__ __forceinline__ T get(const T* __restrict__ tw, int t, int j, int r) const {
+    constexpr int LRP = F::lrp(P), LNS = 4 * P, SH = LOG2N - LNS - LRP;
+    const int m = (t + F::TG * j) & ((1 << LNS) - 1);
+    return tw[(r * m) << SH];
+  }
+};
+
+// Pass P of the length-2^LOG2N transform held by thread t of its TG threads.  Pass 0
+// takes its inputs from in(k) (natural order, any memory); the last pass hands its
+// outputs to out(k, value); passes in between read and write the padded LDS buffer.
+template <typename R, int LOG2N, int P, class TW, class In, class Out>
+__device__ __forceinline__ void fft_pass(typename Cx<R>::T* buf, int t, const typename Cx<R>::T* __restrict__ tw,
+                                         const TW& twr, In& in, Out& out) {
+  using T = typename Cx<R>::T;
+  using F = Fft<LOG2N>;
+  constexpr int LRP = F::lrp(P), RP = 1 << LRP, NB = F::nb(P);
+  constexpr int LNS = 4 * P, NS = 1 << LNS, STRIDE = F::N / RP;
+  constexpr bool FIRST = P == 0, LAST = P == F::NPASS - 1;
+  T v[NB][RP];
+  if constexpr (FIRST) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < RP; ++r) v[j][r] = in(t + F::TG * j + r * STRIDE, r);
+  } else {
+    static_assert(STRIDE % 16 == 0, "padded reads need a stride that is a multiple of 16");
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int lb = lpad(t + F::TG * j);
+#pragma unroll
+      for (int r = 0; r < RP; ++r) v[j][r] = buf[lb + r * (STRIDE + STRIDE / 16)];
+    }
+    if constexpr (!LAST) fft_sync<F::WAVE>();   // every read of this pass precedes every write
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if constexpr (!FIRST) {
+#pragma unroll
+      for (int r = 1; r < RP; ++r) v[j][r] = cmul(v[j][r], twr.template get<P>(tw, t, j, r));
+    }
+    dft<R, RP>(v[j]);
+    const int b = t + F::TG * j;
+    const int idxD = ((b >> LNS) << (LNS + LRP)) + (b & (NS - 1));
+    if constexpr (LAST) {
+#pragma unroll
+      for (int q = 0; q < RP; ++q) out(idxD + q * NS, v[j][q]);
+    } else if constexpr (FIRST) {
+      // k = 16 b + q: lpad(k) = 17 b + q
+#pragma unroll
+      for (int q = 0; q < RP; ++q) buf[17 * b + q] = v[j][q];
+    } else {
+      const int lb = lpad(idxD);
+#pragma unroll
+      for (int q = 0; q < RP; ++q) buf[lb + q * (NS + NS / 16)] = v[j][q];
+    }
+  }
+  if constexpr (!LAST) fft_sync<F::WAVE>();
+}
+
+template <typename R, int LOG2N, int P, class TW, class In, class Out>
+__device__ __forceinline__ void fft_passes(typename Cx<R>::T* buf, int t, const typename Cx<R>::T* __restrict__ tw,
+                                           const TW& twr, In& in, Out& out) {
+  fft_pass<R, LOG2N, P>(buf, t, tw, twr, in, out);
+  if constexpr (P + 1 < Fft<LOG2N>::NPASS) fft_passes<R, LOG2N, P + 1>(buf, t, tw, twr, in, out);
+}
+
+// Row pass with the compile-time engine.  blockIdx.x = ring m * blocks per ring + block,
+// each block covering G * iters row pairs; blockIdx.y = set.  FMAX records the largest
+// |F| per (set, ring) for the FP16 split form.
+template <typename R, int LOG2N, bool FMAX>
+__global__ void __launch_bounds__(kBlock)
+rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename Cx<R>::T* __restrict__ tw,
+                     const typename Cx<R>::T* __restrict__ Z, long long zset, R* __restrict__ F,
+                     long long fset, unsigned* __restrict__ fmax_bits, int nb) {
+  using T = typename Cx<R>::T;
+  using FF = Fft<LOG2N>;
+  constexpr int n = FF::N;
+  constexpr bool REG = sizeof(R) == 4 && FF::NTW <= 32;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int g = threadIdx.x / FF::TG, t = threadIdx.x - g * FF::TG;
+  T* buf = reinterpret_cast<T*>(lds_raw) + g * FF::L;
+  const int per_block = FF::G * iters;
+  const int nrb = (n / 2 + per_block - 1) / per_block;
+  const int m = blockIdx.x / nrb, blk = blockIdx.x - m * nrb;
+  const int set = blockIdx.y;
+  const BinDev bin = bins[m];
+  const int H = bin.h, cols = bin.cols;
+  R* __restrict__ fs = F + (long long)set * fset + (long long)m * n * n;
+  const T* __restrict__ zs = Z + (long long)set * zset + bin.zoff;
+  Twiddles<R, LOG2N, REG> twr;
+  twr.load(tw, t);
+  R vmax = R(0);
+  for (int it = 0; it < iters; ++it) {
+    const int pair = blk * per_block + it * FF::G + g;
+    const bool active = pair < n / 2;
+    const int ya = 2 * (active ? pair : 0);
+    R* __restrict__ row0 = fs + (long long)ya * n;
+    R* __restrict__ row1 = row0 + n;
+    auto out = [&](int k, T v) {
+      if (active) {
+        row0[k] = v.x;
+        row1[k] = v.y;
+        if constexpr (FMAX) vmax = fmax(vmax, fmax(fabs(v.x), fabs(v.y)));
+      }
+    };
+    if (cols == 0) {   // ring without lattice cells: its field is zero
+      for (int k = t; k < n; k += FF::TG) out(k, Cx<R>::mk(R(0), R(0)));
+      continue;
+    }
+    // input k of the row pair: Z(gx, ya) + i Z(gx, ya + 1) at gx = k (k <= H) or
+    // gx = k - n (k >= n - H), using Z(-gx, y) = conj Z(gx, y); zero elsewhere.  Slab r
+    // of the first pass covers k in [r n/16, (r + 1) n/16).
+    const T* __restrict__ za = zs + (long long)ya * cols;
+    const T* __restrict__ zb = za + cols;
+    auto in = [&](int k, int r) -> T {
+      constexpr int S = n / 16;
+      const bool lo_slab = r * S <= H, hi_slab = (r + 1) * S - 1 >= n - H;
+      T x = Cx<R>::mk(R(0), R(0));
+      if (active && (lo_slab || hi_slab)) {
+        if (k <= H) {
+          const T a = za[k], b = zb[k];
+          x = Cx<R>::mk(a.x - b.y, a.y + b.x);
+        } else if (k >= n - H) {
+          const T a = za[n - k], b = zb[n - k];
+          x = Cx<R>::mk(a.x + b.y, -a.y + b.x);
+        }
+      }
+      return x;
+    };
+    fft_sync<FF::WAVE>();   // the previous transform's last reads are done
+    fft_passes<R, LOG2N, 0>(buf, t, tw, twr, in, out);
+  }
+  if constexpr (FMAX) {
+    float v = (float)vmax;
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    // non-negative floats order like their bit patterns
+    if ((threadIdx.x & 63) == 0) atomicMax(&fmax_bits[(long long)set * nb + m], __float_as_uint(v));
+  }
+}
+
 // Weight W(g) of one cell for the plan's weight mode (Sec. 2, after Eq. 10).
 template <typename R>
 __device__ __forceinline__ R weight_of(const float* __restrict__ w, int wmode, long long idx) {
@@ -279,74 +494,6 @@ colpass_kernel(const GT* __restrict__ grids, const float* __restrict__ w, int w_
   stockham_fft<R, U>(buf, n, log2n, t, geo.Tg, tw, out);
 }
 
-// Row pass: one transform per (ring, row pair); blockIdx.x = ring m * blocks per ring +
-// block, each block covering G * iters row pairs; blockIdx.y = set.
-template <typename R, int U>
-__global__ void __launch_bounds__(kBlock)
-rowpass_kernel(int n, int log2n, int iters, const BinDev* __restrict__ bins,
-               const typename Cx<R>::T* __restrict__ tw, const typename Cx<R>::T* __restrict__ Z,
-               long long zset, R* __restrict__ F, long long fset, unsigned* __restrict__ fmax_bits,
-               int nb) {
-  using T = typename Cx<R>::T;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  const FftGeom geo = fft_geom(n);
-  const int g = threadIdx.x / geo.Tg, t = threadIdx.x - g * geo.Tg;
-  T* buf = reinterpret_cast<T*>(lds_raw) + g * fft_lds_elems(n);
-  const int per_block = geo.G * iters;
-  const int nrb = (n / 2 + per_block - 1) / per_block;
-  const int m = blockIdx.x / nrb, blk = blockIdx.x - m * nrb;
-  const int set = blockIdx.y;
-  const BinDev bin = bins[m];
-  const int H = bin.h, cols = bin.cols;
-  const long long nn = (long long)n * n;
-  R* __restrict__ fs = F + (long long)set * fset + (long long)m * nn;
-  const T* __restrict__ zs = Z + (long long)set * zset + bin.zoff;
-  T* lds = reinterpret_cast<T*>(lds_raw);
-  const int L = fft_lds_elems(n);
-  const int span = 2 * H + 1;
-  R vmax = R(0);   // largest |F| written by this thread (recorded when fmax_bits is given)
-  for (int it = 0; it < iters; ++it) {
-    const int pair0 = blk * per_block + it * geo.G;
-    const int pair = pair0 + g;
-    const bool active = pair < n / 2;
-    const int ya = 2 * (active ? pair : 0);
-    auto out = [&](int k, T v) {
-      if (active) {
-        fs[(long long)ya * n + k] = v.x;
-        fs[(long long)(ya + 1) * n + k] = v.y;
-        vmax = fmax(vmax, fmax(fabs(v.x), fabs(v.y)));
-      }
-    };
-    if (cols == 0) {   // ring without lattice cells: its field is zero
-      for (int k = t; k < n; k += geo.Tg) out(k, Cx<R>::mk(R(0), R(0)));
-      continue;
-    }
-    for (int q = threadIdx.x; q < geo.G * L; q += blockDim.x) lds[q] = Cx<R>::mk(R(0), R(0));
-    __syncthreads();
-    // stage Z(., ya) + i Z(., ya + 1) over gx in [-H, H] (Z(-gx, y) = conj Z(gx, y))
-    const int npair = min(geo.G, n / 2 - pair0);
-    for (int q = threadIdx.x; q < npair * span; q += blockDim.x) {
-      const int gg = q / span;
-      const int gx = q - gg * span - H;
-      const int y0 = 2 * (pair0 + gg);
-      const int agx = gx < 0 ? -gx : gx;
-      const T za = zs[(long long)y0 * cols + agx];
-      const T zb = zs[(long long)(y0 + 1) * cols + agx];
-      lds[gg * L + lpad(gx < 0 ? gx + n : gx)] =
-          gx < 0 ? Cx<R>::mk(za.x + zb.y, -za.y + zb.x) : Cx<R>::mk(za.x - zb.y, za.y + zb.x);
-    }
-    __syncthreads();
-    stockham_fft<R, U>(buf, n, log2n, t, geo.Tg, tw, out);
-    __syncthreads();   // the staging area is refilled by the next iteration
-  }
-  if (fmax_bits) {
-    float v = (float)vmax;
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    // non-negative floats order like their bit patterns
-    if ((threadIdx.x & 63) == 0) atomicMax(&fmax_bits[(long long)set * nb + m], __float_as_uint(v));
-  }
-}
-
 namespace {
 template <typename K>
 hipError_t allow_lds(K kernel, size_t bytes) {
@@ -402,6 +549,33 @@ hipError_t launch_colpass_weight(const abs_plan_s* p, const float* w, int w_batc
   return launch_colpass<double, false, float2>(p, nullptr, w, w_batched, nsets, Z, zset, tiles, tw, st);
 }
 
+template <typename R, int LOG2N>
+hipError_t launch_rowpass_n(const abs_plan_s* p, int nsets, const typename Cx<R>::T* Z, long long zset,
+                            R* F, long long fset, unsigned* fmax_bits, const BinDev* bins,
+                            const typename Cx<R>::T* tw, hipStream_t st) {
+  using FF = Fft<LOG2N>;
+  const int iters = std::max(1, std::min(kRowIters, FF::N / 2 / FF::G));
+  const int per_block = FF::G * iters;
+  const int nrb = (FF::N / 2 + per_block - 1) / per_block;
+  const dim3 grid((unsigned)(p->nb * nrb), (unsigned)nsets);
+  const size_t lds = (size_t)FF::G * FF::L * sizeof(typename Cx<R>::T);
+  hipError_t e;
+  if constexpr (sizeof(R) == 4) {
+    if (fmax_bits) {   // FP16 split form: largest |F| per (set, ring)
+      auto k = rowpass_fixed_kernel<R, LOG2N, true>;
+      if ((e = allow_lds(k, lds)) != hipSuccess) return e;
+      k<<<grid, kBlock, lds, st>>>(iters, bins, tw, Z, zset, F, fset, fmax_bits, p->nb);
+      return hipGetLastError();
+    }
+  }
+  {
+    auto k = rowpass_fixed_kernel<R, LOG2N, false>;
+    if ((e = allow_lds(k, lds)) != hipSuccess) return e;
+    k<<<grid, kBlock, lds, st>>>(iters, bins, tw, Z, zset, F, fset, nullptr, p->nb);
+  }
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_rowpass(const abs_plan_s* p, int nsets, const typename Cx<R>::T* Z,
                           long long zset, R* F, long long fset, unsigned* fmax_bits, hipStream_t st) {
@@ -409,24 +583,14 @@ hipError_t launch_rowpass(const abs_plan_s* p, int nsets, const typename Cx<R>::
   const BinDev* bins = reinterpret_cast<const BinDev*>(base + p->dl.bins);
   const bool f64 = sizeof(R) == 8;
   const auto* tw = reinterpret_cast<const typename Cx<R>::T*>(base + (f64 ? p->dl.tw64 : p->dl.tw));
-  const FftGeom geo = fft_geom(p->n);
-  const int iters = std::max(1, std::min(kRowIters, p->n / 2 / geo.G));
-  const int per_block = geo.G * iters;
-  const int nrb = (p->n / 2 + per_block - 1) / per_block;
-  const dim3 grid((unsigned)(p->nb * nrb), (unsigned)nsets);
-  const size_t lds = (size_t)geo.G * fft_lds_elems(p->n) * sizeof(typename Cx<R>::T);
-  if (p->n > 4096) {
-    auto k = rowpass_kernel<R, 2>;
-    hipError_t e = allow_lds(k, lds);
-    if (e != hipSuccess) return e;
-    k<<<grid, kBlock, lds, st>>>(p->n, p->log2n, iters, bins, tw, Z, zset, F, fset, fmax_bits, p->nb);
-  } else {
-    auto k = rowpass_kernel<R, 1>;
-    hipError_t e = allow_lds(k, lds);
-    if (e != hipSuccess) return e;
-    k<<<grid, kBlock, lds, st>>>(p->n, p->log2n, iters, bins, tw, Z, zset, F, fset, fmax_bits, p->nb);
+  switch (p->log2n) {
+#define ABS_ROW_CASE(L) \
+  case L: return launch_rowpass_n<R, L>(p, nsets, Z, zset, F, fset, fmax_bits, bins, tw, st);
+    ABS_ROW_CASE(4) ABS_ROW_CASE(5) ABS_ROW_CASE(6) ABS_ROW_CASE(7) ABS_ROW_CASE(8)
+    ABS_ROW_CASE(9) ABS_ROW_CASE(10) ABS_ROW_CASE(11) ABS_ROW_CASE(12) ABS_ROW_CASE(13)
+#undef ABS_ROW_CASE
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_rowpass_f32(const abs_plan_s* p, int nsets, const float2* Z, long long zset,

@@ -9,12 +9,14 @@
 // contributions: no floating-point atomics, and the sums are accumulated as 64-bit
 // fixed-point integers with a power-of-two scale, so the result is independent of
 // the order inside each cell (bitwise reproducible).
-//   prep:    nearest cell per visibility, per-cell counts, largest |w V| and w, and a
-//            realisation-minor copy of the values (one 8*batch-byte record per baseline)
+//   prep:    nearest cell per visibility, per-cell counts, largest w
 //   scan:    exclusive prefix sum of the counts (three kernels)
-//   fill:    visibility indices into per-cell lists
-//   gather:  one thread per cell sums its list and the list of its mirror cell
-//            (7 x 7 neighbouring lists for the Gaussian kernel) and writes FP32.
+//   fill:    every visibility's values for all realisations copied, as one record of
+//            8*batch bytes, to its slot in cell order (and its index, when weights or
+//            the Gaussian kernel need it); largest |w V|
+//   gather:  one thread per cell streams the records of its cell and of its mirror
+//            cell (7 x 7 neighbouring cells for the Gaussian kernel), 16 realisations
+//            per pass, and writes FP32.
 #include <algorithm>
 
 #include "abs_internal.h"
@@ -25,10 +27,12 @@ struct GridScalars {
   unsigned int vmax_bits;   // largest |w V| component over all realisations (float bits)
   unsigned int wmax_bits;   // largest w
   unsigned long long dropped;
+  int maxcnt;               // most visibilities with one nearest cell
 };
 
 constexpr int kScanItems = 16;                    // per thread
 constexpr int kScanTile = kBlock * kScanItems;    // per block
+constexpr int kRec = 16;                          // realisations per fill / gather pass
 
 __global__ void __launch_bounds__(kBlock)
 grid_clear_kernel(int* __restrict__ cnt, long long ncnt, GridScalars* sc) {
@@ -38,6 +42,7 @@ grid_clear_kernel(int* __restrict__ cnt, long long ncnt, GridScalars* sc) {
     sc->vmax_bits = 0u;
     sc->wmax_bits = 0u;
     sc->dropped = 0ull;
+    sc->maxcnt = 0;
   }
 }
 
@@ -63,10 +68,10 @@ __device__ __forceinline__ int nearest_cell(double2 U, double du, int n) {
 }
 
 __global__ void __launch_bounds__(kBlock)
-grid_prep_kernel(int n, double du, long long nvis, int batch, const double2* __restrict__ uv,
-                 const float2* __restrict__ vis, const float* __restrict__ vw, int* __restrict__ cell,
-                 int* __restrict__ cnt, float2* __restrict__ visT, GridScalars* sc) {
-  float vm = 0.f, wm = 0.f;
+grid_prep_kernel(int n, double du, long long nvis, const double2* __restrict__ uv,
+                 const float* __restrict__ vw, int* __restrict__ cell, int* __restrict__ cnt,
+                 GridScalars* sc) {
+  float wm = 0.f;
   unsigned long long ndrop = 0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nvis; i += stride) {
@@ -77,23 +82,13 @@ grid_prep_kernel(int n, double du, long long nvis, int batch, const double2* __r
       continue;
     }
     atomicAdd(&cnt[c], 1);
-    const float wi = vw ? vw[i] : 1.0f;
-    wm = fmaxf(wm, fabsf(wi));
-    for (int b = 0; b < batch; ++b) {
-      const float2 v = vis[(long long)b * nvis + i];
-      visT[i * batch + b] = v;
-      vm = fmaxf(vm, fabsf(wi) * fmaxf(fabsf(v.x), fabsf(v.y)));
-    }
+    wm = fmaxf(wm, fabsf(vw ? vw[i] : 1.0f));
   }
-  vm = block_max(vm);
   wm = block_max(wm);
   for (int o = 32; o > 0; o >>= 1) ndrop += __shfl_xor(ndrop, o);
   if ((threadIdx.x & 63) == 0 && ndrop) atomicAdd(&sc->dropped, ndrop);
-  if (threadIdx.x == 0) {
-    // non-negative floats order like their bit patterns
-    atomicMax(&sc->vmax_bits, __float_as_uint(vm));
-    atomicMax(&sc->wmax_bits, __float_as_uint(wm));
-  }
+  // non-negative floats order like their bit patterns
+  if (threadIdx.x == 0) atomicMax(&sc->wmax_bits, __float_as_uint(wm));
 }
 
 // Exclusive scan of cnt[0 .. ncells) into start[0 .. ncells], in three launches.
@@ -119,7 +114,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
 
 __global__ void __launch_bounds__(kBlock)
 scan_tiles_kernel(const int* __restrict__ cnt, long long ncells, int* __restrict__ start,
-                  int* __restrict__ tile_sum) {
+                  int* __restrict__ tile_sum, GridScalars* sc) {
   const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
   int v[kScanItems];
   int s = 0;
@@ -130,12 +125,16 @@ scan_tiles_kernel(const int* __restrict__ cnt, long long ncells, int* __restrict
   }
   int total;
   int run = block_exclusive_scan(s, &total);
+  int mx = 0;
   for (int k = 0; k < kScanItems; ++k) {
     const long long i = base + k;
     if (i < ncells) start[i] = run;
     run += v[k];
+    mx = max(mx, v[k]);
   }
   if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
+  if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(&sc->maxcnt, mx);
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -163,57 +162,108 @@ scan_add_kernel(int* __restrict__ start, long long ncells, const int* __restrict
   }
 }
 
+// One workgroup per kBlock consecutive visibilities.  Each visibility claims a slot in
+// its cell's run of the sorted order; the realisations' values are then copied into
+// cell-sorted records sorted[pos * batch + b] through LDS, kRec realisations at a time,
+// so that consecutive lanes store consecutive values of whole records (a batch of 16
+// fills one 128-byte line per record).  Also finds the largest |w V| component.
 __global__ void __launch_bounds__(kBlock)
-grid_fill_kernel(long long nvis, const int* __restrict__ cell, const int* __restrict__ start,
-                 int* __restrict__ cnt, int* __restrict__ list) {
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nvis; i += stride) {
+grid_fill_kernel(long long nvis, int batch, const int* __restrict__ cell,
+                 const int* __restrict__ start, int* __restrict__ cnt,
+                 const float2* __restrict__ vis, const float* __restrict__ vw,
+                 int* __restrict__ list, float2* __restrict__ sorted, GridScalars* sc) {
+  __shared__ float2 tile[kRec][kBlock + 1];
+  __shared__ int posl[kBlock];
+  const long long i0 = (long long)blockIdx.x * kBlock;
+  const long long i = i0 + threadIdx.x;
+  int pos = -1;
+  float wa = 0.f;
+  if (i < nvis) {
     const int c = cell[i];
-    if (c < 0) continue;
-    const int slot = atomicSub(&cnt[c], 1) - 1;   // counts run down to zero
-    list[start[c] + slot] = (int)i;
+    if (c >= 0) {
+      pos = start[c] + atomicSub(&cnt[c], 1) - 1;   // counts run down to zero
+      wa = fabsf(vw ? vw[i] : 1.0f);
+      if (list) list[pos] = (int)i;
+    }
   }
+  posl[threadIdx.x] = pos;
+  const int nrow = (int)(nvis - i0 < kBlock ? nvis - i0 : kBlock);
+  float vm = 0.f;
+  for (int b0 = 0; b0 < batch; b0 += kRec) {
+    const int nbc = min(kRec, batch - b0);
+    __syncthreads();   // posl written; the previous chunk's tile consumed
+    for (int bb = 0; bb < nbc; ++bb) {
+      float2 v = make_float2(0.f, 0.f);
+      if (i < nvis) v = vis[(long long)(b0 + bb) * nvis + i];
+      if (pos >= 0) vm = fmaxf(vm, wa * fmaxf(fabsf(v.x), fabsf(v.y)));
+      tile[bb][threadIdx.x] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nrow * nbc; e += kBlock) {
+      const int r = e / nbc, bb = e - r * nbc;
+      const int pr = posl[r];
+      if (pr >= 0) sorted[(long long)pr * batch + b0 + bb] = tile[bb][r];
+    }
+  }
+  vm = block_max(vm);
+  if (threadIdx.x == 0) atomicMax(&sc->vmax_bits, __float_as_uint(vm));
 }
 
-// Power-of-two scale 2^E such that 2 * nvis contributions of magnitude <= maxval fit
-// in 62 bits (each visibility reaches a cell at most twice: directly and mirrored).
-__device__ __forceinline__ double fixed_scale(float maxval, long long nvis) {
+// Sums are formed in fixed point held in FP64: every term is rounded to an integer
+// multiple of 2^-E (E from a power-of-two scale) and the running sums stay below 2^52
+// in magnitude, so every addition is exact and the sum does not depend on the order of
+// its terms (bitwise reproducible).  Terms are at most maxval in size and a cell adds at
+// most `terms` of them.
+__device__ __forceinline__ double fixed_scale(float maxval, long long terms) {
   if (!(maxval > 0.f)) return 1.0;
   int e;
   (void)frexpf(maxval, &e);               // maxval < 2^e
   int lg = 0;
-  while ((1ll << lg) < 2 * (nvis > 0 ? nvis : 1)) ++lg;
-  return ldexp(1.0, 61 - e - lg);
+  while ((1ll << lg) < (terms > 0 ? terms : 1)) ++lg;
+  return ldexp(1.0, 51 - e - lg);
 }
 
-__device__ __forceinline__ long long fx(double v, double s) { return llrint(v * s); }
-
-// One thread per cell (iy, ix): sums the visibilities whose nearest cell is within
-// R cells of it, directly (V) and through the mirror (conj V).  B is the compile-time
-// batch chunk held in registers; `b0` selects the chunk.
-template <int R, int B>
+// LPC lanes per cell (iy, ix), lane q holding realisations b0 + 2q and b0 + 2q + 1: sums
+// the visibilities whose nearest cell is within R cells of it, directly (V) and through
+// the mirror (conj V).  The records of one source cell are contiguous in `sorted`
+// (VEC: one 16-byte load per record and lane, batch even).  Lane 0 of each cell also
+// sums the weights when b0 == 0.
+template <int R, int LPC, bool VEC>
 __global__ void __launch_bounds__(kBlock)
-grid_gather_kernel(int n, double du, double pit2, long long nvis, int batch, int b0,
-                   const double2* __restrict__ uv, const float2* __restrict__ visT,
+grid_gather_kernel(int n, double du, double pit2, int batch, int b0,
+                   const double2* __restrict__ uv, const float2* __restrict__ sorted,
                    const float* __restrict__ vw, const int* __restrict__ start,
                    const int* __restrict__ list, int integer_counts, const GridScalars* sc,
                    float2* __restrict__ grid, float* __restrict__ wsum) {
   const long long nn = (long long)n * n;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long c = gt / LPC;
+  const int q = (int)(gt - c * LPC);
   if (c >= nn) return;
   const int iy = (int)(c / n), ix = (int)(c - (long long)iy * n);
   const int gy = iy < n / 2 ? iy : iy - n, gx = ix < n / 2 ? ix : ix - n;
-  const double sv = fixed_scale(__uint_as_float(sc->vmax_bits), nvis);
-  const double sw = integer_counts ? 1.0 : fixed_scale(__uint_as_float(sc->wmax_bits), nvis);
-  const int nb = min(B, batch - b0);
-  long long ar[B], ai[B];
-#pragma unroll
-  for (int b = 0; b < B; ++b) ar[b] = ai[b] = 0;
-  long long aw = 0;
-  const bool want_w = wsum != nullptr && b0 == 0;
+  // a cell adds at most 2 (2R + 1)^2 maxcnt terms, each with kernel weight <= 1
+  const long long terms = 2ll * (2 * R + 1) * (2 * R + 1) * (long long)sc->maxcnt;
+  const double sv = fixed_scale(__uint_as_float(sc->vmax_bits), terms);
+  const double sw = integer_counts ? 1.0 : fixed_scale(__uint_as_float(sc->wmax_bits), terms);
+  const int bq = b0 + 2 * q;                 // this lane's first realisation
+  const bool has0 = bq < batch, has1 = bq + 1 < batch;
+  double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0, aw = 0.0;
+  const bool want_w = wsum != nullptr && b0 == 0 && q == 0;
   const int half = n / 2;
+  auto load = [&](int p) -> float4 {
+    const float2* rec = sorted + (long long)p * batch + bq;
+    if constexpr (VEC) {
+      return has0 ? *reinterpret_cast<const float4*>(rec) : make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      const float2 a = has0 ? rec[0] : make_float2(0.f, 0.f);
+      const float2 b = has1 ? rec[1] : make_float2(0.f, 0.f);
+      return make_float4(a.x, a.y, b.x, b.y);
+    }
+  };
   if (gx > -half && gy > -half) {   // cells of the row / column -n/2 receive nothing
     for (int mir = 0; mir < 2; ++mir) {
+      const double sgn = mir ? -1.0 : 1.0;
       for (int dy = -R; dy <= R; ++dy)
         for (int dx = -R; dx <= R; ++dx) {
           // source cell s: direct pass s = g + d, mirrored pass s = -g + d
@@ -221,36 +271,36 @@ grid_gather_kernel(int n, double du, double pit2, long long nvis, int batch, int
           if (!(sx > -half && sx < half && sy > -half && sy < half)) continue;
           const int sc_idx = (sy < 0 ? sy + n : sy) * n + (sx < 0 ? sx + n : sx);
           const int p0 = start[sc_idx], p1 = start[sc_idx + 1];
+          float4 nxt = p0 < p1 ? load(p0) : make_float4(0.f, 0.f, 0.f, 0.f);
           for (int p = p0; p < p1; ++p) {
-            const int i = list[p];
-            double kw = 1.0;
-            if (R > 0) {
-              const double2 U = uv[i];
-              // the contribution sits at the cell g (direct) or at -g (mirrored)
-              const double ex = (mir ? -(double)gx : (double)gx) * du - U.x;
-              const double ey = (mir ? -(double)gy : (double)gy) * du - U.y;
-              kw = exp(-pit2 * (ex * ex + ey * ey));
-            }
-            const double cw = kw * (double)(vw ? vw[i] : 1.0f);
-            if (want_w) aw += fx(cw, sw);
-            const float2* vr = visT + (long long)i * batch + b0;
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-              if (b < nb) {
-                const float2 v = vr[b];
-                ar[b] += fx(cw * (double)v.x, sv);
-                ai[b] += mir ? -fx(cw * (double)v.y, sv) : fx(cw * (double)v.y, sv);
+            const float4 v = nxt;
+            if (p + 1 < p1) nxt = load(p + 1);   // next record in flight while this one adds
+            double cw = 1.0;
+            if (R > 0 || vw) {
+              const int i = list[p];
+              if (R > 0) {
+                const double2 U = uv[i];
+                // the contribution sits at the cell g (direct) or at -g (mirrored)
+                const double ex = (mir ? -(double)gx : (double)gx) * du - U.x;
+                const double ey = (mir ? -(double)gy : (double)gy) * du - U.y;
+                cw = exp(-pit2 * (ex * ex + ey * ey));
               }
+              if (vw) cw *= (double)vw[i];
             }
+            if (want_w) aw += rint(cw * sw);
+            const double f = cw * sv;
+            ar0 += rint((double)v.x * f);
+            ai0 += sgn * rint((double)v.y * f);
+            ar1 += rint((double)v.z * f);
+            ai1 += sgn * rint((double)v.w * f);
           }
         }
     }
   }
   const double iv = 1.0 / sv;  // a power of two: exact
-#pragma unroll
-  for (int b = 0; b < B; ++b)
-    if (b < nb) grid[(long long)(b0 + b) * nn + c] = make_float2((float)((double)ar[b] * iv), (float)((double)ai[b] * iv));
-  if (want_w) wsum[c] = (float)((double)aw / sw);
+  if (has0) grid[(long long)bq * nn + c] = make_float2((float)(ar0 * iv), (float)(ai0 * iv));
+  if (has1) grid[(long long)(bq + 1) * nn + c] = make_float2((float)(ar1 * iv), (float)(ai1 * iv));
+  if (want_w) wsum[c] = (float)(aw / sw);
 }
 
 __global__ void grid_dropped_kernel(const GridScalars* sc, long long* dropped) {
@@ -258,7 +308,7 @@ __global__ void grid_dropped_kernel(const GridScalars* sc, long long* dropped) {
 }
 
 struct GridWork {
-  size_t sc, cell, cnt, start, tiles, list, visT, total;
+  size_t sc, cell, cnt, start, tiles, list, sorted, total;
 };
 
 GridWork grid_layout(long long n, long long nvis, int batch) {
@@ -279,7 +329,7 @@ GridWork grid_layout(long long n, long long nvis, int batch) {
   off = al(off + (size_t)ntiles * 4);
   g.list = off;
   off = al(off + (size_t)nvis * 4);
-  g.visT = off;
+  g.sorted = off;
   off = al(off + (size_t)nvis * batch * 8);
   g.total = off;
   return g;
@@ -318,36 +368,51 @@ extern "C" abs_status abs_grid(abs_plan_t p, int64_t nvis, int32_t batch, const 
   int* start = reinterpret_cast<int*>(wk + gl.start);
   int* tsum = reinterpret_cast<int*>(wk + gl.tiles);
   int* list = reinterpret_cast<int*>(wk + gl.list);
-  float2* visT = reinterpret_cast<float2*>(wk + gl.visT);
+  float2* sorted = reinterpret_cast<float2*>(wk + gl.sorted);
   const long long cells = (long long)p->n * p->n;
   const int ntiles = (int)((cells + kScanTile - 1) / kScanTile);
   const int integer_counts = (vis_w == nullptr && kernel == ABS_NEAREST) ? 1 : 0;
   const double pi = 3.14159265358979323846;
   const double pit2 = pi * pi * p->theta0 * p->theta0;
   const double2* uvd = reinterpret_cast<const double2*>(uv);
+  // the original index of each sorted entry is needed for per-visibility weights and
+  // for the Gaussian kernel's distances
+  int* lst = (vis_w != nullptr || kernel == ABS_GAUSS7) ? list : nullptr;
   (void)hipGetLastError();
   prof_begin(p, ABS_STAGE_GRID, st);
   grid_clear_kernel<<<1024, kBlock, 0, st>>>(cnt, cells, sc);
   const unsigned gv = (unsigned)std::min<long long>(8192, std::max<long long>(1, (nvis + kBlock - 1) / kBlock));
-  if (nvis > 0)
-    grid_prep_kernel<<<gv, kBlock, 0, st>>>(p->n, p->du, nvis, batch, uvd,
-                                            reinterpret_cast<const float2*>(vis), vis_w, cell, cnt,
-                                            visT, sc);
-  scan_tiles_kernel<<<ntiles, kBlock, 0, st>>>(cnt, cells, start, tsum);
+  if (nvis > 0) grid_prep_kernel<<<gv, kBlock, 0, st>>>(p->n, p->du, nvis, uvd, vis_w, cell, cnt, sc);
+  scan_tiles_kernel<<<ntiles, kBlock, 0, st>>>(cnt, cells, start, tsum, sc);
   scan_sums_kernel<<<1, kBlock, 0, st>>>(tsum, ntiles, start, cells);
   scan_add_kernel<<<ntiles, kBlock, 0, st>>>(start, cells, tsum);
-  if (nvis > 0) grid_fill_kernel<<<gv, kBlock, 0, st>>>(nvis, cell, start, cnt, list);
-  const unsigned gc = (unsigned)((cells + kBlock - 1) / kBlock);
-  constexpr int kChunk = 8;
-  for (int b0 = 0; b0 < batch; b0 += kChunk) {
-    if (kernel == ABS_GAUSS7)
-      grid_gather_kernel<3, kChunk><<<gc, kBlock, 0, st>>>(
-          p->n, p->du, pit2, nvis, batch, b0, uvd, visT, vis_w, start, list, integer_counts, sc,
-          reinterpret_cast<float2*>(grid), wsum);
-    else
-      grid_gather_kernel<0, kChunk><<<gc, kBlock, 0, st>>>(
-          p->n, p->du, pit2, nvis, batch, b0, uvd, visT, vis_w, start, list, integer_counts, sc,
-          reinterpret_cast<float2*>(grid), wsum);
+  if (nvis > 0)
+    grid_fill_kernel<<<(unsigned)((nvis + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        nvis, batch, cell, start, cnt, reinterpret_cast<const float2*>(vis), vis_w, lst, sorted, sc);
+  const bool vec = (batch & 1) == 0;
+  float2* g2 = reinterpret_cast<float2*>(grid);
+  // lanes per cell: enough pairs of realisations for one pass of up to kRec of them
+  const int nbc = std::min(batch, kRec);
+  const int lpc = nbc <= 2 ? 1 : nbc <= 4 ? 2 : nbc <= 8 ? 4 : 8;
+  const unsigned gc = (unsigned)((cells * lpc + kBlock - 1) / kBlock);
+  for (int b0 = 0; b0 < batch; b0 += 2 * lpc) {
+#define ABS_GATHER(RR, LL, VV)                                                                  \
+  grid_gather_kernel<RR, LL, VV><<<gc, kBlock, 0, st>>>(p->n, p->du, pit2, batch, b0, uvd, sorted, \
+                                                        vis_w, start, lst, integer_counts, sc, g2, wsum)
+#define ABS_GATHER_L(RR, VV)                 \
+  switch (lpc) {                             \
+    case 1: ABS_GATHER(RR, 1, VV); break;    \
+    case 2: ABS_GATHER(RR, 2, VV); break;    \
+    case 4: ABS_GATHER(RR, 4, VV); break;    \
+    default: ABS_GATHER(RR, 8, VV); break;   \
+  }
+    if (kernel == ABS_GAUSS7) {
+      if (vec) { ABS_GATHER_L(3, true) } else { ABS_GATHER_L(3, false) }
+    } else {
+      if (vec) { ABS_GATHER_L(0, true) } else { ABS_GATHER_L(0, false) }
+    }
+#undef ABS_GATHER_L
+#undef ABS_GATHER
   }
   if (dropped) grid_dropped_kernel<<<1, 1, 0, st>>>(sc, reinterpret_cast<long long*>(dropped));
   prof_end(p, ABS_STAGE_GRID, st);

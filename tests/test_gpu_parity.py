@@ -188,6 +188,32 @@ def test_gridding_matches_oracle_and_is_deterministic():
     assert np.allclose(w3.cpu().numpy(), wo, rtol=1e-5, atol=1e-6 * wo.max())
 
 
+@pytest.mark.parametrize("batch", [3, 18])
+def test_gridding_batches(batch):
+    """Odd batches (8-byte record loads) and batches over 16 (two gather passes), with
+    per-visibility weights on the nearest-cell kernel."""
+    A = _A()
+    torch = _torch()
+    n = 128
+    p = A.Plan(n, oplan.log_edges(3.0, 40.0, 6), max_batch=batch, wmode=A.W_INV_COUNT).bind()
+    uv, vis = synth.visibility_stream(40000, 40.0, 16.0, 1.0, seed=11 + batch, batch=batch)
+    vw = np.random.default_rng(batch).uniform(0.5, 1.5, len(uv)).astype(np.float32)
+    uvt, vt = torch.from_numpy(uv).cuda(), torch.from_numpy(vis).cuda()
+    for w in (None, vw):
+        g, ws, d = p.grid(uvt, vt, vis_w=None if w is None else torch.from_numpy(w).cuda())
+        torch.cuda.synchronize()
+        for b in range(batch):
+            go, wo, dro = ogrid.grid_visibilities(n, 1.0, uv, vis[b],
+                                                  vis_w=None if w is None else w.astype(np.float64))
+            scale = np.abs(vis).max() * (1.0 if w is None else 1.5)
+            assert np.allclose(g[b].cpu().numpy(), go, rtol=2 ** -22, atol=2 ** -23 * scale), (b, w is None)
+            assert int(d.item()) == dro
+        if w is None:
+            assert np.array_equal(ws.cpu().numpy(), wo.astype(np.float32))
+        else:
+            assert np.allclose(ws.cpu().numpy(), wo, rtol=2 ** -22, atol=2 ** -22)
+
+
 def p_theta0(p):
     return 0.6 * np.deg2rad(24.68)
 
