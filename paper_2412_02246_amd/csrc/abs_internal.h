@@ -41,10 +41,11 @@ struct DevLayout {
 struct WorkLayout {
   int nsets;          // D sets (one per grid) followed by I sets
   int nisets;
-  size_t zd, zi, fd, fi, part, fmax, total;
+  size_t zd, zi, fd, fi, part, part64, fmax, total;
   int64_t zset;       // complex elements per set of column-pass output
   int64_t fset;       // values per set of fields (nbins * n * n)
-  int64_t partset;    // doubles per set of contraction partials (nblk * ntrip)
+  int64_t partset;    // doubles per data set of contraction partials (nblk * ntrip)
+  int64_t partset64;  // doubles per weight set (nblk64 * ntrip)
 };
 
 }  // namespace abs_impl
@@ -78,8 +79,10 @@ struct abs_plan_s {
   // contraction kernel (compiled at run time for this triplet list)
   int ngroups = 0;               // wave groups of the FP32 kernel; one wave per group
   int ngroups64 = 0;             // wave groups of the FP64 kernel (weight fields)
-  int pix_per_block = 0;         // pixels per contraction workgroup
-  int nblk = 0;                  // contraction workgroups per set
+  int pix_per_block = 0;         // pixels per contraction workgroup (data sets)
+  int nblk = 0;                  // contraction pixel blocks per data set
+  int pix_per_block64 = 0;       // the same for the FP64 weight sets (fewer sets: smaller blocks)
+  int nblk64 = 0;
   std::string jit_src;
   std::vector<char> jit_code;
   bool compiled = false;

@@ -27,43 +27,54 @@ __global__ void fill_u32_kernel(unsigned* __restrict__ a, int n, unsigned v) {
 hipError_t launch_rowpass_f64(const abs_plan_s* p, int nsets, const double2* Z, long long zset,
                               double* F, long long fset, hipStream_t st);
 
+// Sum of nblk workgroup partials part[k * ntrip + t] for the block's 64 triplets, in a
+// fixed order: wave w adds its quarter of k in sequence, then the quarters are added in
+// order w = 0 .. 3.  Every thread of the block must call it.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nblk, int ntrip,
+                                               int t) {
+  __shared__ double q4[4][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int k0 = (int)((long long)nblk * wave / 4), k1 = (int)((long long)nblk * (wave + 1) / 4);
+  double s = 0.0;
+  if (t < ntrip)
+    for (int k = k0; k < k1; ++k) s += part[(long long)k * ntrip + t];
+  __syncthreads();   // q4 is reused by the next call
+  q4[wave][lane] = s;
+  __syncthreads();
+  return ((q4[0][lane] + q4[1][lane]) + q4[2][lane]) + q4[3][lane];
+}
+
 // B[b][t] = S / (A N), S and N the per-triangle sums: workgroup partials are added
 // in FP64 in a fixed order and divided by n^2 (the sum over pixels of a product of
-// three DFTs counts every closed triangle n^2 times).
+// three DFTs counts every closed triangle n^2 times).  Block: 64 triplets of grid b.
 __global__ void __launch_bounds__(kBlock)
-finalize_kernel(const double* __restrict__ part, long long partset, int nblk, int ntrip,
+finalize_kernel(const double* __restrict__ part, long long partset, int nblk,
+                const double* __restrict__ part64, long long partset64, int nblk64, int ntrip,
                 int batch, int nisets, const double* __restrict__ n_given, double inv_npix,
                 double norm, double* __restrict__ B, double* __restrict__ N) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.x * 64 + (threadIdx.x & 63);
   const int b = blockIdx.y;
-  if (t >= ntrip) return;
-  const double* ps = part + (long long)b * partset;
-  double s = 0.0;
-  for (int k = 0; k < nblk; ++k) s += ps[(long long)k * ntrip + t];
-  s *= inv_npix;
+  const double s = sum_partials(part + (long long)b * partset, nblk, ntrip, t) * inv_npix;
   double nn;
   if (nisets == 0) {
-    nn = n_given[t];
+    nn = t < ntrip ? n_given[t] : 0.0;
   } else {
-    const int is = batch + (nisets > 1 ? b : 0);
-    const double* pn = part + (long long)is * partset;
-    nn = 0.0;
-    for (int k = 0; k < nblk; ++k) nn += pn[(long long)k * ntrip + t];
-    nn *= inv_npix;
+    const int is = nisets > 1 ? b : 0;
+    nn = sum_partials(part64 + (long long)is * partset64, nblk64, ntrip, t) * inv_npix;
   }
-  B[(long long)b * ntrip + t] = s / (norm * nn);
-  if (N) N[(long long)b * ntrip + t] = nn;
+  if (threadIdx.x < 64 && t < ntrip) {
+    B[(long long)b * ntrip + t] = s / (norm * nn);
+    if (N) N[(long long)b * ntrip + t] = nn;
+  }
 }
 
 // abs_counts: N_t alone from the weight-set partials.
 __global__ void __launch_bounds__(kBlock)
-counts_kernel(const double* __restrict__ part, int nblk, int ntrip, double inv_npix,
+counts_kernel(const double* __restrict__ part64, int nblk64, int ntrip, double inv_npix,
               double* __restrict__ N) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntrip) return;
-  double nn = 0.0;
-  for (int k = 0; k < nblk; ++k) nn += part[(long long)k * ntrip + t];
-  N[t] = nn * inv_npix;
+  const int t = blockIdx.x * 64 + (threadIdx.x & 63);
+  const double nn = sum_partials(part64, nblk64, ntrip, t) * inv_npix;
+  if (threadIdx.x < 64 && t < ntrip) N[t] = nn;
 }
 
 abs_status ensure_device(abs_plan_s* p) {
@@ -74,13 +85,16 @@ abs_status ensure_device(abs_plan_s* p) {
   return ABS_OK;
 }
 
+// Workgroups: 4 triplet groups ("slice") x pixel block, numbered so that the slices of
+// one pixel block go to one XCD (the kernel decodes blockIdx.x the same way).
 abs_status launch_contract(hipFunction_t fn, int ngroups, const void* F, long long fset,
                            long long npix, int ppb, int nblk, int ntrip, int nsets, double* part,
                            hipStream_t st) {
   void* Fp = const_cast<void*>(F);
   void* args[] = {&Fp, &fset, &npix, &ppb, &part, &nblk, &ntrip};
   const unsigned gz = (unsigned)((ngroups + 3) / 4);
-  return hipModuleLaunchKernel(fn, (unsigned)nblk, (unsigned)nsets, gz, kBlock, 1, 1, 0, st, args,
+  const unsigned gx = 8u * (unsigned)((nblk + 7) / 8) * gz;
+  return hipModuleLaunchKernel(fn, gx, (unsigned)nsets, 1, kBlock, 1, 1, 0, st, args,
                                nullptr) == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
 
@@ -127,9 +141,9 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
       return ABS_ERR_DEVICE;
     if (launch_rowpass_f64(p, wl.nisets, Z, wl.zset, F, wl.fset, st) != hipSuccess)
       return ABS_ERR_DEVICE;
-    return launch_contract(p->contract64, p->ngroups64, F, wl.fset, npix, p->pix_per_block,
-                           p->nblk, (int)p->ntrip, wl.nisets, part + (long long)batch * wl.partset,
-                           st);
+    return launch_contract(p->contract64, p->ngroups64, F, wl.fset, npix, p->pix_per_block64,
+                           p->nblk64, (int)p->ntrip, wl.nisets,
+                           reinterpret_cast<double*>(work + wl.part64), st);
   }
   return ABS_OK;
 }
@@ -218,10 +232,11 @@ abs_status abs_estimate(abs_plan_t p, int32_t batch, int32_t dtype, const void* 
   s = run_fields_and_contract(p, wl, batch, dtype, grids, w, w_batched, wk, st);
   if (s != ABS_OK) return s;
   const double* part = reinterpret_cast<const double*>(wk + wl.part);
+  const double* part64 = reinterpret_cast<const double*>(wk + wl.part64);
   const double inv = 1.0 / ((double)p->n * (double)p->n);
-  const dim3 g((unsigned)((p->ntrip + kBlock - 1) / kBlock), (unsigned)batch);
-  finalize_kernel<<<g, kBlock, 0, st>>>(part, wl.partset, p->nblk, (int)p->ntrip, batch,
-                                        wl.nisets, n_given, inv, p->norm, B, N);
+  const dim3 g((unsigned)((p->ntrip + 63) / 64), (unsigned)batch);
+  finalize_kernel<<<g, kBlock, 0, st>>>(part, wl.partset, p->nblk, part64, wl.partset64, p->nblk64,
+                                        (int)p->ntrip, batch, wl.nisets, n_given, inv, p->norm, B, N);
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
 
@@ -241,8 +256,8 @@ abs_status abs_counts(abs_plan_t p, const float* w, void* work, size_t work_byte
   s = run_fields_and_contract(p, wl, 0, ABS_C64, nullptr, w, 0, wk, st);
   if (s != ABS_OK) return s;
   const double inv = 1.0 / ((double)p->n * (double)p->n);
-  counts_kernel<<<(unsigned)((p->ntrip + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-      reinterpret_cast<const double*>(wk + wl.part), p->nblk, (int)p->ntrip, inv, N);
+  counts_kernel<<<(unsigned)((p->ntrip + 63) / 64), kBlock, 0, st>>>(
+      reinterpret_cast<const double*>(wk + wl.part64), p->nblk64, (int)p->ntrip, inv, N);
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
 

@@ -152,6 +152,7 @@ WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_c
   w.zset = n * p->ncols;
   w.fset = (int64_t)p->nb * n * n;
   w.partset = (int64_t)p->nblk * p->ntrip;
+  w.partset64 = (int64_t)p->nblk64 * p->ntrip;
   auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
   size_t off = 0;
   w.zd = off;
@@ -163,7 +164,9 @@ WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_c
   w.fi = off;
   off = al(off + (size_t)w.nisets * w.fset * 8);
   w.part = off;
-  off = al(off + (size_t)w.nsets * w.partset * 8);
+  off = al(off + (size_t)batch * w.partset * 8);
+  w.part64 = off;
+  off = al(off + (size_t)w.nisets * w.partset64 * 8);
   w.fmax = off;
   off = al(off + (size_t)batch * p->nb * 4);
   w.total = off;
@@ -183,15 +186,15 @@ WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_c
 namespace {
 
 // Split ntrip triplets into G (a multiple of 4) contiguous groups whose register
-// estimate, rw * (slots + 2 * bins used), stays within the budget.
+// estimate, rw * (slots + bins used), stays within the budget.
 std::vector<int> split_groups(const abs_plan_s* p, int rw) {
   const int T = (int)p->ntrip;
-  const int kBudget = 212;
+  const int kBudget = 200;
   auto cost_ok = [&](int t0, int t1) {
     std::set<int> bins;
     for (int t = t0; t < t1; ++t)
       for (int q = 0; q < 3; ++q) bins.insert(p->trips[3 * t + q]);
-    return rw * ((t1 - t0) + 2 * (int)bins.size()) <= kBudget;
+    return rw * ((t1 - t0) + (int)bins.size()) <= kBudget;
   };
   for (int G = 4; G <= 16384; G += 4) {
     std::vector<int> start(G + 1);
@@ -203,10 +206,35 @@ std::vector<int> split_groups(const abs_plan_s* p, int rw) {
   return {};
 }
 
+// Kernel layout.  A workgroup is 4 waves (4 consecutive triplet groups, "slice" z) on
+// one pixel block of one set.  The pixels are walked in chunks of 64 (one per lane);
+// the rings the slice uses (its union U_z) are staged chunk by chunk in LDS, each wave
+// loading every 4th of them, so every field value is read from memory once per
+// workgroup.  A wave's loads for chunk c + 1 are issued two chunks ahead and stored to
+// the LDS stage that chunk c - 1 occupied, after the one barrier per chunk that also
+// publishes chunk c.  Workgroups are numbered so that the slices of one pixel block
+// run on one XCD (blocks are dealt to the 8 XCDs round robin), where they share L2.
 void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, const char* name,
                  const char* R, std::string& s) {
   char buf[1024];
-  const int G = (int)start.size() - 1;
+  const int G = (int)start.size() - 1;   // a multiple of 4
+  const int GZ = G / 4;
+  const bool dbl = std::strcmp(R, "double") == 0;
+  const int kRed = dbl ? 16 : 32;
+  std::vector<std::vector<int>> gbins(G), U(GZ);
+  for (int g = 0; g < G; ++g) {
+    std::set<int> b;
+    for (int t = start[g]; t < start[g + 1]; ++t)
+      for (int q = 0; q < 3; ++q) b.insert(p->trips[3 * t + q]);
+    gbins[g].assign(b.begin(), b.end());
+  }
+  int NU = 1;
+  for (int z = 0; z < GZ; ++z) {
+    std::set<int> b;
+    for (int g = 4 * z; g < 4 * z + 4; ++g) b.insert(gbins[g].begin(), gbins[g].end());
+    U[z].assign(b.begin(), b.end());
+    NU = std::max(NU, (int)U[z].size());
+  }
   std::snprintf(buf, sizeof buf,
                 "extern \"C\" __global__ void __launch_bounds__(256) %s(\n"
                 "    const %s* __restrict__ F, long long set_stride, long long npix, int ppb,\n"
@@ -214,69 +242,103 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, const char*
   s += buf;
   std::snprintf(buf, sizeof buf,
                 "  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;\n"
-                "  const int grp = blockIdx.z * 4 + wave;\n"
+                "  const int xcd = blockIdx.x & 7, kx = blockIdx.x >> 3;\n"
+                "  const int blk = xcd + 8 * (kx / %d), z = kx %% %d;\n"
+                "  if (blk >= nblk) return;\n"
+                "  const int grp = z * 4 + wave;\n"
                 "  const long long set = blockIdx.y;\n"
-                "  const %s* __restrict__ Fs = F + set * set_stride;\n"
-                "  const long long p0 = (long long)blockIdx.x * ppb;\n"
+                "  const long long p0 = (long long)blk * ppb;\n"
                 "  const long long p1 = (p0 + ppb < npix) ? p0 + ppb : npix;\n"
-                "  double* __restrict__ out = part + (set * nblk + blockIdx.x) * (long long)ntrip;\n"
+                "  const int nch = (int)((p1 - p0) / 64);\n"
+                "  const %s* __restrict__ Fs = F + set * set_stride + p0;\n"
+                "  double* __restrict__ out = part + (set * nblk + blk) * (long long)ntrip;\n"
                 "  __shared__ %s red_all[4 * %d * 65];\n"
+                "  __shared__ %s stg[2][%d][64];\n"
                 "  %s* red = red_all + wave * %d * 65;\n"
-                "  switch (grp) {\n", R, R, std::strcmp(R, "double") == 0 ? 16 : 32, R,
-                std::strcmp(R, "double") == 0 ? 16 : 32);
+                "  switch (grp) {\n", GZ, GZ, R, R, kRed, R, NU, R, kRed);
   s += buf;
   for (int g = 0; g < G; ++g) {
+    const int z = g / 4, w = g % 4;
     const int t0 = start[g], t1 = start[g + 1];
-    if (t1 <= t0) continue;
-    std::set<int> bins;
-    for (int t = t0; t < t1; ++t)
-      for (int q = 0; q < 3; ++q) bins.insert(p->trips[3 * t + q]);
+    const std::vector<int>& Uz = U[z];
+    auto slot = [&](int m) { return (int)(std::lower_bound(Uz.begin(), Uz.end(), m) - Uz.begin()); };
+    std::vector<int> mine;   // rings this wave stages
+    for (int k = w; k < (int)Uz.size(); k += 4) mine.push_back(Uz[k]);
     std::snprintf(buf, sizeof buf, "  case %d: {\n", g);
     s += buf;
     for (int t = t0; t < t1; ++t) {
       std::snprintf(buf, sizeof buf, "    %s a%d = 0;\n", R, t - t0);
       s += buf;
     }
-    for (int m : bins) {
+    for (size_t k = 0; k < mine.size(); ++k) {
       std::snprintf(buf, sizeof buf,
-                    "    const %s* __restrict__ q%d = Fs + %dLL * npix;\n    %s n%d = 0;\n", R, m,
-                    m, R, m);
+                    "    const %s* __restrict__ L%zu = Fs + %dLL * npix;\n    %s e%zu, o%zu;\n", R, k,
+                    mine[k], R, k, k);
       s += buf;
     }
-    s += "    long long p = p0 + lane;\n    if (p < p1) {\n";
-    for (int m : bins) {
-      std::snprintf(buf, sizeof buf, "      n%d = q%d[p];\n", m, m);
-      s += buf;
-    }
-    s += "    }\n    for (; p < p1; p += 64) {\n";
-    for (int m : bins) {
-      std::snprintf(buf, sizeof buf, "      const %s d%d = n%d;\n", R, m, m);
-      s += buf;
-    }
-    s += "      const long long pn = p + 64;\n      if (pn < p1) {\n";
-    for (int m : bins) {
-      std::snprintf(buf, sizeof buf, "        n%d = q%d[pn];\n", m, m);
-      s += buf;
-    }
-    std::snprintf(buf, sizeof buf, "      }\n      %s t;\n", R);
-    s += buf;
-    int ci = -1, cj = -1;
-    for (int t = t0; t < t1; ++t) {
-      const int i = p->trips[3 * t], j = p->trips[3 * t + 1], k = p->trips[3 * t + 2];
-      if (i != ci || j != cj) {
-        std::snprintf(buf, sizeof buf, "      t = d%d * d%d;\n", i, j);
-        s += buf;
-        ci = i;
-        cj = j;
+    // prologue: chunk 0 to stage 0, chunk 1 in flight (odd set), chunk 2 in flight (even
+    // set).  nch is even (pixel blocks are multiples of 128 pixels); loads past the last
+    // chunk re-read it, which keeps every load unconditional.
+    auto loads = [&](const char* set, const char* chunk) {
+      std::string r;
+      for (size_t k = 0; k < mine.size(); ++k) {
+        std::snprintf(buf, sizeof buf, "    %s%zu = L%zu[(unsigned)(64 * min(%s, nch - 1) + lane)];\n", set,
+                      k, k, chunk);
+        r += buf;
       }
-      std::snprintf(buf, sizeof buf, "      a%d = abs_fma(t, d%d, a%d);\n", t - t0, k, t - t0);
-      s += buf;
-    }
+      return r;
+    };
+    auto stores = [&](const char* set, const char* stage) {
+      std::string r;
+      for (size_t k = 0; k < mine.size(); ++k) {
+        std::snprintf(buf, sizeof buf, "    stg[%s][%d][lane] = %s%zu;\n", stage, slot(mine[k]), set, k);
+        r += buf;
+      }
+      return r;
+    };
+    auto compute = [&](const char* stage) {
+      std::string r;
+      for (int m : gbins[g]) {
+        std::snprintf(buf, sizeof buf, "    const %s d%d_%s = stg[%s][%d][lane];\n", R, m, stage, stage,
+                      slot(m));
+        r += buf;
+      }
+      std::snprintf(buf, sizeof buf, "    {\n    %s t;\n", R);
+      r += buf;
+      int ci = -1, cj = -1;
+      for (int t = t0; t < t1; ++t) {
+        const int i = p->trips[3 * t], j = p->trips[3 * t + 1], k = p->trips[3 * t + 2];
+        if (i != ci || j != cj) {
+          std::snprintf(buf, sizeof buf, "    t = d%d_%s * d%d_%s;\n", i, stage, j, stage);
+          r += buf;
+          ci = i;
+          cj = j;
+        }
+        std::snprintf(buf, sizeof buf, "    a%d = abs_fma(t, d%d_%s, a%d);\n", t - t0, k, stage, t - t0);
+        r += buf;
+      }
+      r += "    }\n";
+      return r;
+    };
+    s += loads("e", "0");
+    s += stores("e", "0");
+    s += loads("o", "1");
+    s += loads("e", "2");
+    // chunk c even: publish stage 0 (chunk c), store chunk c + 1 (odd set) to stage 1,
+    // load chunk c + 3 into the odd set, compute chunk c; then the same for c + 1.  The
+    // loads of a chunk are issued two chunks before it is stored.
+    s += "    for (int c = 0; c < nch; c += 2) {\n    __syncthreads();\n";
+    s += stores("o", "1");
+    s += loads("o", "c + 3");
+    s += compute("0");
+    s += "    __syncthreads();\n";
+    s += stores("e", "0");
+    s += loads("e", "c + 4");
+    s += compute("1");
     s += "    }\n";
     // Cross-lane sums through LDS, kRed accumulators at a time: every lane stores its
     // values as one row per accumulator, then lane l < kRed adds row l in FP64.  One
     // store per accumulator keeps the generated code (and its compile time) small.
-    const int kRed = std::strcmp(R, "double") == 0 ? 16 : 32;
     for (int c0 = t0; c0 < t1; c0 += kRed) {
       const int c1 = std::min(t1, c0 + kRed);
       for (int t = c0; t < c1; ++t) {
@@ -587,6 +649,9 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
   const int64_t npix = (int64_t)n * n;
   p->pix_per_block = (int)std::min<int64_t>(16384, std::max<int64_t>(1024, npix / 64));
   p->nblk = (int)((npix + p->pix_per_block - 1) / p->pix_per_block);
+  // one weight set per call as a rule: smaller blocks keep the GPU busy
+  p->pix_per_block64 = (int)std::max<int64_t>(1024, npix / 256);
+  p->nblk64 = (int)((npix + p->pix_per_block64 - 1) / p->pix_per_block64);
 
   // device layout of the plan tables
   auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
