@@ -292,7 +292,7 @@ __device__ __forceinline__ void fft_pass(typename Cx<R>::T* buf, int t, const ty
 #pragma unroll
     for (int j = 0; j < NB; ++j)
 #pragma unroll
-      for (int r = 0; r < RP; ++r) v[j][r] = in(t + F::TG * j + r * STRIDE, r);
+      for (int r = 0; r < RP; ++r) v[j][r] = in(t + F::TG * j + r * STRIDE, j, r);
   } else {
     static_assert(STRIDE % 16 == 0, "padded reads need a stride that is a multiple of 16");
 #pragma unroll
@@ -314,7 +314,7 @@ __device__ __forceinline__ void fft_pass(typename Cx<R>::T* buf, int t, const ty
     const int idxD = ((b >> LNS) << (LNS + LRP)) + (b & (NS - 1));
     if constexpr (LAST) {
 #pragma unroll
-      for (int q = 0; q < RP; ++q) out(idxD + q * NS, v[j][q]);
+      for (int q = 0; q < RP; ++q) out(idxD + q * NS, j, q, v[j][q]);
     } else if constexpr (FIRST) {
       // k = 16 b + q: lpad(k) = 17 b + q
 #pragma unroll
@@ -361,33 +361,26 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
   Twiddles<R, LOG2N, REG> twr;
   twr.load(tw, t);
   R vmax = R(0);
+  constexpr int S = n / 16;
   for (int it = 0; it < iters; ++it) {
     const int pair = blk * per_block + it * FF::G + g;
     const bool active = pair < n / 2;
-    const int ya = 2 * (active ? pair : 0);
-    R* __restrict__ row0 = fs + (long long)ya * n;
-    R* __restrict__ row1 = row0 + n;
-    auto out = [&](int k, T v) {
-      if (active) {
-        row0[k] = v.x;
-        row1[k] = v.y;
-        if constexpr (FMAX) vmax = fmax(vmax, fmax(fabs(v.x), fabs(v.y)));
-      }
-    };
     if (cols == 0) {   // ring without lattice cells: its field is zero
-      for (int k = t; k < n; k += FF::TG) out(k, Cx<R>::mk(R(0), R(0)));
+      if (active)
+        for (int k = t; k < n; k += FF::TG) {
+          fs[(long long)(2 * pair) * n + k] = R(0);
+          fs[(long long)(2 * pair + 1) * n + k] = R(0);
+        }
       continue;
     }
-    // input k of the row pair: Z(gx, ya) + i Z(gx, ya + 1) at gx = k (k <= H) or
+    // Input k of the row pair: Z(gx, ya) + i Z(gx, ya + 1) at gx = k (k <= H) or
     // gx = k - n (k >= n - H), using Z(-gx, y) = conj Z(gx, y); zero elsewhere.  Slab r
-    // of the first pass covers k in [r n/16, (r + 1) n/16).
-    const T* __restrict__ za = zs + (long long)ya * cols;
+    // of the first pass covers k in [r n/16, (r + 1) n/16); all-zero slabs are not read.
+    const T* __restrict__ za = zs + (long long)(2 * (active ? pair : 0)) * cols;
     const T* __restrict__ zb = za + cols;
-    auto in = [&](int k, int r) -> T {
-      constexpr int S = n / 16;
-      const bool lo_slab = r * S <= H, hi_slab = (r + 1) * S - 1 >= n - H;
+    auto in = [&](int k, int, int r) -> T {
       T x = Cx<R>::mk(R(0), R(0));
-      if (active && (lo_slab || hi_slab)) {
+      if (active && (r * S <= H || (r + 1) * S - 1 >= n - H)) {
         if (k <= H) {
           const T a = za[k], b = zb[k];
           x = Cx<R>::mk(a.x - b.y, a.y + b.x);
@@ -397,6 +390,16 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
         }
       }
       return x;
+    };
+    R* __restrict__ row0 = fs + (long long)(2 * (active ? pair : 0)) * n;
+    R* __restrict__ row1 = row0 + n;
+    auto out = [&](int k, int, int, T v) {
+      if (active) {
+        row0[k] = v.x;
+        row1[k] = v.y;
+      }
+      if constexpr (FMAX)
+        if (active) vmax = fmax(vmax, fmax(fabs(v.x), fabs(v.y)));
     };
     fft_sync<FF::WAVE>();   // the previous transform's last reads are done
     fft_passes<R, LOG2N, 0>(buf, t, tw, twr, in, out);

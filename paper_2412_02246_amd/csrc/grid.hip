@@ -176,6 +176,12 @@ grid_fill_kernel(long long nvis, int batch, const int* __restrict__ cell,
   __shared__ int posl[kBlock];
   const long long i0 = (long long)blockIdx.x * kBlock;
   const long long i = i0 + threadIdx.x;
+  // the first kRec realisations are loaded before the slot is claimed, so that the
+  // loads and the atomic are in flight together
+  float2 v0[kRec];
+#pragma unroll
+  for (int bb = 0; bb < kRec; ++bb)
+    v0[bb] = (bb < batch && i < nvis) ? vis[(long long)bb * nvis + i] : make_float2(0.f, 0.f);
   int pos = -1;
   float wa = 0.f;
   if (i < nvis) {
@@ -192,11 +198,14 @@ grid_fill_kernel(long long nvis, int batch, const int* __restrict__ cell,
   for (int b0 = 0; b0 < batch; b0 += kRec) {
     const int nbc = min(kRec, batch - b0);
     __syncthreads();   // posl written; the previous chunk's tile consumed
-    for (int bb = 0; bb < nbc; ++bb) {
-      float2 v = make_float2(0.f, 0.f);
-      if (i < nvis) v = vis[(long long)(b0 + bb) * nvis + i];
-      if (pos >= 0) vm = fmaxf(vm, wa * fmaxf(fabsf(v.x), fabsf(v.y)));
-      tile[bb][threadIdx.x] = v;
+#pragma unroll
+    for (int bb = 0; bb < kRec; ++bb) {
+      if (bb < nbc) {
+        float2 v = v0[bb];
+        if (b0 > 0) v = i < nvis ? vis[(long long)(b0 + bb) * nvis + i] : make_float2(0.f, 0.f);
+        if (pos >= 0) vm = fmaxf(vm, wa * fmaxf(fabsf(v.x), fabsf(v.y)));
+        tile[bb][threadIdx.x] = v;
+      }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < nrow * nbc; e += kBlock) {
@@ -237,10 +246,14 @@ grid_gather_kernel(int n, double du, double pit2, int batch, int b0,
                    float2* __restrict__ grid, float* __restrict__ wsum) {
   const long long nn = (long long)n * n;
   const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long c = gt / LPC;
-  const int q = (int)(gt - c * LPC);
-  if (c >= nn) return;
-  const int iy = (int)(c / n), ix = (int)(c - (long long)iy * n);
+  const long long lc = gt / LPC;
+  const int q = (int)(gt - lc * LPC);
+  if (lc >= nn) return;
+  // rows in the order |gy| = 0, 1, 1, 2, 2, ...: the densely sampled short baselines
+  // (the longest lists) are gathered first and do not form a tail
+  const int r = (int)(lc / n), ix = (int)(lc - (long long)r * n);
+  const int iy = (r & 1) ? n - 1 - (r >> 1) : (r >> 1);
+  const long long c = (long long)iy * n + ix;
   const int gy = iy < n / 2 ? iy : iy - n, gx = ix < n / 2 ? ix : ix - n;
   // a cell adds at most 2 (2R + 1)^2 maxcnt terms, each with kernel weight <= 1
   const long long terms = 2ll * (2 * R + 1) * (2 * R + 1) * (long long)sc->maxcnt;
@@ -271,10 +284,13 @@ grid_gather_kernel(int n, double du, double pit2, int batch, int b0,
           if (!(sx > -half && sx < half && sy > -half && sy < half)) continue;
           const int sc_idx = (sy < 0 ? sy + n : sy) * n + (sx < 0 ? sx + n : sx);
           const int p0 = start[sc_idx], p1 = start[sc_idx + 1];
-          float4 nxt = p0 < p1 ? load(p0) : make_float4(0.f, 0.f, 0.f, 0.f);
+          // two records in flight while one adds
+          float4 nx1 = p0 < p1 ? load(p0) : make_float4(0.f, 0.f, 0.f, 0.f);
+          float4 nx2 = p0 + 1 < p1 ? load(p0 + 1) : make_float4(0.f, 0.f, 0.f, 0.f);
           for (int p = p0; p < p1; ++p) {
-            const float4 v = nxt;
-            if (p + 1 < p1) nxt = load(p + 1);   // next record in flight while this one adds
+            const float4 v = nx1;
+            nx1 = nx2;
+            if (p + 2 < p1) nx2 = load(p + 2);
             double cw = 1.0;
             if (R > 0 || vw) {
               const int i = list[p];
