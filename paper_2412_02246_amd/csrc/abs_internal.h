@@ -41,7 +41,7 @@ struct DevLayout {
 struct WorkLayout {
   int nsets;          // D sets (one per grid) followed by I sets
   int nisets;
-  size_t zd, zi, fd, fi, part, part64, fmax, total;
+  size_t zd, zi, fd, fi, part, part64, fmax, xc, total;
   int64_t zset;       // complex elements per set of column-pass output
   int64_t fset;       // values per set of fields (nbins * n * n)
   int64_t partset;    // doubles per data set of contraction partials (nblk * ntrip)
@@ -59,6 +59,7 @@ struct abs_plan_s {
   std::vector<double> edges, lo2, hi2;
   // rings
   std::vector<int> h, cols;
+  int hmax = 0;                  // largest h over the rings (extent of the Hermitian part)
   std::vector<int64_t> zoff;     // complex elements, per ring, within one set
   int64_t ncols = 0;             // sum of cols
   std::vector<double> radius;    // mean |g| per ring

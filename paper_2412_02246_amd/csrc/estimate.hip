@@ -12,9 +12,10 @@
 
 namespace abs_impl {
 hipError_t launch_colpass_data(const abs_plan_s* p, const void* grids, int dtype, const float* w,
-                               int w_batched, int batch, float2* Z, long long zset, hipStream_t st);
+                               int w_batched, int batch, void* xc, float2* Z, long long zset,
+                               hipStream_t st);
 hipError_t launch_colpass_weight(const abs_plan_s* p, const float* w, int w_batched, int nsets,
-                                 double2* Z, long long zset, hipStream_t st);
+                                 void* xc, double2* Z, long long zset, hipStream_t st);
 hipError_t launch_rowpass_f32(const abs_plan_s* p, int nsets, const float2* Z, long long zset,
                               float* F, long long fset, unsigned* fmax_bits, hipStream_t st);
 hipError_t launch_mfma_contract(const abs_plan_s* p, const float* F, long long fset, int nsets,
@@ -109,7 +110,8 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
     float2* Z = reinterpret_cast<float2*>(work + wl.zd);
     float* F = reinterpret_cast<float*>(work + wl.fd);
     prof_begin(p, ABS_STAGE_COLPASS, st);
-    if (launch_colpass_data(p, grids, dtype, w, w_batched, batch, Z, wl.zset, st) != hipSuccess)
+    if (launch_colpass_data(p, grids, dtype, w, w_batched, batch, work + wl.xc, Z, wl.zset, st) !=
+        hipSuccess)
       return ABS_ERR_DEVICE;
     prof_end(p, ABS_STAGE_COLPASS, st);
     // FP16 splits need a power-of-two scale per (grid, ring): the row pass records max |F|
@@ -137,7 +139,7 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
   if (wl.nisets > 0) {
     double2* Z = reinterpret_cast<double2*>(work + wl.zi);
     double* F = reinterpret_cast<double*>(work + wl.fi);
-    if (launch_colpass_weight(p, w, w_batched, wl.nisets, Z, wl.zset, st) != hipSuccess)
+    if (launch_colpass_weight(p, w, w_batched, wl.nisets, work + wl.xc, Z, wl.zset, st) != hipSuccess)
       return ABS_ERR_DEVICE;
     if (launch_rowpass_f64(p, wl.nisets, Z, wl.zset, F, wl.fset, st) != hipSuccess)
       return ABS_ERR_DEVICE;

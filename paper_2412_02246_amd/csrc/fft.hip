@@ -12,10 +12,16 @@
 //
 // Each length-n transform is a self-sorting (Stockham) FFT run by n/16 threads (two
 // radix-16 butterflies per thread at n = 8192): radix-16 passes, then one radix-2, 4
-// or 8 pass.  The block first stages the (mostly zero) inputs of its transforms in a
-// padded LDS buffer (one slot of padding every 16 elements keeps strided accesses off
-// a single bank); a thread keeps its butterflies in registers between passes, and the
-// last pass writes the output in natural order straight to global memory.
+// or 8 pass, with n a compile-time constant.  The first pass reads its inputs straight
+// from memory (skipping the all-zero slabs of the pruned input), passes exchange data
+// through a padded LDS buffer (one slot of padding every 16 elements keeps strided
+// accesses off a single bank), and a thread keeps its butterflies and twiddles in
+// registers.  The row pass writes the last pass's output in natural order straight to
+// global memory; the column pass gathers its tile's outputs in LDS first.
+//
+// Before the column pass, the Hermitian part of the weighted grid is copied into a
+// column-major array (herm_kernel) so that each column transform reads its input
+// contiguously.
 //
 // Data fields D (Eq. 10) are computed in FP32.  Weight fields I (Eq. 11) are computed
 // in FP64: their triple sums N_t can be tiny next to the size of the individual
@@ -124,75 +130,6 @@ __device__ __forceinline__ void dft(typename Cx<R>::T* v) {
 }
 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
-
-// One Stockham pass of radix RP over a length-n transform held by Tg threads; thread t
-// owns butterflies b = t + Tg * j, j < 16 U / RP.  Input comes from buf (padded); LAST
-// writes out(k, value), otherwise the output goes back to buf.
-template <typename R, int RP, int U, bool FIRST, bool LAST, class Out>
-__device__ __forceinline__ void stockham_pass(typename Cx<R>::T* buf, int n, int log2n, int lns,
-                                              int t, int Tg, const typename Cx<R>::T* __restrict__ tw,
-                                              Out& out) {
-  using T = typename Cx<R>::T;
-  constexpr int NB = 16 * U / RP;
-  constexpr int LRP = RP == 16 ? 4 : RP == 8 ? 3 : RP == 4 ? 2 : 1;
-  const int stride = n >> LRP;       // n / RP
-  const int Ns = 1 << lns;
-  T v[NB][RP];
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    const int b = t + Tg * j;
-#pragma unroll
-    for (int r = 0; r < RP; ++r) v[j][r] = buf[lpad(b + r * stride)];
-  }
-  __syncthreads();  // every read of this pass precedes every write
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    const int b = t + Tg * j;
-    const int m = b & (Ns - 1);
-    if (!FIRST && m != 0) {
-      const int sh = log2n - lns - LRP;   // twiddle exp(-2 pi i r m / (Ns RP)) = tw[(r m) << sh]
-#pragma unroll
-      for (int r = 1; r < RP; ++r) v[j][r] = cmul(v[j][r], tw[(r * m) << sh]);
-    }
-    dft<R, RP>(v[j]);
-    const int idxD = ((b >> lns) << (lns + LRP)) + m;
-#pragma unroll
-    for (int q = 0; q < RP; ++q) {
-      const int k = idxD + q * Ns;
-      if constexpr (LAST) out(k, v[j][q]);
-      else buf[lpad(k)] = v[j][q];
-    }
-  }
-  if constexpr (!LAST) __syncthreads();
-}
-
-// Length-n forward FFT (16 <= n <= 8192) of the sequence staged in buf (padded, natural
-// order), by Tg = n / (16 U) threads, output in natural order through out(k, value);
-// every thread of the block must call it (it synchronises the block).
-template <typename R, int U, class Out>
-__device__ void stockham_fft(typename Cx<R>::T* buf, int n, int log2n, int t, int Tg,
-                             const typename Cx<R>::T* __restrict__ tw, Out out) {
-  const int np16 = log2n >> 2, lrest = log2n & 3;
-  const int npass = np16 + (lrest ? 1 : 0);
-  int lns = 0;
-  for (int p = 0; p < npass; ++p) {
-    const bool first = p == 0, last = p == npass - 1;
-    const int lr = p < np16 ? 4 : lrest;
-    if (lr == 4) {
-      if (first && last) stockham_pass<R, 16, U, true, true>(buf, n, log2n, lns, t, Tg, tw, out);
-      else if (first) stockham_pass<R, 16, U, true, false>(buf, n, log2n, lns, t, Tg, tw, out);
-      else if (last) stockham_pass<R, 16, U, false, true>(buf, n, log2n, lns, t, Tg, tw, out);
-      else stockham_pass<R, 16, U, false, false>(buf, n, log2n, lns, t, Tg, tw, out);
-    } else if (lr == 3) {
-      stockham_pass<R, 8, U, false, true>(buf, n, log2n, lns, t, Tg, tw, out);
-    } else if (lr == 2) {
-      stockham_pass<R, 4, U, false, true>(buf, n, log2n, lns, t, Tg, tw, out);
-    } else {
-      stockham_pass<R, 2, U, false, true>(buf, n, log2n, lns, t, Tg, tw, out);
-    }
-    lns += lr;
-  }
-}
 
 // ---------------------------------------------------------------------------------
 // Compile-time-length engine (used by the row pass).  With n fixed every LDS address is
@@ -346,10 +283,19 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
   using T = typename Cx<R>::T;
   using FF = Fft<LOG2N>;
   constexpr int n = FF::N;
-  constexpr bool REG = sizeof(R) == 4 && FF::NTW <= 32;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int g = threadIdx.x / FF::TG, t = threadIdx.x - g * FF::TG;
   T* buf = reinterpret_cast<T*>(lds_raw) + g * FF::L;
+  // A twiddle table of up to 16 KB is copied into LDS after the FFT buffers (registers
+  // stay free for more waves per SIMD); larger ones are read from memory.
+  constexpr bool TWL = FF::N * sizeof(T) <= 16384;
+  const T* __restrict__ twp = tw;
+  if constexpr (TWL) {
+    T* twl = reinterpret_cast<T*>(lds_raw) + FF::G * FF::L;
+    for (int k = threadIdx.x; k < n; k += kBlock) twl[k] = tw[k];
+    __syncthreads();
+    twp = twl;
+  }
   const int per_block = FF::G * iters;
   const int nrb = (n / 2 + per_block - 1) / per_block;
   const int m = blockIdx.x / nrb, blk = blockIdx.x - m * nrb;
@@ -358,8 +304,7 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
   const int H = bin.h, cols = bin.cols;
   R* __restrict__ fs = F + (long long)set * fset + (long long)m * n * n;
   const T* __restrict__ zs = Z + (long long)set * zset + bin.zoff;
-  Twiddles<R, LOG2N, REG> twr;
-  twr.load(tw, t);
+  Twiddles<R, LOG2N, false> twr;
   R vmax = R(0);
   constexpr int S = n / 16;
   for (int it = 0; it < iters; ++it) {
@@ -376,18 +321,16 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
     // Input k of the row pair: Z(gx, ya) + i Z(gx, ya + 1) at gx = k (k <= H) or
     // gx = k - n (k >= n - H), using Z(-gx, y) = conj Z(gx, y); zero elsewhere.  Slab r
     // of the first pass covers k in [r n/16, (r + 1) n/16); all-zero slabs are not read.
-    const T* __restrict__ za = zs + (long long)(2 * (active ? pair : 0)) * cols;
-    const T* __restrict__ zb = za + cols;
+    // the column pass stored the pair's inputs: P(gx) = Z(gx, ya) + i Z(gx, ya + 1) at
+    // zp[4 gx] and Q(gx) = conj Z(gx, ya) + i conj Z(gx, ya + 1), the input at -gx, next
+    // to it (blocks of 4 rows)
+    const int pr = active ? pair : 0;
+    const T* __restrict__ zp = zs + (long long)(pr >> 1) * 4 * cols + 2 * (pr & 1);
     auto in = [&](int k, int, int r) -> T {
       T x = Cx<R>::mk(R(0), R(0));
       if (active && (r * S <= H || (r + 1) * S - 1 >= n - H)) {
-        if (k <= H) {
-          const T a = za[k], b = zb[k];
-          x = Cx<R>::mk(a.x - b.y, a.y + b.x);
-        } else if (k >= n - H) {
-          const T a = za[n - k], b = zb[n - k];
-          x = Cx<R>::mk(a.x + b.y, -a.y + b.x);
-        }
+        if (k <= H) x = zp[4 * k];
+        else if (k >= n - H) x = zp[4 * (n - k) + 1];
       }
       return x;
     };
@@ -402,7 +345,7 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
         if (active) vmax = fmax(vmax, fmax(fabs(v.x), fabs(v.y)));
     };
     fft_sync<FF::WAVE>();   // the previous transform's last reads are done
-    fft_passes<R, LOG2N, 0>(buf, t, tw, twr, in, out);
+    fft_passes<R, LOG2N, 0>(buf, t, twp, twr, in, out);
   }
   if constexpr (FMAX) {
     float v = (float)vmax;
@@ -427,74 +370,130 @@ __device__ __forceinline__ float2 load_vis(const double2* __restrict__ g, long l
   return make_float2((float)v.x, (float)v.y);
 }
 
-// FFT geometry of a block of kBlock threads: G transforms at once, Tg threads each.
-struct FftGeom {
-  int G, Tg;
-};
-__host__ __device__ inline FftGeom fft_geom(int n) {
-  const int per = n >= 16 ? n / 16 : 1;          // butterflies of a radix-16 pass
-  const int Tg = per < kBlock ? per : kBlock;
-  return {kBlock / Tg, Tg};
-}
-__host__ __device__ inline int fft_lds_elems(int n) { return n + n / 16; }
+// Hermitian part of the weighted grid on the half-plane columns 0 <= gx <= hm and rows
+// |gy| <= hm (hm: the largest |gx| of any ring cell), stored column by column as
+// xc[set][gx][gy + hm] with column length lc = 2 hm + 1, so that the column pass reads
+// each column contiguously.  DATA: X(g) = (W(g) V(g) + conj(W(-g) V(-g))) / 2 (FP32);
+// otherwise Y(g) = (W(g) + W(-g)) / 2 (FP64, real).  The grid is read by rows (coalesced
+// in gx) and written by columns through an LDS tile of kHx x kHy cells.
+constexpr int kHx = 64, kHy = 16;
+template <bool DATA> struct HermT;
+template <> struct HermT<true> { using T = float2; };
+template <> struct HermT<false> { using T = double; };
 
-// Column pass: one transform per (ring, column gx); blockIdx.x = column tile (G columns
-// of one ring), blockIdx.y = set.  DATA: stage X = (W V(g) + conj(W V(-g)))/2 of grid
-// `set`; otherwise Y = (W(g) + W(-g))/2 of weight array `set`.
-template <typename R, int U, bool DATA, typename GT>
+template <bool DATA, typename GT>
 __global__ void __launch_bounds__(kBlock)
-colpass_kernel(const GT* __restrict__ grids, const float* __restrict__ w, int w_batched, int wmode,
-               int n, int log2n, const ColTile* __restrict__ tiles, const BinDev* __restrict__ bins,
-               const typename Cx<R>::T* __restrict__ tw, typename Cx<R>::T* __restrict__ Z,
-               long long zset) {
-  using T = typename Cx<R>::T;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  const FftGeom geo = fft_geom(n);
-  const int g = threadIdx.x / geo.Tg, t = threadIdx.x - g * geo.Tg;
-  T* buf = reinterpret_cast<T*>(lds_raw) + g * fft_lds_elems(n);
-  const ColTile tile = tiles[blockIdx.x];
-  const int set = blockIdx.y;
+herm_kernel(const GT* __restrict__ grids, const float* __restrict__ w, int w_batched, int wmode,
+            int n, int hm, int lc, typename HermT<DATA>::T* __restrict__ xc) {
+  using OT = typename HermT<DATA>::T;
+  __shared__ OT tile[kHy][kHx + 1];
+  const int set = blockIdx.z;
+  const int gx0 = blockIdx.x * kHx, gy0 = blockIdx.y * kHy - hm;
   const long long nn = (long long)n * n;
-  const float* __restrict__ ws = (w && w_batched) ? w + (long long)set * nn : w;
-  const BinDev bin = bins[tile.m];
-  const bool active = g < tile.ncols;
-  const int gx = tile.gx0 + (active ? g : 0);
-  const int H = bin.h;
-  (void)gx;
-  const double lo2 = bin.lo2, hi2 = bin.hi2;
   const GT* __restrict__ gs = DATA ? grids + (long long)set * nn : nullptr;
-  T* lds = reinterpret_cast<T*>(lds_raw);
-  const int L = fft_lds_elems(n);
-  for (int q = threadIdx.x; q < geo.G * L; q += blockDim.x) lds[q] = Cx<R>::mk(R(0), R(0));
-  __syncthreads();
-  // stage the ring cells of the tile's columns: gy in [-H, H], column-fastest for
-  // coalesced reads of the grid rows
-  const int nc = tile.ncols, nrows = 2 * H + 1;
-  for (int q = threadIdx.x; q < nrows * nc; q += blockDim.x) {
-    const int r = q / nc, c = q - r * nc;
-    const int gy = r - H, cx = tile.gx0 + c;
-    const double d2 = (double)((long long)cx * cx + (long long)gy * gy);
-    if (!(d2 >= lo2 && d2 < hi2)) continue;
-    const int iy = gy < 0 ? gy + n : gy;
-    const int my = gy > 0 ? n - gy : -gy, mx = cx > 0 ? n - cx : 0;
-    const long long i0 = (long long)iy * n + cx, i1 = (long long)my * n + mx;
-    const R w0 = weight_of<R>(ws, wmode, i0), w1 = weight_of<R>(ws, wmode, i1);
-    T v;
-    if constexpr (DATA) {
-      const float2 a = load_vis(gs, i0), b = load_vis(gs, i1);
-      v = Cx<R>::mk(R(0.5) * (w0 * a.x + w1 * b.x), R(0.5) * (w0 * a.y - w1 * b.y));
-    } else {
-      v = Cx<R>::mk(R(0.5) * (w0 + w1), R(0));
+  const float* __restrict__ ws = (w && w_batched) ? w + (long long)set * nn : w;
+  const int tx = threadIdx.x & (kHx - 1), ty = threadIdx.x / kHx;
+  for (int yy = ty; yy < kHy; yy += kBlock / kHx) {
+    const int gx = gx0 + tx, gy = gy0 + yy;
+    OT v{};
+    if (gx <= hm && gy <= hm) {
+      const int iy = gy < 0 ? gy + n : gy;
+      const int my = gy > 0 ? n - gy : -gy, mx = gx > 0 ? n - gx : 0;
+      const long long i0 = (long long)iy * n + gx, i1 = (long long)my * n + mx;
+      if constexpr (DATA) {
+        const float w0 = weight_of<float>(ws, wmode, i0), w1 = weight_of<float>(ws, wmode, i1);
+        const float2 a = load_vis(gs, i0), b = load_vis(gs, i1);
+        v = make_float2(0.5f * (w0 * a.x + w1 * b.x), 0.5f * (w0 * a.y - w1 * b.y));
+      } else {
+        v = 0.5 * (weight_of<double>(ws, wmode, i0) + weight_of<double>(ws, wmode, i1));
+      }
     }
-    lds[c * L + lpad(iy)] = v;
+    tile[yy][tx] = v;
   }
   __syncthreads();
-  T* __restrict__ zs = Z + (long long)set * zset + bin.zoff;
-  const int cols = bin.cols;
-  auto out = [&](int k, T v) {
-    if (active) zs[(long long)k * cols + gx] = v;
-  };
-  stockham_fft<R, U>(buf, n, log2n, t, geo.Tg, tw, out);
+  for (int e = threadIdx.x; e < kHx * kHy; e += kBlock) {
+    const int c = e / kHy, yy = e - c * kHy;
+    const int gx = gx0 + c, gy = gy0 + yy;
+    if (gx <= hm && gy <= hm) xc[((long long)set * (hm + 1) + gx) * lc + gy + hm] = tile[yy][c];
+  }
+}
+
+// Column pass: one transform per (ring, column gx), Z_m(gx, y) = sum over the ring's
+// cells in column gx of X(gx, gy) exp(-2 pi i gy y / n).  A block takes `tpb` column
+// tiles (G columns of one ring each) in turn; blockIdx.y = set.  Input k of a column is
+// the cell gy = k (k <= H) or gy = k - n (k >= n - H) when it lies in the ring, read
+// from the column-major Hermitian part.  Z_m is stored in blocks of 4 rows,
+// Z_m[y / 4][gx][y % 4] (zidx), so that the tile's outputs, gathered in LDS, leave as
+// runs of 4 ncols consecutive elements (whole 128-byte lines for 4 FP32 columns) and
+// the row pass reads each input of a row pair with one load.
+template <typename R, int LOG2N>
+__global__ void __launch_bounds__(kBlock)
+colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, int hm, int lc,
+                     const ColTile* __restrict__ tiles, int ntiles, int tpb,
+                     const BinDev* __restrict__ bins, const typename Cx<R>::T* __restrict__ tw,
+                     typename Cx<R>::T* __restrict__ Z, long long zset) {
+  using T = typename Cx<R>::T;
+  using FF = Fft<LOG2N>;
+  constexpr int n = FF::N, S = n / 16;
+  constexpr bool DATA = sizeof(R) == 4;
+  constexpr bool REG = DATA && FF::NTW <= 32;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int g = threadIdx.x / FF::TG, t = threadIdx.x - g * FF::TG;
+  T* buf = reinterpret_cast<T*>(lds_raw) + g * FF::L;
+  const int set = blockIdx.y;
+  Twiddles<R, LOG2N, REG> twr;
+  twr.load(tw, t);
+  for (int it = 0; it < tpb; ++it) {
+    const int ti = blockIdx.x * tpb + it;
+    if (ti >= ntiles) break;   // the same for the whole block
+    const ColTile tile = tiles[ti];
+    const BinDev bin = bins[tile.m];
+    const bool active = g < tile.ncols;
+    const int gx = tile.gx0 + (active ? g : 0);
+    const int H = bin.h, cols = bin.cols;
+    const double lo2 = bin.lo2, hi2 = bin.hi2;
+    const auto* __restrict__ col = xc + ((long long)set * (hm + 1) + gx) * lc + hm;   // col[gy]
+    auto in = [&](int k, int, int r) -> T {
+      T x = Cx<R>::mk(R(0), R(0));
+      if (active && (r * S <= H || (r + 1) * S - 1 >= n - H)) {
+        const int gy = k <= H ? k : k - n;
+        if (k <= H || k >= n - H) {
+          const double d2 = (double)((long long)gx * gx + (long long)gy * gy);
+          if (d2 >= lo2 && d2 < hi2) {
+            if constexpr (DATA) x = col[gy];
+            else x = Cx<R>::mk(col[gy], R(0));
+          }
+        }
+      }
+      return x;
+    };
+    // outputs of the block's transforms gathered as stage[y * G + g] (over the FFT
+    // buffers, once every transform has finished reading them)
+    T* stage = reinterpret_cast<T*>(lds_raw);
+    constexpr int PL = FF::NPASS - 1, NBL = FF::nb(PL), RPL = 1 << FF::lrp(PL), NSL = 1 << (4 * PL);
+    T res[NBL][RPL];   // output (j, q) of the last pass is element t + TG j + q NSL
+    auto out = [&](int, int j, int q, T v) { res[j][q] = v; };
+    __syncthreads();   // the previous tile's stage has been written out
+    fft_passes<R, LOG2N, 0>(buf, t, tw, twr, in, out);
+    __syncthreads();   // every transform has read its buffer
+#pragma unroll
+    for (int j = 0; j < NBL; ++j)
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) stage[(t + FF::TG * j + q * NSL) * FF::G + g] = res[j][q];
+    __syncthreads();
+    // row pair (2p, 2p + 1) of column gx is stored as P = a + i b and Q = conj a + i conj b
+    // (a, b the two rows): the row pass takes P for gx >= 0 and Q for the mirrored
+    // column -gx, one value per input
+    const int nc = tile.ncols, run = 4 * nc;
+    T* __restrict__ zs = Z + (long long)set * zset + bin.zoff + 4LL * tile.gx0;
+    for (int e = threadIdx.x; e < n * nc; e += kBlock) {
+      const int yb = e / run, rem = e - yb * run, c = rem >> 2, yi = rem & 3;
+      const int y0 = 4 * yb + (yi & 2);
+      const T a = stage[y0 * FF::G + c], b = stage[(y0 + 1) * FF::G + c];
+      zs[(long long)yb * 4 * cols + rem] =
+          (yi & 1) ? Cx<R>::mk(a.x + b.y, -a.y + b.x) : Cx<R>::mk(a.x - b.y, a.y + b.x);
+    }
+  }
 }
 
 namespace {
@@ -507,49 +506,72 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 constexpr int kRowIters = 4;
 }  // namespace
 
-int colpass_tile_columns(int n) { return fft_geom(n).G; }
+constexpr int kColTilesPerBlock = 2;
 
-template <typename R, bool DATA, typename GT>
-hipError_t launch_colpass(const abs_plan_s* p, const GT* grids, const float* w, int w_batched,
-                          int nsets, typename Cx<R>::T* Z, long long zset, const ColTile* tiles,
-                          const typename Cx<R>::T* tw, hipStream_t st) {
-  const char* base = static_cast<const char*>(p->dev);
-  const BinDev* bins = reinterpret_cast<const BinDev*>(base + p->dl.bins);
-  const dim3 grid((unsigned)p->tiles.size(), (unsigned)nsets);
-  const FftGeom geo = fft_geom(p->n);
-  const size_t lds = (size_t)geo.G * fft_lds_elems(p->n) * sizeof(typename Cx<R>::T);
-  if (p->n > 4096) {
-    auto k = colpass_kernel<R, 2, DATA, GT>;
-    hipError_t e = allow_lds(k, lds);
-    if (e != hipSuccess) return e;
-    k<<<grid, kBlock, lds, st>>>(grids, w, w_batched, p->wmode, p->n, p->log2n, tiles, bins, tw, Z, zset);
-  } else {
-    auto k = colpass_kernel<R, 1, DATA, GT>;
-    hipError_t e = allow_lds(k, lds);
-    if (e != hipSuccess) return e;
-    k<<<grid, kBlock, lds, st>>>(grids, w, w_batched, p->wmode, p->n, p->log2n, tiles, bins, tw, Z, zset);
-  }
+template <bool DATA, typename GT>
+hipError_t launch_herm(const abs_plan_s* p, const GT* grids, const float* w, int w_batched, int nsets,
+                       typename HermT<DATA>::T* xc, hipStream_t st) {
+  const int hm = p->hmax, lc = 2 * p->hmax + 1;
+  const dim3 grid((unsigned)((hm + kHx) / kHx), (unsigned)((lc + kHy - 1) / kHy), (unsigned)nsets);
+  herm_kernel<DATA, GT><<<grid, kBlock, 0, st>>>(grids, w, w_batched, p->wmode, p->n, hm, lc, xc);
   return hipGetLastError();
 }
 
-hipError_t launch_colpass_data(const abs_plan_s* p, const void* grids, int dtype, const float* w,
-                               int w_batched, int batch, float2* Z, long long zset, hipStream_t st) {
+template <typename R, int LOG2N>
+hipError_t launch_colpass_n(const abs_plan_s* p, int nsets, const typename HermT<sizeof(R) == 4>::T* xc,
+                            typename Cx<R>::T* Z, long long zset, const typename Cx<R>::T* tw,
+                            hipStream_t st) {
+  using FF = Fft<LOG2N>;
   const char* base = static_cast<const char*>(p->dev);
+  const BinDev* bins = reinterpret_cast<const BinDev*>(base + p->dl.bins);
   const ColTile* tiles = reinterpret_cast<const ColTile*>(base + p->dl.tiles);
+  const int ntiles = (int)p->tiles.size();
+  if (ntiles == 0) return hipSuccess;
+  const dim3 grid((unsigned)((ntiles + kColTilesPerBlock - 1) / kColTilesPerBlock), (unsigned)nsets);
+  const size_t lds = (size_t)FF::G * FF::L * sizeof(typename Cx<R>::T);
+  auto k = colpass_fixed_kernel<R, LOG2N>;
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
+  k<<<grid, kBlock, lds, st>>>(xc, p->hmax, 2 * p->hmax + 1, tiles, ntiles, kColTilesPerBlock, bins, tw,
+                               Z, zset);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_colpass(const abs_plan_s* p, int nsets, const typename HermT<sizeof(R) == 4>::T* xc,
+                          typename Cx<R>::T* Z, long long zset, const typename Cx<R>::T* tw,
+                          hipStream_t st) {
+  switch (p->log2n) {
+#define ABS_COL_CASE(L) \
+  case L: return launch_colpass_n<R, L>(p, nsets, xc, Z, zset, tw, st);
+    ABS_COL_CASE(4) ABS_COL_CASE(5) ABS_COL_CASE(6) ABS_COL_CASE(7) ABS_COL_CASE(8)
+    ABS_COL_CASE(9) ABS_COL_CASE(10) ABS_COL_CASE(11) ABS_COL_CASE(12) ABS_COL_CASE(13)
+#undef ABS_COL_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_colpass_data(const abs_plan_s* p, const void* grids, int dtype, const float* w,
+                               int w_batched, int batch, void* xc, float2* Z, long long zset,
+                               hipStream_t st) {
+  const char* base = static_cast<const char*>(p->dev);
   const float2* tw = reinterpret_cast<const float2*>(base + p->dl.tw);
-  if (dtype == ABS_C128)
-    return launch_colpass<float, true, double2>(p, static_cast<const double2*>(grids), w, w_batched,
-                                                batch, Z, zset, tiles, tw, st);
-  return launch_colpass<float, true, float2>(p, static_cast<const float2*>(grids), w, w_batched,
-                                             batch, Z, zset, tiles, tw, st);
+  float2* x = static_cast<float2*>(xc);
+  hipError_t e = dtype == ABS_C128
+                     ? launch_herm<true, double2>(p, static_cast<const double2*>(grids), w, w_batched, batch, x, st)
+                     : launch_herm<true, float2>(p, static_cast<const float2*>(grids), w, w_batched, batch, x, st);
+  if (e != hipSuccess) return e;
+  return launch_colpass<float>(p, batch, x, Z, zset, tw, st);
 }
 
 hipError_t launch_colpass_weight(const abs_plan_s* p, const float* w, int w_batched, int nsets,
-                                 double2* Z, long long zset, hipStream_t st) {
+                                 void* xc, double2* Z, long long zset, hipStream_t st) {
   const char* base = static_cast<const char*>(p->dev);
-  const ColTile* tiles = reinterpret_cast<const ColTile*>(base + p->dl.tiles);
   const double2* tw = reinterpret_cast<const double2*>(base + p->dl.tw64);
-  return launch_colpass<double, false, float2>(p, nullptr, w, w_batched, nsets, Z, zset, tiles, tw, st);
+  double* x = static_cast<double*>(xc);
+  hipError_t e = launch_herm<false, float2>(p, nullptr, w, w_batched, nsets, x, st);
+  if (e != hipSuccess) return e;
+  return launch_colpass<double>(p, nsets, x, Z, zset, tw, st);
 }
 
 template <typename R, int LOG2N>
@@ -561,7 +583,8 @@ hipError_t launch_rowpass_n(const abs_plan_s* p, int nsets, const typename Cx<R>
   const int per_block = FF::G * iters;
   const int nrb = (FF::N / 2 + per_block - 1) / per_block;
   const dim3 grid((unsigned)(p->nb * nrb), (unsigned)nsets);
-  const size_t lds = (size_t)FF::G * FF::L * sizeof(typename Cx<R>::T);
+  using T = typename Cx<R>::T;
+  const size_t lds = (size_t)FF::G * FF::L * sizeof(T) + (FF::N * sizeof(T) <= 16384 ? FF::N * sizeof(T) : 0);
   hipError_t e;
   if constexpr (sizeof(R) == 4) {
     if (fmax_bits) {   // FP16 split form: largest |F| per (set, ring)

@@ -169,6 +169,10 @@ WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_c
   off = al(off + (size_t)w.nisets * w.partset64 * 8);
   w.fmax = off;
   off = al(off + (size_t)batch * p->nb * 4);
+  // column-major Hermitian part for the column pass: 8 bytes per cell (FP32 complex for
+  // the data sets, FP64 real for the weight sets), reused by both in turn
+  w.xc = off;
+  off = al(off + (size_t)std::max(batch, w.nisets) * (size_t)(p->hmax + 1) * (size_t)(2 * p->hmax + 1) * 8);
   w.total = off;
   return w;
 }
@@ -594,6 +598,8 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
     p->radius[m] = cnt ? sr / (double)cnt : std::nan("");
   }
   p->ncols = acc;
+  p->hmax = 0;
+  for (int m = 0; m < nb; ++m) p->hmax = std::max(p->hmax, p->h[m]);
 
   // triplets i <= j <= k with at least one closed lattice triangle
   const bool wrap = (p->flags & ABS_ALLOW_WRAP) && p->edges[nb] > n / 3.0;
