@@ -274,7 +274,37 @@ grid_gather_kernel(int n, double du, double pit2, int batch, int b0,
       return make_float4(a.x, a.y, b.x, b.y);
     }
   };
-  if (gx > -half && gy > -half) {   // cells of the row / column -n/2 receive nothing
+  const bool inside = gx > -half && gy > -half;   // row / column -n/2 receive nothing
+  if (R == 0 && vw == nullptr && inside) {
+    // Nearest cell, unit weights: the records of g and of -g form one list of
+    // cd + cm entries, walked in chunks of kG with the next chunk's loads in flight.
+    // Terms are integers in FP64, so the order of the additions does not matter.
+    constexpr int kG = 4;
+    const int s0 = (int)c, s1 = ((gy ? n - iy : 0) * n) + (gx ? n - ix : 0);
+    const int p0 = start[s0], cd = start[s0 + 1] - p0;
+    const int q0 = start[s1], cm = start[s1 + 1] - q0;
+    const int ct = cd + cm;
+    auto rec = [&](int i) { return i < cd ? p0 + i : q0 + (i - cd); };
+    float4 cur[kG], nxt[kG];
+#pragma unroll
+    for (int u = 0; u < kG; ++u) cur[u] = u < ct ? load(rec(u)) : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i0 = 0; i0 < ct; i0 += kG) {
+#pragma unroll
+      for (int u = 0; u < kG; ++u)
+        nxt[u] = i0 + kG + u < ct ? load(rec(i0 + kG + u)) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {
+        const double sgn = i0 + u < cd ? 1.0 : -1.0;   // entries past ct are zero
+        ar0 += rint((double)cur[u].x * sv);
+        ai0 += sgn * rint((double)cur[u].y * sv);
+        ar1 += rint((double)cur[u].z * sv);
+        ai1 += sgn * rint((double)cur[u].w * sv);
+      }
+#pragma unroll
+      for (int u = 0; u < kG; ++u) cur[u] = nxt[u];
+    }
+    if (want_w) aw = rint(sw) * (double)ct;   // sw = 1 for integer counts
+  } else if (inside) {
     for (int mir = 0; mir < 2; ++mir) {
       const double sgn = mir ? -1.0 : 1.0;
       for (int dy = -R; dy <= R; ++dy)
