@@ -318,12 +318,11 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
         }
       continue;
     }
-    // Input k of the row pair: Z(gx, ya) + i Z(gx, ya + 1) at gx = k (k <= H) or
-    // gx = k - n (k >= n - H), using Z(-gx, y) = conj Z(gx, y); zero elsewhere.  Slab r
+    // Input k of the row pair (ya, ya + 1): Z(gx, ya) + i Z(gx, ya + 1) at gx = k (k <= H)
+    // or gx = k - n (k >= n - H), using Z(-gx, y) = conj Z(gx, y); zero elsewhere.  The
+    // column pass stored both forms, P(gx) = Z(gx, ya) + i Z(gx, ya + 1) at zp[4 gx] and
+    // Q(gx) = conj Z(gx, ya) + i conj Z(gx, ya + 1) next to it (blocks of 4 rows).  Slab r
     // of the first pass covers k in [r n/16, (r + 1) n/16); all-zero slabs are not read.
-    // the column pass stored the pair's inputs: P(gx) = Z(gx, ya) + i Z(gx, ya + 1) at
-    // zp[4 gx] and Q(gx) = conj Z(gx, ya) + i conj Z(gx, ya + 1), the input at -gx, next
-    // to it (blocks of 4 rows)
     const int pr = active ? pair : 0;
     const T* __restrict__ zp = zs + (long long)(pr >> 1) * 4 * cols + 2 * (pr & 1);
     auto in = [&](int k, int, int r) -> T {
