@@ -80,6 +80,7 @@ struct abs_plan_s {
   // contraction kernel (compiled at run time for this triplet list)
   int ngroups = 0;               // wave groups of the FP32 kernel; one wave per group
   int ngroups64 = 0;             // wave groups of the FP64 kernel (weight fields)
+  int waves = 4, waves64 = 4;    // waves (groups) per workgroup of the two kernels
   int pix_per_block = 0;         // pixels per contraction workgroup (data sets)
   int nblk = 0;                  // contraction pixel blocks per data set
   int pix_per_block64 = 0;       // the same for the FP64 weight sets (fewer sets: smaller blocks)

@@ -88,14 +88,14 @@ abs_status ensure_device(abs_plan_s* p) {
 
 // Workgroups: 4 triplet groups ("slice") x pixel block, numbered so that the slices of
 // one pixel block go to one XCD (the kernel decodes blockIdx.x the same way).
-abs_status launch_contract(hipFunction_t fn, int ngroups, const void* F, long long fset,
+abs_status launch_contract(hipFunction_t fn, int ngroups, int waves, const void* F, long long fset,
                            long long npix, int ppb, int nblk, int ntrip, int nsets, double* part,
                            hipStream_t st) {
   void* Fp = const_cast<void*>(F);
   void* args[] = {&Fp, &fset, &npix, &ppb, &part, &nblk, &ntrip};
-  const unsigned gz = (unsigned)((ngroups + 3) / 4);
+  const unsigned gz = (unsigned)((ngroups + waves - 1) / waves);
   const unsigned gx = 8u * (unsigned)((nblk + 7) / 8) * gz;
-  return hipModuleLaunchKernel(fn, gx, (unsigned)nsets, 1, kBlock, 1, 1, 0, st, args,
+  return hipModuleLaunchKernel(fn, gx, (unsigned)nsets, 1, (unsigned)(64 * waves), 1, 1, 0, st, args,
                                nullptr) == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
 
@@ -128,7 +128,7 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
     prof_begin(p, ABS_STAGE_CONTRACT, st);
     abs_status s;
     if (p->precision == ABS_FP32)
-      s = launch_contract(p->contract, p->ngroups, F, wl.fset, npix, p->pix_per_block, p->nblk,
+      s = launch_contract(p->contract, p->ngroups, p->waves, F, wl.fset, npix, p->pix_per_block, p->nblk,
                           (int)p->ntrip, batch, part, st);
     else
       s = launch_mfma_contract(p, F, wl.fset, batch, part, fmax, st) == hipSuccess ? ABS_OK
@@ -143,7 +143,7 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
       return ABS_ERR_DEVICE;
     if (launch_rowpass_f64(p, wl.nisets, Z, wl.zset, F, wl.fset, st) != hipSuccess)
       return ABS_ERR_DEVICE;
-    return launch_contract(p->contract64, p->ngroups64, F, wl.fset, npix, p->pix_per_block64,
+    return launch_contract(p->contract64, p->ngroups64, p->waves64, F, wl.fset, npix, p->pix_per_block64,
                            p->nblk64, (int)p->ntrip, wl.nisets,
                            reinterpret_cast<double*>(work + wl.part64), st);
   }

@@ -189,9 +189,10 @@ WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_c
 // abs_contract64 (FP64 fields and accumulators, for the weight fields).
 namespace {
 
-// Split ntrip triplets into G (a multiple of 4) contiguous groups whose register
-// estimate, rw * (slots + bins used), stays within the budget.
-std::vector<int> split_groups(const abs_plan_s* p, int rw) {
+// Split ntrip triplets into G contiguous groups whose register estimate, rw * (slots +
+// bins used), stays within the budget.  G is a multiple of the waves per workgroup
+// (*waves): 4, or 8 when more than 4 groups are needed (fewer slices re-read the fields).
+std::vector<int> split_groups(const abs_plan_s* p, int rw, int* waves) {
   const int T = (int)p->ntrip;
   const int kBudget = 200;
   auto cost_ok = [&](int t0, int t1) {
@@ -200,29 +201,39 @@ std::vector<int> split_groups(const abs_plan_s* p, int rw) {
       for (int q = 0; q < 3; ++q) bins.insert(p->trips[3 * t + q]);
     return rw * ((t1 - t0) + (int)bins.size()) <= kBudget;
   };
-  for (int G = 4; G <= 16384; G += 4) {
+  auto even = [&](int G) {
     std::vector<int> start(G + 1);
-    bool ok = true;
     for (int g = 0; g <= G; ++g) start[g] = (int)((int64_t)T * g / G);
+    return start;
+  };
+  for (int G = 4; G <= 16384; G += 4) {
+    std::vector<int> start = even(G);
+    bool ok = true;
     for (int g = 0; g < G && ok; ++g) ok = cost_ok(start[g], start[g + 1]);
-    if (ok) return start;
+    if (!ok) continue;
+    if (G == 4) {
+      *waves = 4;
+      return start;
+    }
+    *waves = 8;
+    return even((G + 7) / 8 * 8);   // more, smaller groups still fit the budget
   }
   return {};
 }
 
-// Kernel layout.  A workgroup is 4 waves (4 consecutive triplet groups, "slice" z) on
+// Kernel layout.  A workgroup is W waves (W consecutive triplet groups, "slice" z) on
 // one pixel block of one set.  The pixels are walked in chunks of 64 (one per lane);
 // the rings the slice uses (its union U_z) are staged chunk by chunk in LDS, each wave
-// loading every 4th of them, so every field value is read from memory once per
+// loading every W-th of them, so every field value is read from memory once per
 // workgroup.  A wave's loads for chunk c + 1 are issued two chunks ahead and stored to
 // the LDS stage that chunk c - 1 occupied, after the one barrier per chunk that also
 // publishes chunk c.  Workgroups are numbered so that the slices of one pixel block
 // run on one XCD (blocks are dealt to the 8 XCDs round robin), where they share L2.
-void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, const char* name,
+void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, int W, const char* name,
                  const char* R, std::string& s) {
   char buf[1024];
-  const int G = (int)start.size() - 1;   // a multiple of 4
-  const int GZ = G / 4;
+  const int G = (int)start.size() - 1;   // a multiple of W
+  const int GZ = G / W;
   const bool dbl = std::strcmp(R, "double") == 0;
   const int kRed = dbl ? 16 : 32;
   std::vector<std::vector<int>> gbins(G), U(GZ);
@@ -235,39 +246,42 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, const char*
   int NU = 1;
   for (int z = 0; z < GZ; ++z) {
     std::set<int> b;
-    for (int g = 4 * z; g < 4 * z + 4; ++g) b.insert(gbins[g].begin(), gbins[g].end());
+    for (int g = W * z; g < W * z + W; ++g) b.insert(gbins[g].begin(), gbins[g].end());
     U[z].assign(b.begin(), b.end());
     NU = std::max(NU, (int)U[z].size());
   }
   std::snprintf(buf, sizeof buf,
-                "extern \"C\" __global__ void __launch_bounds__(256) %s(\n"
+                "extern \"C\" __global__ void __launch_bounds__(%d) %s(\n"
                 "    const %s* __restrict__ F, long long set_stride, long long npix, int ppb,\n"
-                "    double* __restrict__ part, int nblk, int ntrip) {\n", name, R);
+                "    double* __restrict__ part, int nblk, int ntrip) {\n", 64 * W, name, R);
   s += buf;
+  // LDS: the staging area during the pixel walk, the reduction rows afterwards
+  const size_t esz = dbl ? 8 : 4;
+  const size_t lds = std::max((size_t)2 * NU * 64 * esz, (size_t)W * kRed * 65 * esz);
   std::snprintf(buf, sizeof buf,
                 "  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;\n"
                 "  const int xcd = blockIdx.x & 7, kx = blockIdx.x >> 3;\n"
                 "  const int blk = xcd + 8 * (kx / %d), z = kx %% %d;\n"
                 "  if (blk >= nblk) return;\n"
-                "  const int grp = z * 4 + wave;\n"
+                "  const int grp = z * %d + wave;\n"
                 "  const long long set = blockIdx.y;\n"
                 "  const long long p0 = (long long)blk * ppb;\n"
                 "  const long long p1 = (p0 + ppb < npix) ? p0 + ppb : npix;\n"
                 "  const int nch = (int)((p1 - p0) / 64);\n"
                 "  const %s* __restrict__ Fs = F + set * set_stride + p0;\n"
                 "  double* __restrict__ out = part + (set * nblk + blk) * (long long)ntrip;\n"
-                "  __shared__ %s red_all[4 * %d * 65];\n"
-                "  __shared__ %s stg[2][%d][64];\n"
-                "  %s* red = red_all + wave * %d * 65;\n"
-                "  switch (grp) {\n", GZ, GZ, R, R, kRed, R, NU, R, kRed);
+                "  __shared__ %s lds_all[%zu];\n"
+                "  %s (*stg)[%d][64] = reinterpret_cast<%s (*)[%d][64]>(lds_all);\n"
+                "  %s* red = lds_all + wave * %d * 65;\n"
+                "  switch (grp) {\n", GZ, GZ, W, R, R, lds / esz, R, NU, R, NU, R, kRed);
   s += buf;
   for (int g = 0; g < G; ++g) {
-    const int z = g / 4, w = g % 4;
+    const int z = g / W, w = g % W;
     const int t0 = start[g], t1 = start[g + 1];
     const std::vector<int>& Uz = U[z];
     auto slot = [&](int m) { return (int)(std::lower_bound(Uz.begin(), Uz.end(), m) - Uz.begin()); };
     std::vector<int> mine;   // rings this wave stages
-    for (int k = w; k < (int)Uz.size(); k += 4) mine.push_back(Uz[k]);
+    for (int k = w; k < (int)Uz.size(); k += W) mine.push_back(Uz[k]);
     std::snprintf(buf, sizeof buf, "  case %d: {\n", g);
     s += buf;
     for (int t = t0; t < t1; ++t) {
@@ -340,6 +354,8 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, const char*
     s += loads("e", "c + 4");
     s += compute("1");
     s += "    }\n";
+    // the reduction rows overlay the staging area: every wave has finished reading it
+    s += "    __syncthreads();\n";
     // Cross-lane sums through LDS, kRed accumulators at a time: every lane stores its
     // values as one row per accumulator, then lane l < kRed adds row l in FP64.  One
     // store per accumulator keeps the generated code (and its compile time) small.
@@ -367,10 +383,13 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, const char*
 }  // namespace
 
 bool build_jit_source(abs_plan_s* p) {
-  const std::vector<int> g32 = split_groups(p, 1), g64 = split_groups(p, 2);
+  int w32 = 4, w64 = 4;
+  const std::vector<int> g32 = split_groups(p, 1, &w32), g64 = split_groups(p, 2, &w64);
   if (g32.empty() || g64.empty()) return false;
   p->ngroups = (int)g32.size() - 1;
   p->ngroups64 = (int)g64.size() - 1;
+  p->waves = w32;
+  p->waves64 = w64;
   std::string s;
   s.reserve(400000);
   s += "// generated: triplet contraction for one ring-triplet list\n";
@@ -381,8 +400,8 @@ bool build_jit_source(abs_plan_s* p) {
        "  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, \"wavefront\");\n"
        "  __builtin_amdgcn_wave_barrier();\n}\n";
   // the FP32 kernel serves the FP32 data path; the weight fields always use FP64
-  if (p->precision == ABS_FP32) emit_kernel(p, g32, "abs_contract", "float", s);
-  emit_kernel(p, g64, "abs_contract64", "double", s);
+  if (p->precision == ABS_FP32) emit_kernel(p, g32, w32, "abs_contract", "float", s);
+  emit_kernel(p, g64, w64, "abs_contract64", "double", s);
   p->jit_src.swap(s);
   return true;
 }
