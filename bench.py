@@ -26,9 +26,12 @@ WORKLOADS = {
     "mwa1024": dict(n=1024, nbins=20, lmin=46.0, lmax=1320.0, batch=16, cfg=1,
                     desc="MWA-shaped single channel: 1024x1024 c64 grid, 20 log rings 46<=l<1320, "
                          "Poisson baseline mask + SNR-5 noise, INV_COUNT weights"),
-    # precision-form shapes in FP32: 4096^2, 32 log rings, edges x4
+    # precision-form shapes: 4096^2, 32 log rings, edges x4
     "mwa4096": dict(n=4096, nbins=32, lmin=4 * 46.0, lmax=4 * 1320.0, batch=2, cfg=2,
                     desc="MWA-shaped 4096x4096 c64 grid, 32 log rings 4x(46<=l<1320), INV_COUNT weights"),
+    # large ensemble shapes: 8192^2, 64 log rings, edges x8 (realisations in batches of 2)
+    "mwa8192": dict(n=8192, nbins=64, lmin=8 * 46.0, lmax=8 * 1320.0, batch=2, cfg=4,
+                    desc="MWA-shaped 8192x8192 c64 grid, 64 log rings 8x(46<=l<1320), INV_COUNT weights"),
 }
 class HipEvents:
     """Raw HIP events (the library records them on the call's stream)."""
@@ -147,12 +150,12 @@ def serve_bench(a):
     prec = {"fp32": A.FP32, "bf16x3": A.BF16X3, "fp16x3": A.FP16X3}[a.precision]
     slots, max_batch = 4, 8
     # compile every plan in worker processes before the GPU is touched
-    from paper_2412_02246_amd.jit import compile_plans
+    from paper_2412_02246_amd.jit import compile_parts
     keys = list(dict.fromkeys((n, e) for n, e, _ in specs))
     kw = dict(wmode=A.W_INV_COUNT, precision=prec, max_batch=max_batch)
     t0 = time.perf_counter()
     plans = [A.Plan(n, e, **kw) for n, e in keys]
-    compile_plans(plans, [(n, e, kw) for n, e in keys], workers=16)
+    compile_parts(plans, [(n, e, kw) for n, e in keys], workers=16)
     print("serve: %d plans compiled in %.1f s" % (len(plans), time.perf_counter() - t0),
           file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
@@ -235,15 +238,21 @@ def main():
     n, nb, batch = W["n"], W["nbins"], (a.batch or W["batch"])
     edges = (W["lmin"] / (2 * np.pi)) * ((W["lmax"] / W["lmin"]) ** (np.arange(nb + 1) / nb))
     nvis = n * n
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda", 0)
     print("bench: workload %s n=%d rings=%d batch=%d nvis=%d" % (a.workload, n, nb, batch, nvis),
           file=sys.stderr, flush=True)
-    uv, vis = synth.mwa_visibilities(n, nvis, edges[-1], synth.seed_for(W["cfg"], 0), batch=batch)
     prec = {"fp32": A.FP32, "bf16x3": A.BF16X3, "fp16x3": A.FP16X3}[a.precision]
-    plan = A.Plan(n, edges, wmode=A.W_INV_COUNT, max_batch=batch, precision=prec).bind()
-    print("bench: plan ntrip=%d npairs=%d; inputs generated" % (plan.ntrip, plan.npairs),
-          file=sys.stderr, flush=True)
+    # the plan's contraction code is compiled in worker processes before this process
+    # touches the GPU
+    t0 = time.perf_counter()
+    plan = A.Plan(n, edges, wmode=A.W_INV_COUNT, max_batch=batch, precision=prec)
+    plan.compile(workers=16)
+    print("bench: plan ntrip=%d npairs=%d, %d code parts compiled in %.1f s" %
+          (plan.ntrip, plan.npairs, plan.jit_parts, time.perf_counter() - t0), file=sys.stderr, flush=True)
+    uv, vis = synth.mwa_visibilities(n, nvis, edges[-1], synth.seed_for(W["cfg"], 0), batch=batch)
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    plan.bind()
+    print("bench: inputs generated", file=sys.stderr, flush=True)
     uv_d = torch.from_numpy(uv).to(dev)
     vis_d = torch.from_numpy(vis).to(dev)
 

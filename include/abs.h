@@ -90,6 +90,7 @@ typedef struct abs_plan_info {
   int64_t plan_bytes;   /* device bytes abs_plan_bind needs                           */
   double norm;          /* the A actually used                                        */
   int64_t mfma_tiles;   /* 16 x 16 output tiles of the precision-form contraction     */
+  int32_t jit_parts;    /* separately compiled pieces of the contraction code         */
 } abs_plan_info;
 
 /* Build a plan on the host: rings (Sec. 2), the triplet list with an exact lattice
@@ -112,23 +113,30 @@ abs_status abs_plan_info_get(abs_plan_t plan, abs_plan_info* out);
  *   radius   double [nbins]     unweighted mean |g| of each ring's lattice cells */
 abs_status abs_plan_triplets(abs_plan_t plan, int32_t* ijk, double* labels, double* radius);
 
-/* Compile the plan's contraction kernel for gfx950 (host only, no device needed).
- * abs_plan_bind calls it when it has not been called.  Errors: ABS_ERR_JIT. */
+/* Compile the plan's contraction code for gfx950 (host only, no device needed): every
+ * part in turn.  The code is generated per triplet list and cut into jit_parts pieces
+ * (runs of triplet groups) that compile independently.  abs_plan_bind compiles what has
+ * not been compiled or installed.  Errors: ABS_ERR_JIT. */
 abs_status abs_plan_compile(abs_plan_t plan);
 
-/* The plan's compiled contraction code object, for caching or for compiling plans in
- * several processes (run-time compilation is serialised within one process).
- *   key    out: identifies the generated source and compile options (may be NULL)
- *   dst    NULL: compile if needed and return the size in *bytes; otherwise copy the code
- *          object into dst (host, *bytes long) and set *bytes to its size
- * Errors: ABS_ERR_INVALID (dst given before compilation), ABS_ERR_NOMEM (*bytes too
- * small), ABS_ERR_JIT. */
-abs_status abs_plan_code(abs_plan_t plan, uint64_t* key, void* dst, size_t* bytes);
+/* Compile one part, 0 <= part < jit_parts.  Errors: ABS_ERR_INVALID, ABS_ERR_JIT. */
+abs_status abs_plan_compile_part(abs_plan_t plan, int32_t part);
 
-/* Install a code object obtained from abs_plan_code of an identical plan (same key);
- * abs_plan_bind then loads it instead of compiling.  The bytes are copied.
- * Errors: ABS_ERR_INVALID (null, empty or key mismatch). */
-abs_status abs_plan_set_code(abs_plan_t plan, uint64_t key, const void* src, size_t bytes);
+/* A part's compiled code object, for caching or for compiling the parts of one or many
+ * plans in several processes (run-time compilation is serialised within one process).
+ *   part   0 <= part < jit_parts
+ *   key    out: identifies the part's generated source and compile options (may be NULL)
+ *   dst    NULL: compile the part if needed and return the size in *bytes; otherwise
+ *          copy the code object into dst (host, *bytes long) and set *bytes to its size
+ * Errors: ABS_ERR_INVALID (bad part, dst given before compilation), ABS_ERR_NOMEM
+ * (*bytes too small), ABS_ERR_JIT. */
+abs_status abs_plan_code(abs_plan_t plan, int32_t part, uint64_t* key, void* dst, size_t* bytes);
+
+/* Install a part's code object obtained from abs_plan_code of an identical plan (same
+ * key); abs_plan_bind then loads it instead of compiling.  The bytes are copied.
+ * Errors: ABS_ERR_INVALID (null, empty, bad part or key mismatch). */
+abs_status abs_plan_set_code(abs_plan_t plan, int32_t part, uint64_t key, const void* src,
+                             size_t bytes);
 
 /* Attach caller-owned device memory of at least plan_bytes bytes (256-byte aligned)
  * to the plan, upload its tables on `stream` and load the compiled kernel on the

@@ -28,7 +28,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nbins", ctypes.c_int32), ("ntrip", ctypes.c_int64),
                 ("npairs", ctypes.c_int64), ("ncols", ctypes.c_int64),
                 ("plan_bytes", ctypes.c_int64), ("norm", ctypes.c_double),
-                ("mfma_tiles", ctypes.c_int64)]
+                ("mfma_tiles", ctypes.c_int64), ("jit_parts", ctypes.c_int32)]
 
 
 class AbsError(RuntimeError):
@@ -57,8 +57,9 @@ def lib():
         "abs_plan_info_get": [_P, ctypes.POINTER(PlanInfo)],
         "abs_plan_triplets": [_P, _P, _P, _P],
         "abs_plan_compile": [_P],
-        "abs_plan_code": [_P, ctypes.POINTER(ctypes.c_uint64), _P, ctypes.POINTER(sz)],
-        "abs_plan_set_code": [_P, ctypes.c_uint64, _P, sz],
+        "abs_plan_compile_part": [_P, i32],
+        "abs_plan_code": [_P, i32, ctypes.POINTER(ctypes.c_uint64), _P, ctypes.POINTER(sz)],
+        "abs_plan_set_code": [_P, i32, ctypes.c_uint64, _P, sz],
         "abs_plan_bind": [_P, _P, sz, _P],
         "abs_estimate_workspace": [_P, i32, i32, i32, ctypes.POINTER(sz)],
         "abs_grid_workspace": [_P, i64, i32, ctypes.POINTER(sz)],

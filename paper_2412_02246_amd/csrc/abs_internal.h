@@ -38,6 +38,17 @@ struct DevLayout {
 };
 
 // Offsets (bytes) of the buffers inside the abs_estimate workspace.
+// One separately compiled piece of the contraction: a run of slices of one kernel kind.
+struct JitPart {
+  int kind = 0;                  // 0: FP32 data fields, 1: FP64 weight fields
+  int z0 = 0, z1 = 0;            // slices [z0, z1) of that kind
+  std::string src;               // generated source
+  std::vector<char> code;        // code object
+  bool compiled = false;
+  hipModule_t module = nullptr;
+  hipFunction_t fn = nullptr;
+};
+
 struct WorkLayout {
   int nsets;          // D sets (one per grid) followed by I sets
   int nisets;
@@ -85,16 +96,11 @@ struct abs_plan_s {
   int nblk = 0;                  // contraction pixel blocks per data set
   int pix_per_block64 = 0;       // the same for the FP64 weight sets (fewer sets: smaller blocks)
   int nblk64 = 0;
-  std::string jit_src;
-  std::vector<char> jit_code;
-  bool compiled = false;
+  std::vector<abs_impl::JitPart> parts;   // contraction code, compiled per part
   // device binding
   abs_impl::DevLayout dl{};
   void* dev = nullptr;
   int device = -1;
-  hipModule_t module = nullptr;
-  hipFunction_t contract = nullptr;     // FP32 data fields
-  hipFunction_t contract64 = nullptr;   // FP64 weight fields
   // timing hook: events recorded around one stage's launches (see abs_profile)
   hipEvent_t prof[4][2] = {};
 };
@@ -102,8 +108,8 @@ struct abs_plan_s {
 namespace abs_impl {
 // plan.cpp
 bool build_jit_source(abs_plan_s* p);
-abs_status compile_jit(abs_plan_s* p);
-uint64_t jit_key(const abs_plan_s* p);
+abs_status compile_jit(abs_plan_s* p, int part);
+uint64_t jit_key(const abs_plan_s* p, int part);
 WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_counts);
 void build_mfma_tables(abs_plan_s* p);
 inline void prof_begin(const abs_plan_s* p, int stage, hipStream_t st) {

@@ -86,17 +86,22 @@ abs_status ensure_device(abs_plan_s* p) {
   return ABS_OK;
 }
 
-// Workgroups: 4 triplet groups ("slice") x pixel block, numbered so that the slices of
-// one pixel block go to one XCD (the kernel decodes blockIdx.x the same way).
-abs_status launch_contract(hipFunction_t fn, int ngroups, int waves, const void* F, long long fset,
+// Workgroups: one slice of `waves` triplet groups x one pixel block, numbered so that the
+// slices of one pixel block go to one XCD (the kernel decodes blockIdx.x the same way);
+// one launch per compiled part of the given kind.
+abs_status launch_contract(const abs_plan_s* p, int kind, int waves, const void* F, long long fset,
                            long long npix, int ppb, int nblk, int ntrip, int nsets, double* part,
                            hipStream_t st) {
   void* Fp = const_cast<void*>(F);
   void* args[] = {&Fp, &fset, &npix, &ppb, &part, &nblk, &ntrip};
-  const unsigned gz = (unsigned)((ngroups + waves - 1) / waves);
-  const unsigned gx = 8u * (unsigned)((nblk + 7) / 8) * gz;
-  return hipModuleLaunchKernel(fn, gx, (unsigned)nsets, 1, (unsigned)(64 * waves), 1, 1, 0, st, args,
-                               nullptr) == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
+  for (const JitPart& q : p->parts) {
+    if (q.kind != kind) continue;
+    const unsigned gx = 8u * (unsigned)((nblk + 7) / 8) * (unsigned)(q.z1 - q.z0);
+    if (hipModuleLaunchKernel(q.fn, gx, (unsigned)nsets, 1, (unsigned)(64 * waves), 1, 1, 0, st, args,
+                              nullptr) != hipSuccess)
+      return ABS_ERR_DEVICE;
+  }
+  return ABS_OK;
 }
 
 // Data sets (FP32) for `batch` grids, then `nisets` weight sets (FP64); partials of
@@ -128,7 +133,7 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
     prof_begin(p, ABS_STAGE_CONTRACT, st);
     abs_status s;
     if (p->precision == ABS_FP32)
-      s = launch_contract(p->contract, p->ngroups, p->waves, F, wl.fset, npix, p->pix_per_block, p->nblk,
+      s = launch_contract(p, 0, p->waves, F, wl.fset, npix, p->pix_per_block, p->nblk,
                           (int)p->ntrip, batch, part, st);
     else
       s = launch_mfma_contract(p, F, wl.fset, batch, part, fmax, st) == hipSuccess ? ABS_OK
@@ -143,7 +148,7 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
       return ABS_ERR_DEVICE;
     if (launch_rowpass_f64(p, wl.nisets, Z, wl.zset, F, wl.fset, st) != hipSuccess)
       return ABS_ERR_DEVICE;
-    return launch_contract(p->contract64, p->ngroups64, p->waves64, F, wl.fset, npix, p->pix_per_block64,
+    return launch_contract(p, 1, p->waves64, F, wl.fset, npix, p->pix_per_block64,
                            p->nblk64, (int)p->ntrip, wl.nisets,
                            reinterpret_cast<double*>(work + wl.part64), st);
   }
@@ -160,25 +165,25 @@ abs_status abs_plan_bind(abs_plan_t p, void* mem, size_t bytes, void* stream) {
   if (!p || !mem) return ABS_ERR_INVALID;
   if (reinterpret_cast<uintptr_t>(mem) & 255) return ABS_ERR_INVALID;
   if (bytes < p->dl.total) return ABS_ERR_NOMEM;
-  abs_status s = compile_jit(p);
-  if (s != ABS_OK) return s;
+  for (int k = 0; k < (int)p->parts.size(); ++k) {
+    const abs_status s = compile_jit(p, k);
+    if (s != ABS_OK) return s;
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return ABS_ERR_DEVICE;
-  if (p->module) {
-    (void)hipModuleUnload(p->module);
-    p->module = nullptr;
-    p->contract = nullptr;
+  for (JitPart& q : p->parts) {
+    if (q.module) {
+      (void)hipModuleUnload(q.module);
+      q.module = nullptr;
+      q.fn = nullptr;
+    }
+    if (hipModuleLoadData(&q.module, q.code.data()) != hipSuccess) {
+      q.module = nullptr;
+      return ABS_ERR_JIT;
+    }
+    if (hipModuleGetFunction(&q.fn, q.module, "abs_contract") != hipSuccess) return ABS_ERR_JIT;
   }
-  if (hipModuleLoadData(&p->module, p->jit_code.data()) != hipSuccess) {
-    p->module = nullptr;
-    return ABS_ERR_JIT;
-  }
-  p->contract = nullptr;
-  if ((p->precision == ABS_FP32 &&
-       hipModuleGetFunction(&p->contract, p->module, "abs_contract") != hipSuccess) ||
-      hipModuleGetFunction(&p->contract64, p->module, "abs_contract64") != hipSuccess)
-    return ABS_ERR_JIT;
   // host image of the tables
   std::vector<char> img(p->dl.total, 0);
   float2* tw = reinterpret_cast<float2*>(img.data() + p->dl.tw);

@@ -229,11 +229,12 @@ std::vector<int> split_groups(const abs_plan_s* p, int rw, int* waves) {
 // the LDS stage that chunk c - 1 occupied, after the one barrier per chunk that also
 // publishes chunk c.  Workgroups are numbered so that the slices of one pixel block
 // run on one XCD (blocks are dealt to the 8 XCDs round robin), where they share L2.
-void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, int W, const char* name,
-                 const char* R, std::string& s) {
+void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, int W, int z0, int z1,
+                 const char* name, const char* R, std::string& s) {
   char buf[1024];
   const int G = (int)start.size() - 1;   // a multiple of W
   const int GZ = G / W;
+  const int PZ = z1 - z0;                 // slices of this part
   const bool dbl = std::strcmp(R, "double") == 0;
   const int kRed = dbl ? 16 : 32;
   std::vector<std::vector<int>> gbins(G), U(GZ);
@@ -244,7 +245,7 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, int W, cons
     gbins[g].assign(b.begin(), b.end());
   }
   int NU = 1;
-  for (int z = 0; z < GZ; ++z) {
+  for (int z = z0; z < z1; ++z) {
     std::set<int> b;
     for (int g = W * z; g < W * z + W; ++g) b.insert(gbins[g].begin(), gbins[g].end());
     U[z].assign(b.begin(), b.end());
@@ -261,7 +262,7 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, int W, cons
   std::snprintf(buf, sizeof buf,
                 "  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;\n"
                 "  const int xcd = blockIdx.x & 7, kx = blockIdx.x >> 3;\n"
-                "  const int blk = xcd + 8 * (kx / %d), z = kx %% %d;\n"
+                "  const int blk = xcd + 8 * (kx / %d), z = %d + kx %% %d;\n"
                 "  if (blk >= nblk) return;\n"
                 "  const int grp = z * %d + wave;\n"
                 "  const long long set = blockIdx.y;\n"
@@ -273,9 +274,9 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, int W, cons
                 "  __shared__ %s lds_all[%zu];\n"
                 "  %s (*stg)[%d][64] = reinterpret_cast<%s (*)[%d][64]>(lds_all);\n"
                 "  %s* red = lds_all + wave * %d * 65;\n"
-                "  switch (grp) {\n", GZ, GZ, W, R, R, lds / esz, R, NU, R, NU, R, kRed);
+                "  switch (grp) {\n", PZ, z0, PZ, W, R, R, lds / esz, R, NU, R, NU, R, kRed);
   s += buf;
-  for (int g = 0; g < G; ++g) {
+  for (int g = W * z0; g < W * z1; ++g) {
     const int z = g / W, w = g % W;
     const int t0 = start[g], t1 = start[g + 1];
     const std::vector<int>& Uz = U[z];
@@ -382,6 +383,10 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, int W, cons
 
 }  // namespace
 
+// Slices per separately compiled part: bounds the size (and compile time) of one
+// generated module, so that large plans compile as several parts in parallel processes.
+constexpr int kSlicesPerPart = 4;
+
 bool build_jit_source(abs_plan_s* p) {
   int w32 = 4, w64 = 4;
   const std::vector<int> g32 = split_groups(p, 1, &w32), g64 = split_groups(p, 2, &w64);
@@ -390,24 +395,35 @@ bool build_jit_source(abs_plan_s* p) {
   p->ngroups64 = (int)g64.size() - 1;
   p->waves = w32;
   p->waves64 = w64;
-  std::string s;
-  s.reserve(400000);
-  s += "// generated: triplet contraction for one ring-triplet list\n";
-  s += "__device__ __forceinline__ float abs_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }\n"
-       "__device__ __forceinline__ double abs_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }\n"
-       "// orders a wave's LDS stores before its loads from other lanes\n"
-       "__device__ __forceinline__ void abs_wave_sync() {\n"
-       "  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, \"wavefront\");\n"
-       "  __builtin_amdgcn_wave_barrier();\n}\n";
+  const std::string head =
+      "// generated: triplet contraction for one ring-triplet list\n"
+      "__device__ __forceinline__ float abs_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }\n"
+      "__device__ __forceinline__ double abs_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }\n"
+      "// orders a wave's LDS stores before its loads from other lanes\n"
+      "__device__ __forceinline__ void abs_wave_sync() {\n"
+      "  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, \"wavefront\");\n"
+      "  __builtin_amdgcn_wave_barrier();\n}\n";
+  p->parts.clear();
+  auto add = [&](int kind, const std::vector<int>& start, int W, const char* R) {
+    const int GZ = ((int)start.size() - 1) / W;
+    for (int z0 = 0; z0 < GZ; z0 += kSlicesPerPart) {
+      JitPart part;
+      part.kind = kind;
+      part.z0 = z0;
+      part.z1 = std::min(GZ, z0 + kSlicesPerPart);
+      part.src = head;
+      emit_kernel(p, start, W, part.z0, part.z1, "abs_contract", R, part.src);
+      p->parts.push_back(std::move(part));
+    }
+  };
   // the FP32 kernel serves the FP32 data path; the weight fields always use FP64
-  if (p->precision == ABS_FP32) emit_kernel(p, g32, w32, "abs_contract", "float", s);
-  emit_kernel(p, g64, w64, "abs_contract64", "double", s);
-  p->jit_src.swap(s);
+  if (p->precision == ABS_FP32) add(0, g32, w32, "float");
+  add(1, g64, w64, "double");
   return true;
 }
 
-// FNV-1a of the generated source and the compile options: identifies a code object.
-uint64_t jit_key(const abs_plan_s* p) {
+// FNV-1a of a part's generated source and the compile options: identifies a code object.
+uint64_t jit_key(const abs_plan_s* p, int part) {
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](const char* d, size_t n) {
     for (size_t i = 0; i < n; ++i) {
@@ -415,18 +431,18 @@ uint64_t jit_key(const abs_plan_s* p) {
       h *= 1099511628211ull;
     }
   };
-  mix(p->jit_src.data(), p->jit_src.size());
+  const std::string& src = p->parts[part].src;
+  mix(src.data(), src.size());
   const char tag[] = "gfx950 -O3 -packed-fp32-ops";
   mix(tag, sizeof tag);
   return h;
 }
 
-abs_status compile_jit(abs_plan_s* p) {
-  if (p->compiled) return ABS_OK;
-  if (p->jit_src.empty() && !build_jit_source(p)) return ABS_ERR_JIT;
+abs_status compile_jit(abs_plan_s* p, int part) {
+  JitPart& q = p->parts[part];
+  if (q.compiled) return ABS_OK;
   hiprtcProgram prog;
-  if (hiprtcCreateProgram(&prog, p->jit_src.c_str(), "abs_contract.hip", 0, nullptr, nullptr) !=
-      HIPRTC_SUCCESS)
+  if (hiprtcCreateProgram(&prog, q.src.c_str(), "abs_contract.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
     return ABS_ERR_JIT;
   // Packed FP32 instructions are disabled for every kernel of this library.
   const char* opts[] = {"--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature",
@@ -441,24 +457,24 @@ abs_status compile_jit(abs_plan_s* p) {
     hiprtcDestroyProgram(&prog);
     return ABS_ERR_JIT;
   }
-  p->jit_code.resize(sz);
-  const bool ok = hiprtcGetCode(prog, p->jit_code.data()) == HIPRTC_SUCCESS;
+  q.code.resize(sz);
+  const bool ok = hiprtcGetCode(prog, q.code.data()) == HIPRTC_SUCCESS;
   hiprtcDestroyProgram(&prog);
   if (!ok) return ABS_ERR_JIT;
   // ABS_JIT_DUMP=<directory>: keep the generated source and code object for inspection.
   if (const char* dir = std::getenv("ABS_JIT_DUMP")) {
     const std::string base = std::string(dir) + "/abs_contract_n" + std::to_string(p->n) + "_t" +
-                             std::to_string(p->ntrip);
+                             std::to_string(p->ntrip) + "_p" + std::to_string(part);
     if (FILE* f = std::fopen((base + ".hip").c_str(), "wb")) {
-      std::fwrite(p->jit_src.data(), 1, p->jit_src.size(), f);
+      std::fwrite(q.src.data(), 1, q.src.size(), f);
       std::fclose(f);
     }
     if (FILE* f = std::fopen((base + ".co").c_str(), "wb")) {
-      std::fwrite(p->jit_code.data(), 1, p->jit_code.size(), f);
+      std::fwrite(q.code.data(), 1, q.code.size(), f);
       std::fclose(f);
     }
   }
-  p->compiled = true;
+  q.compiled = true;
   return ABS_OK;
 }
 
@@ -720,6 +736,7 @@ abs_status abs_plan_info_get(abs_plan_t p, abs_plan_info* o) {
   o->plan_bytes = (int64_t)p->dl.total;
   o->norm = p->norm;
   o->mfma_tiles = (int64_t)p->mt_ptile.size();
+  o->jit_parts = (int32_t)p->parts.size();
   return ABS_OK;
 }
 
@@ -733,32 +750,43 @@ abs_status abs_plan_triplets(abs_plan_t p, int32_t* ijk, double* labels, double*
 
 abs_status abs_plan_compile(abs_plan_t p) {
   if (!p) return ABS_ERR_INVALID;
-  return compile_jit(p);
-}
-
-abs_status abs_plan_code(abs_plan_t p, uint64_t* key, void* dst, size_t* bytes) {
-  if (!p || !bytes) return ABS_ERR_INVALID;
-  if (key) *key = jit_key(p);
-  if (!dst) {
-    if (!p->compiled) {
-      const abs_status s = compile_jit(p);
-      if (s != ABS_OK) return s;
-    }
-    *bytes = p->jit_code.size();
-    return ABS_OK;
+  for (int k = 0; k < (int)p->parts.size(); ++k) {
+    const abs_status s = compile_jit(p, k);
+    if (s != ABS_OK) return s;
   }
-  if (!p->compiled) return ABS_ERR_INVALID;
-  if (*bytes < p->jit_code.size()) return ABS_ERR_NOMEM;
-  std::memcpy(dst, p->jit_code.data(), p->jit_code.size());
-  *bytes = p->jit_code.size();
   return ABS_OK;
 }
 
-abs_status abs_plan_set_code(abs_plan_t p, uint64_t key, const void* src, size_t bytes) {
-  if (!p || !src || bytes == 0) return ABS_ERR_INVALID;
-  if (key != jit_key(p)) return ABS_ERR_INVALID;   // compiled for another triplet list
-  p->jit_code.assign(static_cast<const char*>(src), static_cast<const char*>(src) + bytes);
-  p->compiled = true;
+abs_status abs_plan_compile_part(abs_plan_t p, int32_t part) {
+  if (!p || part < 0 || part >= (int)p->parts.size()) return ABS_ERR_INVALID;
+  return compile_jit(p, part);
+}
+
+abs_status abs_plan_code(abs_plan_t p, int32_t part, uint64_t* key, void* dst, size_t* bytes) {
+  if (!p || !bytes || part < 0 || part >= (int)p->parts.size()) return ABS_ERR_INVALID;
+  JitPart& q = p->parts[part];
+  if (key) *key = jit_key(p, part);
+  if (!dst) {
+    if (!q.compiled) {
+      const abs_status s = compile_jit(p, part);
+      if (s != ABS_OK) return s;
+    }
+    *bytes = q.code.size();
+    return ABS_OK;
+  }
+  if (!q.compiled) return ABS_ERR_INVALID;
+  if (*bytes < q.code.size()) return ABS_ERR_NOMEM;
+  std::memcpy(dst, q.code.data(), q.code.size());
+  *bytes = q.code.size();
+  return ABS_OK;
+}
+
+abs_status abs_plan_set_code(abs_plan_t p, int32_t part, uint64_t key, const void* src, size_t bytes) {
+  if (!p || !src || bytes == 0 || part < 0 || part >= (int)p->parts.size()) return ABS_ERR_INVALID;
+  if (key != jit_key(p, part)) return ABS_ERR_INVALID;   // compiled for another triplet list
+  JitPart& q = p->parts[part];
+  q.code.assign(static_cast<const char*>(src), static_cast<const char*>(src) + bytes);
+  q.compiled = true;
   return ABS_OK;
 }
 
@@ -771,15 +799,15 @@ abs_status abs_estimate_workspace(abs_plan_t p, int32_t batch, int32_t w_batched
 
 abs_status abs_destroy(abs_plan_t p) {
   if (!p) return ABS_OK;
-  if (p->module) {
+  bool loaded = false;
+  for (const JitPart& q : p->parts) loaded = loaded || q.module;
+  if (loaded) {
     int cur = -1;
-    if (hipGetDevice(&cur) == hipSuccess && p->device >= 0 && cur != p->device) {
-      (void)hipSetDevice(p->device);
-      (void)hipModuleUnload(p->module);
-      (void)hipSetDevice(cur);
-    } else {
-      (void)hipModuleUnload(p->module);
-    }
+    const bool other = hipGetDevice(&cur) == hipSuccess && p->device >= 0 && cur != p->device;
+    if (other) (void)hipSetDevice(p->device);
+    for (JitPart& q : p->parts)
+      if (q.module) (void)hipModuleUnload(q.module);
+    if (other) (void)hipSetDevice(cur);
   }
   delete p;
   return ABS_OK;

@@ -34,6 +34,10 @@ class Plan:
         lib = L.lib()
         e = np.ascontiguousarray(edges, dtype=np.float64)
         self._edges = e
+        self._spec = (int(n), tuple(float(x) for x in e),
+                      dict(du=float(du), norm=float(norm), theta0=float(theta0),
+                           precision=int(precision), wmode=int(wmode), max_batch=int(max_batch),
+                           flags=int(flags)))
         d = L.PlanDesc(n=int(n), nbins=len(e) - 1,
                        edges=e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                        du=float(du), norm=float(norm), theta0=float(theta0),
@@ -48,6 +52,7 @@ class Plan:
         self.ntrip, self.npairs, self.ncols = info.ntrip, info.npairs, info.ncols
         self.plan_bytes, self.norm = info.plan_bytes, info.norm
         self.mfma_tiles = info.mfma_tiles
+        self.jit_parts = info.jit_parts
         self.precision = int(precision)
         self.wmode, self.max_batch = int(wmode), int(max_batch)
         ijk = np.zeros((self.ntrip, 3), np.int32)
@@ -61,23 +66,30 @@ class Plan:
         self._work = None
 
     # -- lifetime -------------------------------------------------------------
-    def compile(self):
-        L.check(L.lib().abs_plan_compile(self.handle), "abs_plan_compile")
+    def compile(self, workers=1):
+        """Compile the contraction code: its parts in turn, or in `workers` worker
+        processes (start those before this process first uses the GPU)."""
+        if workers > 1 and self.jit_parts > 1:
+            from .jit import compile_parts
+            compile_parts([self], [self._spec], workers=workers)
+        else:
+            L.check(L.lib().abs_plan_compile(self.handle), "abs_plan_compile")
         return self
 
-    def code(self):
-        """(key, bytes) of the compiled contraction code object (compiles if needed)."""
+    def code(self, part):
+        """(key, bytes) of one compiled part's code object (compiles it if needed)."""
         key, n = ctypes.c_uint64(), ctypes.c_size_t()
-        L.check(L.lib().abs_plan_code(self.handle, ctypes.byref(key), None, ctypes.byref(n)),
-                "abs_plan_code")
+        L.check(L.lib().abs_plan_code(self.handle, int(part), ctypes.byref(key), None,
+                                      ctypes.byref(n)), "abs_plan_code")
         buf = ctypes.create_string_buffer(n.value)
-        L.check(L.lib().abs_plan_code(self.handle, None, buf, ctypes.byref(n)), "abs_plan_code")
+        L.check(L.lib().abs_plan_code(self.handle, int(part), None, buf, ctypes.byref(n)),
+                "abs_plan_code")
         return key.value, buf.raw[:n.value]
 
-    def set_code(self, key, blob):
+    def set_code(self, part, key, blob):
         buf = ctypes.create_string_buffer(blob, len(blob))
-        L.check(L.lib().abs_plan_set_code(self.handle, ctypes.c_uint64(key), buf, len(blob)),
-                "abs_plan_set_code")
+        L.check(L.lib().abs_plan_set_code(self.handle, int(part), ctypes.c_uint64(key), buf,
+                                          len(blob)), "abs_plan_set_code")
         return self
 
     def bind(self, device=None, stream=None):

@@ -181,12 +181,12 @@ class GpuExecutor:
         """Create the plans for these keys, compile their kernels (in `workers` worker
         processes when > 1; start those before this process first uses the GPU), and
         bind them to the device."""
-        from .jit import compile_plans
+        from .jit import compile_parts
         from .plan import Plan
         keys = [k for k in dict.fromkeys(keys) if k not in self.plans]
         kw = dict(wmode=self.wmode, precision=self.precision, max_batch=self.max_batch)
         made = [Plan(n, e, **kw) for n, e in keys]
-        compile_plans(made, [(n, e, kw) for n, e in keys], workers=workers)
+        compile_parts(made, [(n, e, kw) for n, e in keys], workers=workers)
         for k, p in zip(keys, made):
             self.plans[k] = p.bind(self.device.index)
 

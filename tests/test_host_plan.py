@@ -111,3 +111,27 @@ def test_workspace_sizes():
     assert (1 << 20) * (4 + 4 + 16) + 2 * n * n * 4 <= g < (1 << 20) * 24 + 2 * n * n * 4 + 8192
     with pytest.raises(A.AbsError):
         p.estimate_workspace(5)
+
+
+def test_jit_parts_code_roundtrip_and_parallel_compile():
+    """The contraction code comes in separately compiled parts (at least the FP32 data
+    kernel and the FP64 weight kernel); a part's code object moves between identical
+    plans by key, and compiling the parts in worker processes gives the same objects."""
+    A = _A()
+    from paper_2412_02246_amd.jit import compile_parts
+    n, e = CASES["c1_128_8log"]
+    p = A.Plan(n, e)
+    assert p.jit_parts >= 2
+    q = A.Plan(n, e)
+    codes = [p.code(k) for k in range(p.jit_parts)]
+    for k, (key, blob) in enumerate(codes):
+        q.set_code(k, key, blob)
+    with pytest.raises(A.AbsError):
+        q.set_code(0, codes[0][0] ^ 1, codes[0][1])     # key of another source
+    with pytest.raises(A.AbsError):
+        p.code(p.jit_parts)                              # no such part
+    r = A.Plan(n, list(e[:-1]))
+    assert r.code(0)[0] != codes[0][0]
+    w = A.Plan(n, e)
+    compile_parts([w], [w._spec], workers=2)
+    assert [w.code(k) for k in range(w.jit_parts)] == codes
