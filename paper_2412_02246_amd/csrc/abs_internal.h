@@ -13,7 +13,7 @@ namespace abs_impl {
 
 constexpr int kBlock = 256;          // threads per workgroup for every kernel here
 constexpr int kMaxBins = 64;
-constexpr int kTilesPerWave = 16;    // MFMA output tiles owned by one wave (precision form)
+constexpr int kTilesPerWave = 12;    // MFMA output tiles owned by one wave (precision form)
 constexpr int kMaxN = 8192;
 
 // One contiguous run of uv columns gx0 .. gx0 + ncols - 1 of ring m, transformed

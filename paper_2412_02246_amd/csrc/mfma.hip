@@ -55,6 +55,44 @@ template <> struct Half<true> {
   }
 };
 
+// Pair products p = a[q] b[q] of 8 pixels split into p ~ hi + lo, both 16-bit.  BF16: hi
+// is p truncated to its upper 16 bits (the two halves of two products packed by one byte
+// permute), lo = a b - hi (fused, exact up to one rounding) rounded to BF16.  FP16: hi
+// rounded to FP16, lo = a b - hi rounded to FP16.  About four VALU operations a product.
+template <bool F16>
+__device__ __forceinline__ void split8(const float* a, const float* b, typename Half<F16>::V& hi,
+                                       typename Half<F16>::V& lo) {
+  const f32x4 a0 = *reinterpret_cast<const f32x4*>(a), a1 = *reinterpret_cast<const f32x4*>(a + 4);
+  const f32x4 b0 = *reinterpret_cast<const f32x4*>(b), b1 = *reinterpret_cast<const f32x4*>(b + 4);
+  const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+  const float bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+  if constexpr (!F16) {
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 hw, lw;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float p0 = av[2 * q] * bv[2 * q], p1 = av[2 * q + 1] * bv[2 * q + 1];
+      const unsigned u0 = __float_as_uint(p0), u1 = __float_as_uint(p1);
+      hw[q] = __builtin_amdgcn_perm(u1, u0, 0x07060302u);   // upper halves of p1 : p0
+      const float l0 = __builtin_fmaf(av[2 * q], bv[2 * q], -__uint_as_float(u0 & 0xffff0000u));
+      const float l1 = __builtin_fmaf(av[2 * q + 1], bv[2 * q + 1], -__uint_as_float(u1 & 0xffff0000u));
+      typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+      const bf16x2 lp = {(__bf16)l0, (__bf16)l1};
+      lw[q] = __builtin_bit_cast(unsigned, lp);
+    }
+    hi = __builtin_bit_cast(typename Half<F16>::V, hw);
+    lo = __builtin_bit_cast(typename Half<F16>::V, lw);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float pv = av[q] * bv[q];
+      const _Float16 h = (_Float16)pv;
+      hi[q] = h;
+      lo[q] = (_Float16)__builtin_fmaf(av[q], bv[q], -(float)h);
+    }
+  }
+}
+
 size_t mfma_lds_bytes(int nb) {
   return (size_t)(nb + 1) * (kRow32 * 4 + 2 * kRow16 * 2);
 }
@@ -140,6 +178,10 @@ mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long lon
     }
     __syncthreads();
     if (c0 + kChunk < p1) load_chunk(c0 + kChunk);
+    // B operand (the tile's ring columns, split) for the chunk's kChunk/32 k-steps, kept
+    // while consecutive tiles of the wave use the same columns
+    HV bh[kChunk / 32], bl[kChunk / 32];
+    int held = -1;   // column ring held by this lane (-1: none yet)
 #pragma unroll
     for (int s = 0; s < kTilesPerWave; ++s) {
       if (s < wr.y) {
@@ -148,30 +190,30 @@ mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long lon
         const float* di = d32 + ij.x * kRow32;
         const float* dj = d32 + ij.y * kRow32;
         const int bin = mt_bins[tile * 16 + row];
-        // one chunk's three split products in fresh accumulators (three independent
-        // chains of kChunk/32 steps), then one FP32 add into the tile's running sum: keeps
-        // every FP32 accumulation chain short (kChunk/32 steps within a chunk, one add per
-        // chunk across the pixel block)
-        f32x4 chh = {0.f, 0.f, 0.f, 0.f}, chl = chh, clh = chh;
+        if (__builtin_amdgcn_ballot_w64(bin != held)) {
+#pragma unroll
+          for (int ks = 0; ks < kChunk / 32; ++ks) {
+            const int x0 = ks * 32 + quad * 8;
+            bh[ks] = *reinterpret_cast<const HV*>(dhi + bin * kRow16 + x0);
+            bl[ks] = *reinterpret_cast<const HV*>(dlo + bin * kRow16 + x0);
+          }
+          held = bin;
+        }
+        // the chunk's three split products summed from zero (a chain of 3 kChunk/32
+        // MFMA steps), then one FP32 add into the tile's running sum: every FP32
+        // accumulation chain stays short
+        f32x4 cs = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < kChunk / 32; ++ks) {
           const int x0 = ks * 32 + quad * 8;
           // A operand: the pair products of this lane's row and 8 pixels, split
           HV ahi, alo;
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const float pv = di[x0 + q] * dj[x0 + q];
-            const HT h = (HT)pv;
-            ahi[q] = h;
-            alo[q] = (HT)(pv - (float)h);
-          }
-          const HV bh = *reinterpret_cast<const HV*>(dhi + bin * kRow16 + x0);
-          const HV bl = *reinterpret_cast<const HV*>(dlo + bin * kRow16 + x0);
-          chh = H::mma(ahi, bh, chh);
-          chl = H::mma(ahi, bl, chl);
-          clh = H::mma(alo, bh, clh);
+          split8<F16>(di + x0, dj + x0, ahi, alo);
+          cs = H::mma(ahi, bh[ks], cs);
+          cs = H::mma(ahi, bl[ks], cs);
+          cs = H::mma(alo, bh[ks], cs);
         }
-        acc[s] += chh + (chl + clh);
+        acc[s] += cs;
       }
     }
     __syncthreads();
