@@ -27,10 +27,10 @@ WORKLOADS = {
                     desc="MWA-shaped single channel: 1024x1024 c64 grid, 20 log rings 46<=l<1320, "
                          "Poisson baseline mask + SNR-5 noise, INV_COUNT weights"),
     # precision-form shapes: 4096^2, 32 log rings, edges x4
-    "mwa4096": dict(n=4096, nbins=32, lmin=4 * 46.0, lmax=4 * 1320.0, batch=2, cfg=2,
+    "mwa4096": dict(n=4096, nbins=32, lmin=4 * 46.0, lmax=4 * 1320.0, batch=16, cfg=2,
                     desc="MWA-shaped 4096x4096 c64 grid, 32 log rings 4x(46<=l<1320), INV_COUNT weights"),
-    # large ensemble shapes: 8192^2, 64 log rings, edges x8 (realisations in batches of 2)
-    "mwa8192": dict(n=8192, nbins=64, lmin=8 * 46.0, lmax=8 * 1320.0, batch=2, cfg=4,
+    # large ensemble shapes: 8192^2, 64 log rings, edges x8 (realisations in batches of 4)
+    "mwa8192": dict(n=8192, nbins=64, lmin=8 * 46.0, lmax=8 * 1320.0, batch=4, cfg=4,
                     desc="MWA-shaped 8192x8192 c64 grid, 64 log rings 8x(46<=l<1320), INV_COUNT weights"),
 }
 class HipEvents:

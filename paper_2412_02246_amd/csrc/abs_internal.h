@@ -34,6 +34,7 @@ struct BinDev {
 struct DevLayout {
   size_t tw, tw64, bins, tiles;
   size_t pt_pairs, mt_ptile, mt_bins, mt_trip, wave_tiles;   // precision-form tables
+  size_t pos32, pos64;   // position of each triplet in the FP32 / FP64 kernel's partials
   size_t total;
 };
 
@@ -92,6 +93,7 @@ struct abs_plan_s {
   int ngroups = 0;               // wave groups of the FP32 kernel; one wave per group
   int ngroups64 = 0;             // wave groups of the FP64 kernel (weight fields)
   int waves = 4, waves64 = 4;    // waves (groups) per workgroup of the two kernels
+  std::vector<int> pos32, pos64; // position of each triplet in the kernels' triplet orders
   int pix_per_block = 0;         // pixels per contraction workgroup (data sets)
   int nblk = 0;                  // contraction pixel blocks per data set
   int pix_per_block64 = 0;       // the same for the FP64 weight sets (fewer sets: smaller blocks)

@@ -28,17 +28,20 @@ __global__ void fill_u32_kernel(unsigned* __restrict__ a, int n, unsigned v) {
 hipError_t launch_rowpass_f64(const abs_plan_s* p, int nsets, const double2* Z, long long zset,
                               double* F, long long fset, hipStream_t st);
 
-// Sum of nblk workgroup partials part[k * ntrip + t] for the block's 64 triplets, in a
-// fixed order: wave w adds its quarter of k in sequence, then the quarters are added in
-// order w = 0 .. 3.  Every thread of the block must call it.
+// Sum of nblk workgroup partials part[k * ntrip + pos[t]] of triplet t (pos: the
+// triplet's position in the writing kernel's order, NULL for t itself) for the block's
+// 64 triplets, in a fixed order: wave w adds its quarter of k in sequence, then the
+// quarters are added in order w = 0 .. 3.  Every thread of the block must call it.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nblk, int ntrip,
-                                               int t) {
+                                               const int* __restrict__ pos, int t) {
   __shared__ double q4[4][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int k0 = (int)((long long)nblk * wave / 4), k1 = (int)((long long)nblk * (wave + 1) / 4);
   double s = 0.0;
-  if (t < ntrip)
-    for (int k = k0; k < k1; ++k) s += part[(long long)k * ntrip + t];
+  if (t < ntrip) {
+    const int c = pos ? pos[t] : t;
+    for (int k = k0; k < k1; ++k) s += part[(long long)k * ntrip + c];
+  }
   __syncthreads();   // q4 is reused by the next call
   q4[wave][lane] = s;
   __syncthreads();
@@ -49,19 +52,20 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
 // in FP64 in a fixed order and divided by n^2 (the sum over pixels of a product of
 // three DFTs counts every closed triangle n^2 times).  Block: 64 triplets of grid b.
 __global__ void __launch_bounds__(kBlock)
-finalize_kernel(const double* __restrict__ part, long long partset, int nblk,
-                const double* __restrict__ part64, long long partset64, int nblk64, int ntrip,
-                int batch, int nisets, const double* __restrict__ n_given, double inv_npix,
-                double norm, double* __restrict__ B, double* __restrict__ N) {
+finalize_kernel(const double* __restrict__ part, long long partset, int nblk, const int* __restrict__ pos,
+                const double* __restrict__ part64, long long partset64, int nblk64,
+                const int* __restrict__ pos64, int ntrip, int batch, int nisets,
+                const double* __restrict__ n_given, double inv_npix, double norm,
+                double* __restrict__ B, double* __restrict__ N) {
   const int t = blockIdx.x * 64 + (threadIdx.x & 63);
   const int b = blockIdx.y;
-  const double s = sum_partials(part + (long long)b * partset, nblk, ntrip, t) * inv_npix;
+  const double s = sum_partials(part + (long long)b * partset, nblk, ntrip, pos, t) * inv_npix;
   double nn;
   if (nisets == 0) {
     nn = t < ntrip ? n_given[t] : 0.0;
   } else {
     const int is = nisets > 1 ? b : 0;
-    nn = sum_partials(part64 + (long long)is * partset64, nblk64, ntrip, t) * inv_npix;
+    nn = sum_partials(part64 + (long long)is * partset64, nblk64, ntrip, pos64, t) * inv_npix;
   }
   if (threadIdx.x < 64 && t < ntrip) {
     B[(long long)b * ntrip + t] = s / (norm * nn);
@@ -71,10 +75,10 @@ finalize_kernel(const double* __restrict__ part, long long partset, int nblk,
 
 // abs_counts: N_t alone from the weight-set partials.
 __global__ void __launch_bounds__(kBlock)
-counts_kernel(const double* __restrict__ part64, int nblk64, int ntrip, double inv_npix,
-              double* __restrict__ N) {
+counts_kernel(const double* __restrict__ part64, int nblk64, const int* __restrict__ pos64, int ntrip,
+              double inv_npix, double* __restrict__ N) {
   const int t = blockIdx.x * 64 + (threadIdx.x & 63);
-  const double nn = sum_partials(part64, nblk64, ntrip, t) * inv_npix;
+  const double nn = sum_partials(part64, nblk64, ntrip, pos64, t) * inv_npix;
   if (threadIdx.x < 64 && t < ntrip) N[t] = nn;
 }
 
@@ -210,6 +214,8 @@ abs_status abs_plan_bind(abs_plan_t p, void* mem, size_t bytes, void* stream) {
   put(p->dl.mt_bins, p->mt_bins);
   put(p->dl.mt_trip, p->mt_trip);
   put(p->dl.wave_tiles, p->wave_tiles);
+  put(p->dl.pos32, p->pos32);
+  put(p->dl.pos64, p->pos64);
   if (hipMemcpyAsync(mem, img.data(), img.size(), hipMemcpyHostToDevice, st) != hipSuccess)
     return ABS_ERR_DEVICE;
   // the host image is a local: wait for the copy before it goes out of scope
@@ -242,8 +248,13 @@ abs_status abs_estimate(abs_plan_t p, int32_t batch, int32_t dtype, const void* 
   const double* part64 = reinterpret_cast<const double*>(wk + wl.part64);
   const double inv = 1.0 / ((double)p->n * (double)p->n);
   const dim3 g((unsigned)((p->ntrip + 63) / 64), (unsigned)batch);
-  finalize_kernel<<<g, kBlock, 0, st>>>(part, wl.partset, p->nblk, part64, wl.partset64, p->nblk64,
-                                        (int)p->ntrip, batch, wl.nisets, n_given, inv, p->norm, B, N);
+  const char* base = static_cast<const char*>(p->dev);
+  // the FP32 contraction writes partials in its own triplet order, the precision form
+  // by triplet index
+  const int* pos = p->precision == ABS_FP32 ? reinterpret_cast<const int*>(base + p->dl.pos32) : nullptr;
+  const int* pos64 = reinterpret_cast<const int*>(base + p->dl.pos64);
+  finalize_kernel<<<g, kBlock, 0, st>>>(part, wl.partset, p->nblk, pos, part64, wl.partset64, p->nblk64,
+                                        pos64, (int)p->ntrip, batch, wl.nisets, n_given, inv, p->norm, B, N);
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
 
@@ -263,8 +274,9 @@ abs_status abs_counts(abs_plan_t p, const float* w, void* work, size_t work_byte
   s = run_fields_and_contract(p, wl, 0, ABS_C64, nullptr, w, 0, wk, st);
   if (s != ABS_OK) return s;
   const double inv = 1.0 / ((double)p->n * (double)p->n);
+  const int* pos64 = reinterpret_cast<const int*>(static_cast<const char*>(p->dev) + p->dl.pos64);
   counts_kernel<<<(unsigned)((p->ntrip + 63) / 64), kBlock, 0, st>>>(
-      reinterpret_cast<const double*>(wk + wl.part64), p->nblk64, (int)p->ntrip, inv, N);
+      reinterpret_cast<const double*>(wk + wl.part64), p->nblk64, pos64, (int)p->ntrip, inv, N);
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
 

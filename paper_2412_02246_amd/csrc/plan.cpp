@@ -189,16 +189,17 @@ WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_c
 // abs_contract64 (FP64 fields and accumulators, for the weight fields).
 namespace {
 
-// Split ntrip triplets into G contiguous groups whose register estimate, rw * (slots +
-// bins used), stays within the budget.  G is a multiple of the waves per workgroup
-// (*waves): 4, or 8 when more than 4 groups are needed (fewer slices re-read the fields).
-std::vector<int> split_groups(const abs_plan_s* p, int rw, int* waves) {
+// Split the ordered triplet list (ord[0 .. ntrip)) into G contiguous groups whose
+// register estimate, rw * (slots + bins used), stays within the budget.  G is a multiple
+// of the waves per workgroup (*waves): 4, or 8 when more than 4 groups are needed (fewer
+// slices re-read the fields).
+std::vector<int> split_groups(const abs_plan_s* p, const std::vector<int>& ord, int rw, int* waves) {
   const int T = (int)p->ntrip;
   const int kBudget = 200;
   auto cost_ok = [&](int t0, int t1) {
     std::set<int> bins;
     for (int t = t0; t < t1; ++t)
-      for (int q = 0; q < 3; ++q) bins.insert(p->trips[3 * t + q]);
+      for (int q = 0; q < 3; ++q) bins.insert(p->trips[3 * ord[t] + q]);
     return rw * ((t1 - t0) + (int)bins.size()) <= kBudget;
   };
   auto even = [&](int G) {
@@ -221,6 +222,49 @@ std::vector<int> split_groups(const abs_plan_s* p, int rw, int* waves) {
   return {};
 }
 
+// Rings a kernel's slices stage, summed over the slices: the fields it reads per pixel.
+int64_t staged_rings(const abs_plan_s* p, const std::vector<int>& ord, const std::vector<int>& start, int W) {
+  const int G = (int)start.size() - 1;
+  int64_t sum = 0;
+  for (int z = 0; z < G / W; ++z) {
+    std::set<int> b;
+    for (int t = start[W * z]; t < start[W * z + W]; ++t)
+      for (int q = 0; q < 3; ++q) b.insert(p->trips[3 * ord[t] + q]);
+    sum += (int64_t)b.size();
+  }
+  return sum;
+}
+
+// Triplet order of one kernel: the plan's (i, j, k) order, or blocks of B consecutive j
+// (each in (i, j, k) order), whichever makes its slices stage the fewest rings.  Blocking
+// by j keeps the triplets of a slice within a narrow band of rings; pairs (i, j) stay
+// contiguous, so each pair product is still formed once per group.
+struct KernelOrder {
+  std::vector<int> ord, start;
+  int waves = 4;
+};
+KernelOrder choose_order(const abs_plan_s* p, int rw) {
+  const int T = (int)p->ntrip;
+  KernelOrder best;
+  int64_t best_cost = -1;
+  for (int B : {0, 4, 8, 16}) {
+    KernelOrder o;
+    o.ord.resize(T);
+    for (int t = 0; t < T; ++t) o.ord[t] = t;
+    if (B > 0)
+      std::stable_sort(o.ord.begin(), o.ord.end(),
+                       [&](int a, int b) { return p->trips[3 * a + 1] / B < p->trips[3 * b + 1] / B; });
+    o.start = split_groups(p, o.ord, rw, &o.waves);
+    if (o.start.empty()) continue;
+    const int64_t cost = staged_rings(p, o.ord, o.start, o.waves);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = std::move(o);
+    }
+  }
+  return best;
+}
+
 // Kernel layout.  A workgroup is W waves (W consecutive triplet groups, "slice" z) on
 // one pixel block of one set.  The pixels are walked in chunks of 64 (one per lane);
 // the rings the slice uses (its union U_z) are staged chunk by chunk in LDS, each wave
@@ -229,8 +273,8 @@ std::vector<int> split_groups(const abs_plan_s* p, int rw, int* waves) {
 // the LDS stage that chunk c - 1 occupied, after the one barrier per chunk that also
 // publishes chunk c.  Workgroups are numbered so that the slices of one pixel block
 // run on one XCD (blocks are dealt to the 8 XCDs round robin), where they share L2.
-void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, int W, int z0, int z1,
-                 const char* name, const char* R, std::string& s) {
+void emit_kernel(const abs_plan_s* p, const std::vector<int>& ord, const std::vector<int>& start, int W,
+                 int z0, int z1, const char* name, const char* R, std::string& s) {
   char buf[1024];
   const int G = (int)start.size() - 1;   // a multiple of W
   const int GZ = G / W;
@@ -241,7 +285,7 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, int W, int 
   for (int g = 0; g < G; ++g) {
     std::set<int> b;
     for (int t = start[g]; t < start[g + 1]; ++t)
-      for (int q = 0; q < 3; ++q) b.insert(p->trips[3 * t + q]);
+      for (int q = 0; q < 3; ++q) b.insert(p->trips[3 * ord[t] + q]);
     gbins[g].assign(b.begin(), b.end());
   }
   int NU = 1;
@@ -326,7 +370,7 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, int W, int 
       r += buf;
       int ci = -1, cj = -1;
       for (int t = t0; t < t1; ++t) {
-        const int i = p->trips[3 * t], j = p->trips[3 * t + 1], k = p->trips[3 * t + 2];
+        const int i = p->trips[3 * ord[t]], j = p->trips[3 * ord[t] + 1], k = p->trips[3 * ord[t] + 2];
         if (i != ci || j != cj) {
           std::snprintf(buf, sizeof buf, "    t = d%d_%s * d%d_%s;\n", i, stage, j, stage);
           r += buf;
@@ -388,13 +432,22 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& start, int W, int 
 constexpr int kSlicesPerPart = 4;
 
 bool build_jit_source(abs_plan_s* p) {
-  int w32 = 4, w64 = 4;
-  const std::vector<int> g32 = split_groups(p, 1, &w32), g64 = split_groups(p, 2, &w64);
-  if (g32.empty() || g64.empty()) return false;
+  const KernelOrder o32 = choose_order(p, 1), o64 = choose_order(p, 2);
+  if (o32.start.empty() || o64.start.empty()) return false;
+  const std::vector<int>& g32 = o32.start;
+  const std::vector<int>& g64 = o64.start;
+  const int w32 = o32.waves, w64 = o64.waves;
   p->ngroups = (int)g32.size() - 1;
   p->ngroups64 = (int)g64.size() - 1;
   p->waves = w32;
   p->waves64 = w64;
+  // partial sums are written in kernel order: position of every triplet in each order
+  p->pos32.assign(p->ntrip, 0);
+  p->pos64.assign(p->ntrip, 0);
+  for (int t = 0; t < (int)p->ntrip; ++t) {
+    p->pos32[o32.ord[t]] = t;
+    p->pos64[o64.ord[t]] = t;
+  }
   const std::string head =
       "// generated: triplet contraction for one ring-triplet list\n"
       "__device__ __forceinline__ float abs_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }\n"
@@ -404,7 +457,8 @@ bool build_jit_source(abs_plan_s* p) {
       "  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, \"wavefront\");\n"
       "  __builtin_amdgcn_wave_barrier();\n}\n";
   p->parts.clear();
-  auto add = [&](int kind, const std::vector<int>& start, int W, const char* R) {
+  auto add = [&](int kind, const std::vector<int>& ord, const std::vector<int>& start, int W,
+                 const char* R) {
     const int GZ = ((int)start.size() - 1) / W;
     for (int z0 = 0; z0 < GZ; z0 += kSlicesPerPart) {
       JitPart part;
@@ -412,13 +466,13 @@ bool build_jit_source(abs_plan_s* p) {
       part.z0 = z0;
       part.z1 = std::min(GZ, z0 + kSlicesPerPart);
       part.src = head;
-      emit_kernel(p, start, W, part.z0, part.z1, "abs_contract", R, part.src);
+      emit_kernel(p, ord, start, W, part.z0, part.z1, "abs_contract", R, part.src);
       p->parts.push_back(std::move(part));
     }
   };
   // the FP32 kernel serves the FP32 data path; the weight fields always use FP64
-  if (p->precision == ABS_FP32) add(0, g32, w32, "float");
-  add(1, g64, w64, "double");
+  if (p->precision == ABS_FP32) add(0, o32.ord, g32, w32, "float");
+  add(1, o64.ord, g64, w64, "double");
   return true;
 }
 
@@ -716,6 +770,10 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
   off = al(off + p->mt_trip.size() * 4);
   p->dl.wave_tiles = off;
   off = al(off + p->wave_tiles.size() * 4);
+  p->dl.pos32 = off;
+  off = al(off + (size_t)p->ntrip * 4);
+  p->dl.pos64 = off;
+  off = al(off + (size_t)p->ntrip * 4);
   p->dl.total = off;
 
   if (!build_jit_source(p)) {

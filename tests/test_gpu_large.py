@@ -48,3 +48,45 @@ def test_c3_full_size(c3, prec):
     assert np.all(np.isfinite(B))
     assert e.max() <= TOL[prec]
     assert en.max() <= 1e-5
+
+
+# 8192 x 8192, 64 log rings over 8 x (46 <= l < 1320): the large-ensemble shapes.  The
+# oracle's sample is every plan triplet within 4 rings spread over the range.
+N5 = 8192
+EDGES5 = oplan.log_edges(8 * 46 / (2 * np.pi), 8 * 1320 / (2 * np.pi), 64)
+SUBSET5 = {0, 21, 42, 63}
+
+
+@pytest.fixture(scope="module")
+def c5():
+    import paper_2412_02246_amd as A
+    V, counts = synth.mwa_like(N5, synth.seed_for(4, 0), U0=N5 / 8)
+    V = V.astype(np.complex64)
+    host = A.Plan(N5, EDGES5)
+    idx = np.array([q for q, t in enumerate(host.triplets) if set(t.tolist()) <= SUBSET5])
+    print("C5 sample: %d of %d triplets" % (len(idx), host.ntrip), flush=True)
+    ref = oest.estimate_subset(V, counts, EDGES5, host.norm, host.triplets[idx], wmode=oest.INV_COUNT)
+    return V, counts, idx, ref, host.triplets
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_c5_full_size(c5, prec):
+    import torch
+    import paper_2412_02246_amd as A
+    V, counts, idx, ref, trips = c5
+    P = {"fp32": A.FP32, "bf16x3": A.BF16X3}[prec]
+    p = A.Plan(N5, EDGES5, wmode=A.W_INV_COUNT, precision=P)
+    p.compile(workers=8)   # the code parts in worker processes
+    p.bind()
+    assert np.array_equal(p.triplets, trips)
+    B, Nn = p.estimate(torch.from_numpy(V).cuda(), torch.from_numpy(counts.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    B = B[0].cpu().numpy()[idx]
+    Nn = Nn[0].cpu().numpy()[idx]
+    e = oest.relative_error(B, ref, p.norm)
+    en = oest.count_error(Nn, ref)
+    print("C5 %s: e_t median %.3g max %.3g, e_N max %.3g over %d sampled triplets"
+          % (prec, np.median(e), e.max(), en.max(), len(idx)), flush=True)
+    assert np.all(np.isfinite(B))
+    assert e.max() <= TOL[prec]
+    assert en.max() <= 1e-5
