@@ -83,7 +83,7 @@ struct abs_plan_s {
   int ct = 0;                    // columns per column-pass block
   std::vector<abs_impl::ColTile> tiles;
   // precision form: 16-pair row tiles, 16 x 16 MFMA tiles and their owner waves
-  std::vector<int> pt_pairs;     // 2 * 16 per row tile: (i, j), padding rows (nb, nb)
+  std::vector<int> pt_pairs;     // 2 * 16 per row tile: (j, k), padding rows (nb, nb)
   std::vector<int> mt_ptile;     // row tile of each MFMA tile
   std::vector<int> mt_bins;      // 16 ring columns per MFMA tile, padding nb
   std::vector<int> mt_trip;      // 256 per MFMA tile: triplet index or -1

@@ -11,17 +11,18 @@
 // partials per triplet, in the same layout as the FP32 path, so the FP64 finaliser is
 // shared.
 //
-// Tiles are block-sparse: pairs are ordered by (j, i) and cut into tiles of 16 rows; each
-// row tile only multiplies against the rings that close a triangle with one of its pairs
-// (16 columns per MFMA tile; absent rows / columns point at a zero row of LDS).  Output
-// entries that are not plan triplets are computed and dropped.
+// Tiles are block-sparse: each triplet i <= j <= k is the pair product D_j D_k of its two
+// largest rings times its smallest ring D_i; pairs ordered by (j, k) are cut into row
+// tiles of 16, and each row tile only multiplies against the rings i that close a triangle
+// with one of its pairs (16 columns per MFMA tile; absent rows / columns point at a zero
+// row of LDS).  Output entries that are not plan triplets are computed and dropped.
 //
 // Workgroup: 8 waves; blockIdx.x = pixel block, blockIdx.y = set, blockIdx.z = wave
 // group.  Per chunk of kChunk pixels the workgroup stages the rings' FP32 values and their
 // hi/lo halves in LDS; each wave then evaluates its MFMA tiles (at most kTilesPerWave,
-// accumulators in registers across the whole pixel block).  Every MFMA tile has its own
-// row tile (a row tile whose rings need more than 16 columns is repeated), so the A
-// operand (the pair products, split) is formed per tile and k-step, just in time.
+// accumulators in registers across the whole pixel block).  The A operand (the row tile's
+// pair products, split) is formed once per chunk and kept for the wave's consecutive tiles
+// of that row tile; the B operand likewise while the columns stay the same.
 #include "abs_internal.h"
 
 namespace abs_impl {
@@ -57,8 +58,9 @@ template <> struct Half<true> {
 
 // Pair products p = a[q] b[q] of 8 pixels split into p ~ hi + lo, both 16-bit.  BF16: hi
 // is p truncated to its upper 16 bits (the two halves of two products packed by one byte
-// permute), lo = a b - hi (fused, exact up to one rounding) rounded to BF16.  FP16: hi
-// rounded to FP16, lo = a b - hi rounded to FP16.  About four VALU operations a product.
+// permute), lo = a b - hi (fused, exact up to one rounding) rounded to BF16: about four
+// VALU operations a product.  FP16: hi = fl16(a b) and lo = fl16(a b - hi), each one
+// mixed-precision FMA: two operations a product.
 template <bool F16>
 __device__ __forceinline__ void split8(const float* a, const float* b, typename Half<F16>::V& hi,
                                        typename Half<F16>::V& lo) {
@@ -83,13 +85,32 @@ __device__ __forceinline__ void split8(const float* a, const float* b, typename 
     hi = __builtin_bit_cast(typename Half<F16>::V, hw);
     lo = __builtin_bit_cast(typename Half<F16>::V, lw);
   } else {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const float pv = av[q] * bv[q];
-      const _Float16 h = (_Float16)pv;
-      hi[q] = h;
-      lo[q] = (_Float16)__builtin_fmaf(av[q], bv[q], -(float)h);
-    }
+    // two products a packed register: hi = fl16(a b) and lo = fl16(a b - hi), each one
+    // mixed-precision FMA writing one half; the second product's lo reads its hi from the
+    // upper half (op_sel), so no separate copy of it is made.  One block for all eight
+    // products: the compiler's hazard tracking does not see into it, so it ends with the
+    // two wait states a matrix instruction needs before reading a VGPR that a VALU
+    // operation has just written.
+    unsigned h0, h1, h2, h3, l0, l1, l2, l3;
+#define ABS_MIX2(H, L, A0, B0, A1, B1)                                            \
+  "v_fma_mixlo_f16 " H ", " A0 ", " B0 ", 0\n\t"                                  \
+  "v_fma_mixhi_f16 " H ", " A1 ", " B1 ", 0\n\t"                                  \
+  "v_fma_mixlo_f16 " L ", " A0 ", " B0 ", -" H " op_sel_hi:[0,0,1]\n\t"           \
+  "v_fma_mixhi_f16 " L ", " A1 ", " B1 ", -" H " op_sel:[0,0,1] op_sel_hi:[0,0,1]\n\t"
+    asm(ABS_MIX2("%0", "%4", "%8", "%9", "%10", "%11")
+        ABS_MIX2("%1", "%5", "%12", "%13", "%14", "%15")
+        ABS_MIX2("%2", "%6", "%16", "%17", "%18", "%19")
+        ABS_MIX2("%3", "%7", "%20", "%21", "%22", "%23")
+        "s_nop 1"
+        : "=&v"(h0), "=&v"(h1), "=&v"(h2), "=&v"(h3), "=&v"(l0), "=&v"(l1), "=&v"(l2), "=&v"(l3)
+        : "v"(av[0]), "v"(bv[0]), "v"(av[1]), "v"(bv[1]), "v"(av[2]), "v"(bv[2]),
+          "v"(av[3]), "v"(bv[3]), "v"(av[4]), "v"(bv[4]), "v"(av[5]), "v"(bv[5]),
+          "v"(av[6]), "v"(bv[6]), "v"(av[7]), "v"(bv[7]));
+#undef ABS_MIX2
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 hw = {h0, h1, h2, h3}, lw = {l0, l1, l2, l3};
+    hi = __builtin_bit_cast(typename Half<F16>::V, hw);
+    lo = __builtin_bit_cast(typename Half<F16>::V, lw);
   }
 }
 
@@ -143,6 +164,19 @@ mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long lon
   f32x4 acc[kTilesPerWave];
 #pragma unroll
   for (int s = 0; s < kTilesPerWave; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // this lane's row of each tile, packed j | k << 8 | column ring << 16 (rings <= kMaxBins,
+  // the zero row included), read once: no global load inside the chunk loop, whose
+  // in-order completion count would otherwise also wait for the next chunk's prefetch
+  unsigned meta[kTilesPerWave];
+#pragma unroll
+  for (int s = 0; s < kTilesPerWave; ++s) {
+    meta[s] = 0;
+    if (s < wr.y) {
+      const int tile = wr.x + s;
+      const int2 ij = pt_pairs[mt_ptile[tile] * 16 + row];
+      meta[s] = (unsigned)ij.x | ((unsigned)ij.y << 8) | ((unsigned)mt_bins[tile * 16 + row] << 16);
+    }
+  }
 
   // The chunk's global loads are issued one chunk ahead (registers), so their latency
   // overlaps the matrix work on the previous chunk.  Thread q stages the values
@@ -178,18 +212,31 @@ mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long lon
     }
     __syncthreads();
     if (c0 + kChunk < p1) load_chunk(c0 + kChunk);
-    // B operand (the tile's ring columns, split) for the chunk's kChunk/32 k-steps, kept
-    // while consecutive tiles of the wave use the same columns
-    HV bh[kChunk / 32], bl[kChunk / 32];
-    int held = -1;   // column ring held by this lane (-1: none yet)
+    // A operand (the row tile's pair products, split) and B operand (the tile's ring
+    // columns, split) for the chunk's kChunk/32 k-steps, each kept while consecutive tiles
+    // of the wave use the same rows / columns
+    HV ah[kChunk / 32], al[kChunk / 32], bh[kChunk / 32], bl[kChunk / 32];
+    unsigned held_rows = ~0u;   // pair (j | k << 8) held by this lane (none yet)
+    int held = -1;              // column ring held by this lane (-1: none yet)
 #pragma unroll
     for (int s = 0; s < kTilesPerWave; ++s) {
       if (s < wr.y) {
-        const int tile = wr.x + s;
-        const int2 ij = pt_pairs[mt_ptile[tile] * 16 + row];
-        const float* di = d32 + ij.x * kRow32;
-        const float* dj = d32 + ij.y * kRow32;
-        const int bin = mt_bins[tile * 16 + row];
+        // opaque copy: keeps the compiler from hoisting the decoded addresses of every
+        // tile out of the chunk loop (three live registers a tile instead of one)
+        unsigned m = meta[s];
+        asm volatile("" : "+v"(m));
+        const unsigned rows = m & 0xffffu;
+        const int bin = (int)(m >> 16);
+        if (__builtin_amdgcn_ballot_w64(rows != held_rows)) {
+          const float* dj = d32 + (rows & 0xffu) * kRow32;
+          const float* dk = d32 + (rows >> 8) * kRow32;
+#pragma unroll
+          for (int ks = 0; ks < kChunk / 32; ++ks) {
+            const int x0 = ks * 32 + quad * 8;
+            split8<F16>(dj + x0, dk + x0, ah[ks], al[ks]);
+          }
+          held_rows = rows;
+        }
         if (__builtin_amdgcn_ballot_w64(bin != held)) {
 #pragma unroll
           for (int ks = 0; ks < kChunk / 32; ++ks) {
@@ -205,13 +252,9 @@ mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long lon
         f32x4 cs = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < kChunk / 32; ++ks) {
-          const int x0 = ks * 32 + quad * 8;
-          // A operand: the pair products of this lane's row and 8 pixels, split
-          HV ahi, alo;
-          split8<F16>(di + x0, dj + x0, ahi, alo);
-          cs = H::mma(ahi, bh[ks], cs);
-          cs = H::mma(ahi, bl[ks], cs);
-          cs = H::mma(alo, bh[ks], cs);
+          cs = H::mma(ah[ks], bh[ks], cs);
+          cs = H::mma(ah[ks], bl[ks], cs);
+          cs = H::mma(al[ks], bh[ks], cs);
         }
         acc[s] += cs;
       }
