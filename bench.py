@@ -71,7 +71,7 @@ PEAK_HBM = 8.0e12
 # WRITE_SIZE passes scaled by a 1 GiB copy (2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE), for the
 # kernel as it stands in this tree (profiles/counters_mwa1024_batch16.md); a workload or
 # precision without an entry reports null.
-MEASURED_TRAFFIC = {("mwa1024", "fp32"): 1348.6e6}
+MEASURED_TRAFFIC = {}
 
 
 def parse():
@@ -278,7 +278,12 @@ def main():
     ms = 1e3 * dt / a.steps
     grids_s = batch * a.steps / dt
     nsets = batch  # the contraction launch timed is the data-set one (the weight set runs in FP64)
-    flops = float(nsets) * n * n * (plan.npairs + 2 * plan.ntrip)
+    # algorithmic flops per pixel: two per triplet (product with the pair, add) plus the
+    # pair products, counted for the orientation with the fewest distinct pairs ((i, j) or
+    # (j, k) of i <= j <= k)
+    ijk = np.asarray(plan.triplets).reshape(-1, 3)
+    pairs = min(len({(int(x[0]), int(x[1])) for x in ijk}), len({(int(x[1]), int(x[2])) for x in ijk}))
+    flops = float(nsets) * n * n * (pairs + 2 * plan.ntrip)
     achieved = flops / (con_ms * 1e-3)
     if a.precision == "fp32":
         roof = {"kernel": "abs_contract (plan-specialised FP32 triplet contraction)", "bound": "alu",

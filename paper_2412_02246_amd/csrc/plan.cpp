@@ -13,6 +13,7 @@
 #include <cstring>
 #include <new>
 #include <set>
+#include <tuple>
 
 #include "abs_internal.h"
 
@@ -182,7 +183,8 @@ WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_c
 // list: every wave owns a fixed group of triplets, holds one accumulator per triplet
 // in registers, and walks its workgroup's pixels with one pixel per lane; the field
 // values of a pixel are loaded once (coalesced across lanes, prefetched one
-// iteration ahead) and every pair product F_i F_j is formed once per pixel.
+// iteration ahead) and every pair product (F_i F_j, or F_j F_k when the plan's
+// triplets are grouped by their two largest rings) is formed once per pixel.
 // Accumulators are summed across the wave through LDS in FP64 and written per
 // workgroup; the finaliser adds workgroups in a fixed order.
 // Two kernels are emitted: abs_contract (FP32 fields, FP32 accumulators) and
@@ -235,31 +237,66 @@ int64_t staged_rings(const abs_plan_s* p, const std::vector<int>& ord, const std
   return sum;
 }
 
-// Triplet order of one kernel: the plan's (i, j, k) order, or blocks of B consecutive j
-// (each in (i, j, k) order), whichever makes its slices stage the fewest rings.  Blocking
-// by j keeps the triplets of a slice within a narrow band of rings; pairs (i, j) stay
-// contiguous, so each pair product is still formed once per group.
+// Pair products a kernel's groups form per pixel: one per run of triplets with the same
+// pair inside a group.
+int64_t pairs_formed(const abs_plan_s* p, const std::vector<int>& ord, const std::vector<int>& start,
+                     bool jk) {
+  int64_t n = 0;
+  for (size_t g = 0; g + 1 < start.size(); ++g) {
+    int pa = -1, pb = -1;
+    for (int t = start[g]; t < start[g + 1]; ++t) {
+      const int* x = &p->trips[3 * ord[t]];
+      const int a = jk ? x[1] : x[0], b = jk ? x[2] : x[1];
+      if (a != pa || b != pb) ++n;
+      pa = a;
+      pb = b;
+    }
+  }
+  return n;
+}
+
+// Triplet order of one kernel.  Each triplet i <= j <= k is formed as a pair product
+// times a single ring: (D_i D_j) D_k, or (D_j D_k) D_i, whose pairs are fewer (a pair of
+// large rings closes triangles with a run of small ones) but whose groups may span more
+// rings.  Base order (i, j, k) or (j, k, i), then optionally blocks of B consecutive j;
+// pairs stay contiguous, so each pair product is formed once per group.  The cost of an
+// order is the VALU work per pixel (pair products formed + one FMA per triplet) plus the
+// rings its slices stage, each weighed as kStagedRingCost operations (a field value read
+// from memory and stored to LDS).
 struct KernelOrder {
   std::vector<int> ord, start;
   int waves = 4;
+  bool jk = false;
 };
+constexpr int64_t kStagedRingCost = 16;
 KernelOrder choose_order(const abs_plan_s* p, int rw) {
   const int T = (int)p->ntrip;
   KernelOrder best;
   int64_t best_cost = -1;
-  for (int B : {0, 4, 8, 16}) {
-    KernelOrder o;
-    o.ord.resize(T);
-    for (int t = 0; t < T; ++t) o.ord[t] = t;
-    if (B > 0)
-      std::stable_sort(o.ord.begin(), o.ord.end(),
-                       [&](int a, int b) { return p->trips[3 * a + 1] / B < p->trips[3 * b + 1] / B; });
-    o.start = split_groups(p, o.ord, rw, &o.waves);
-    if (o.start.empty()) continue;
-    const int64_t cost = staged_rings(p, o.ord, o.start, o.waves);
-    if (best_cost < 0 || cost < best_cost) {
-      best_cost = cost;
-      best = std::move(o);
+  for (bool jk : {false, true}) {
+    std::vector<int> base(T);
+    for (int t = 0; t < T; ++t) base[t] = t;
+    if (jk)
+      std::stable_sort(base.begin(), base.end(), [&](int a, int b) {
+        const int* x = &p->trips[3 * a];
+        const int* y = &p->trips[3 * b];
+        return std::make_tuple(x[1], x[2], x[0]) < std::make_tuple(y[1], y[2], y[0]);
+      });
+    for (int B : {0, 4, 8, 16}) {
+      KernelOrder o;
+      o.jk = jk;
+      o.ord = base;
+      if (B > 0)
+        std::stable_sort(o.ord.begin(), o.ord.end(),
+                         [&](int a, int b) { return p->trips[3 * a + 1] / B < p->trips[3 * b + 1] / B; });
+      o.start = split_groups(p, o.ord, rw, &o.waves);
+      if (o.start.empty()) continue;
+      const int64_t cost = kStagedRingCost * staged_rings(p, o.ord, o.start, o.waves) +
+                           pairs_formed(p, o.ord, o.start, jk) + T;
+      if (best_cost < 0 || cost < best_cost) {
+        best_cost = cost;
+        best = std::move(o);
+      }
     }
   }
   return best;
@@ -274,7 +311,7 @@ KernelOrder choose_order(const abs_plan_s* p, int rw) {
 // publishes chunk c.  Workgroups are numbered so that the slices of one pixel block
 // run on one XCD (blocks are dealt to the 8 XCDs round robin), where they share L2.
 void emit_kernel(const abs_plan_s* p, const std::vector<int>& ord, const std::vector<int>& start, int W,
-                 int z0, int z1, const char* name, const char* R, std::string& s) {
+                 bool jk, int z0, int z1, const char* name, const char* R, std::string& s) {
   char buf[1024];
   const int G = (int)start.size() - 1;   // a multiple of W
   const int GZ = G / W;
@@ -368,16 +405,18 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& ord, const std::ve
       }
       std::snprintf(buf, sizeof buf, "    {\n    %s t;\n", R);
       r += buf;
-      int ci = -1, cj = -1;
+      // pair (a, b) and single ring c of each triplet: (i, j) and k, or (j, k) and i
+      int pa = -1, pb = -1;
       for (int t = t0; t < t1; ++t) {
-        const int i = p->trips[3 * ord[t]], j = p->trips[3 * ord[t] + 1], k = p->trips[3 * ord[t] + 2];
-        if (i != ci || j != cj) {
-          std::snprintf(buf, sizeof buf, "    t = d%d_%s * d%d_%s;\n", i, stage, j, stage);
+        const int* x = &p->trips[3 * ord[t]];
+        const int a = jk ? x[1] : x[0], b = jk ? x[2] : x[1], c = jk ? x[0] : x[2];
+        if (a != pa || b != pb) {
+          std::snprintf(buf, sizeof buf, "    t = d%d_%s * d%d_%s;\n", a, stage, b, stage);
           r += buf;
-          ci = i;
-          cj = j;
+          pa = a;
+          pb = b;
         }
-        std::snprintf(buf, sizeof buf, "    a%d = abs_fma(t, d%d_%s, a%d);\n", t - t0, k, stage, t - t0);
+        std::snprintf(buf, sizeof buf, "    a%d = abs_fma(t, d%d_%s, a%d);\n", t - t0, c, stage, t - t0);
         r += buf;
       }
       r += "    }\n";
@@ -458,7 +497,7 @@ bool build_jit_source(abs_plan_s* p) {
       "  __builtin_amdgcn_wave_barrier();\n}\n";
   p->parts.clear();
   auto add = [&](int kind, const std::vector<int>& ord, const std::vector<int>& start, int W,
-                 const char* R) {
+                 bool jk, const char* R) {
     const int GZ = ((int)start.size() - 1) / W;
     for (int z0 = 0; z0 < GZ; z0 += kSlicesPerPart) {
       JitPart part;
@@ -466,13 +505,13 @@ bool build_jit_source(abs_plan_s* p) {
       part.z0 = z0;
       part.z1 = std::min(GZ, z0 + kSlicesPerPart);
       part.src = head;
-      emit_kernel(p, ord, start, W, part.z0, part.z1, "abs_contract", R, part.src);
+      emit_kernel(p, ord, start, W, jk, part.z0, part.z1, "abs_contract", R, part.src);
       p->parts.push_back(std::move(part));
     }
   };
   // the FP32 kernel serves the FP32 data path; the weight fields always use FP64
-  if (p->precision == ABS_FP32) add(0, o32.ord, g32, w32, "float");
-  add(1, o64.ord, g64, w64, "double");
+  if (p->precision == ABS_FP32) add(0, o32.ord, g32, w32, o32.jk, "float");
+  add(1, o64.ord, g64, w64, o64.jk, "double");
   return true;
 }
 
