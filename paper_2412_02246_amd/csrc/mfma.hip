@@ -179,18 +179,23 @@ mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long lon
   }
 
   // The chunk's global loads are issued one chunk ahead (registers), so their latency
-  // overlaps the matrix work on the previous chunk.  Thread q stages the values
-  // (m, x) = divmod(threadIdx.x + kMfmaThreads * u, kChunk), u < kStage.
-  constexpr int kStage = (kMaxBins * kChunk) / kMfmaThreads;
-  const int nstage = (nb * kChunk + kMfmaThreads - 1) / kMfmaThreads;
-  float pre[kStage];
+  // overlaps the matrix work on the previous chunk.  Thread q stages the pixel pairs
+  // (m, x / 2) = divmod(threadIdx.x + kMfmaThreads * u, kChunk / 2), u < kStage: 8-byte
+  // loads, and whole-word LDS stores of the two pixels' values and halves.
+  constexpr int kStage = (kMaxBins * kChunk / 2) / kMfmaThreads;
+  const int nstage = (nb * kChunk / 2 + kMfmaThreads - 1) / kMfmaThreads;
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef HT h16x2 __attribute__((ext_vector_type(2)));
+  f32x2 pre[kStage];
   auto load_chunk = [&](long long c0) {
 #pragma unroll
     for (int u = 0; u < kStage; ++u) {
       const int q = threadIdx.x + kMfmaThreads * u;
-      const int m = q / kChunk, x = q - m * kChunk;
-      const long long p = c0 + x;
-      pre[u] = (u < nstage && m < nb && p < p1) ? Fs[(long long)m * npix + p] : 0.f;
+      const int m = q / (kChunk / 2), x = 2 * (q - m * (kChunk / 2));
+      const long long p = c0 + x;   // p1 and p are even: p < p1 covers both pixels
+      pre[u] = (u < nstage && m < nb && p < p1)
+                   ? *reinterpret_cast<const f32x2*>(Fs + (long long)m * npix + p)
+                   : f32x2{0.f, 0.f};
     }
   };
   if (p0 < p1) load_chunk(p0);
@@ -199,15 +204,18 @@ mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long lon
 #pragma unroll
     for (int u = 0; u < kStage; ++u) {
       const int q = threadIdx.x + kMfmaThreads * u;
-      const int m = q / kChunk, x = q - m * kChunk;
+      const int m = q / (kChunk / 2), x = 2 * (q - m * (kChunk / 2));
       if (u < nstage && m < nb) {
-        float v = pre[u];
-        if (scaled) v = ldexpf(v, kF16Exp - sexp[m]);
-        const HT h = (HT)v;
-        const HT l = (HT)(v - (float)h);
-        d32[m * kRow32 + x] = v;
-        dhi[m * kRow16 + x] = h;
-        dlo[m * kRow16 + x] = l;
+        f32x2 v = pre[u];
+        if (scaled) {
+          v.x = ldexpf(v.x, kF16Exp - sexp[m]);
+          v.y = ldexpf(v.y, kF16Exp - sexp[m]);
+        }
+        const h16x2 h = {(HT)v.x, (HT)v.y};
+        const h16x2 l = {(HT)(v.x - (float)h.x), (HT)(v.y - (float)h.y)};
+        *reinterpret_cast<f32x2*>(d32 + m * kRow32 + x) = v;
+        *reinterpret_cast<h16x2*>(dhi + m * kRow16 + x) = h;
+        *reinterpret_cast<h16x2*>(dlo + m * kRow16 + x) = l;
       }
     }
     __syncthreads();

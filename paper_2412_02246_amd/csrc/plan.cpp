@@ -577,8 +577,7 @@ abs_status compile_jit(abs_plan_s* p, int part) {
 // k: 228 against 528 at 32 rings, 855 against 2080 at 64).  Pairs ordered by (j, k) are cut
 // into row tiles of 16; each row tile multiplies against the union of its rings i, 16 per
 // MFMA tile, and all column tiles of a row tile share it (the kernel forms its operand once
-// and keeps it while the wave's consecutive tiles use the same rows).  Tiles are dealt to
-// waves in contiguous, balanced runs of at most kTilesPerWave.
+// and keeps it while the wave's consecutive tiles use the same rows).
 void build_mfma_tables(abs_plan_s* p) {
   const int nb = p->nb;
   std::vector<std::vector<int>> cset(nb * nb);
@@ -597,6 +596,8 @@ void build_mfma_tables(abs_plan_s* p) {
   p->mt_bins.clear();
   p->mt_trip.clear();
   const int npt = (int)((pairs.size() + 15) / 16);
+  std::vector<std::vector<std::vector<int>>> ctiles(npt);   // column tiles of each row tile
+  int T = 0;
   for (int pt = 0; pt < npt; ++pt) {
     std::set<int> cs;
     for (int r = 0; r < 16; ++r) {
@@ -613,28 +614,62 @@ void build_mfma_tables(abs_plan_s* p) {
     }
     const std::vector<int> cv(cs.begin(), cs.end());
     for (size_t c0 = 0; c0 < cv.size(); c0 += 16) {
-      p->mt_ptile.push_back(pt);
-      int cols[16];
+      std::vector<int> cols(16);
       for (int c = 0; c < 16; ++c) cols[c] = c0 + c < cv.size() ? cv[c0 + c] : nb;
-      for (int c = 0; c < 16; ++c) p->mt_bins.push_back(cols[c]);
-      for (int r = 0; r < 16; ++r) {
-        const int j = p->pt_pairs[2 * (pt * 16 + r)], k = p->pt_pairs[2 * (pt * 16 + r) + 1];
-        for (int c = 0; c < 16; ++c) {
-          const int i = cols[c];
-          p->mt_trip.push_back(j < nb && i < nb ? tindex[(j * nb + k) * nb + i] : -1);
-        }
-      }
+      ctiles[pt].push_back(cols);
+      ++T;
     }
   }
-  const int T = (int)p->mt_ptile.size();
+  // Row tiles (with all their column tiles) are dealt to waves longest first, each to the
+  // least loaded wave with room (longest-processing-time rule); a wave's cost counts 2
+  // per tile (its matrix work and column operand) and 5 per row tile (forming and
+  // splitting the pair products, the larger part).  Early row tiles (small rings) have
+  // one column tile, late ones up to four, so equal tile counts would be unequal work.
+  auto cost = [&](int pt) { return 5 + 2 * (int)ctiles[pt].size(); };
+  std::vector<int> order(npt);
+  for (int pt = 0; pt < npt; ++pt) order[pt] = pt;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
   int waves = std::max(8, (T + kTilesPerWave - 1) / kTilesPerWave);
   waves = (waves + 7) / 8 * 8;
+  std::vector<std::vector<int>> assign;
+  for (;; waves += 8) {
+    std::vector<int> load(waves, 0), cnt(waves, 0);
+    assign.assign(waves, {});
+    bool ok = true;
+    for (int pt : order) {
+      int best = -1;
+      for (int w = 0; w < waves; ++w)
+        if (cnt[w] + (int)ctiles[pt].size() <= kTilesPerWave && (best < 0 || load[w] < load[best])) best = w;
+      if (best < 0) {
+        ok = false;
+        break;
+      }
+      assign[best].push_back(pt);
+      load[best] += cost(pt);
+      cnt[best] += (int)ctiles[pt].size();
+    }
+    if (ok) break;
+  }
   p->mfma_groups = waves / 8;
   p->wave_tiles.assign(2 * waves, 0);
+  int tile = 0;
   for (int w = 0; w < waves; ++w) {
-    const int a = (int)((int64_t)T * w / waves), b = (int)((int64_t)T * (w + 1) / waves);
-    p->wave_tiles[2 * w] = a;
-    p->wave_tiles[2 * w + 1] = b - a;
+    std::sort(assign[w].begin(), assign[w].end());
+    p->wave_tiles[2 * w] = tile;
+    for (int pt : assign[w])
+      for (const std::vector<int>& cols : ctiles[pt]) {
+        p->mt_ptile.push_back(pt);
+        for (int c = 0; c < 16; ++c) p->mt_bins.push_back(cols[c]);
+        for (int r = 0; r < 16; ++r) {
+          const int j = p->pt_pairs[2 * (pt * 16 + r)], k = p->pt_pairs[2 * (pt * 16 + r) + 1];
+          for (int c = 0; c < 16; ++c) {
+            const int i = cols[c];
+            p->mt_trip.push_back(j < nb && i < nb ? tindex[(j * nb + k) * nb + i] : -1);
+          }
+        }
+        ++tile;
+      }
+    p->wave_tiles[2 * w + 1] = tile - p->wave_tiles[2 * w];
   }
 }
 
