@@ -71,7 +71,7 @@ PEAK_HBM = 8.0e12
 # WRITE_SIZE passes scaled by a 1 GiB copy (2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE), for the
 # kernel as it stands in this tree (profiles/counters_mwa1024_batch16.md); a workload or
 # precision without an entry reports null.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {("mwa1024", "fp32"): 1348.6e6}
 
 
 def parse():
