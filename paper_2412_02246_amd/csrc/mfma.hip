@@ -118,7 +118,7 @@ size_t mfma_lds_bytes(int nb) {
   return (size_t)(nb + 1) * (kRow32 * 4 + 2 * kRow16 * 2);
 }
 
-template <bool F16>
+template <bool F16, int NBMAX, int DEPTH>
 __global__ void __launch_bounds__(kMfmaThreads)
 mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long long npix, int ppb,
                      double* __restrict__ part, int nblk, int ntrip, int nb,
@@ -178,35 +178,49 @@ mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long lon
     }
   }
 
-  // The chunk's global loads are issued one chunk ahead (registers), so their latency
-  // overlaps the matrix work on the previous chunk.  Thread q stages the pixel pairs
+  // The chunk's global loads are issued DEPTH chunks ahead into registers (DEPTH buffers,
+  // used in turn), so that several chunks' loads are in flight while the matrix work runs:
+  // with few rings a chunk's work is short and one chunk ahead leaves the memory latency
+  // exposed.  Thread q stages the pixel pairs
   // (m, x / 2) = divmod(threadIdx.x + kMfmaThreads * u, kChunk / 2), u < kStage: 8-byte
   // loads, and whole-word LDS stores of the two pixels' values and halves.
-  constexpr int kStage = (kMaxBins * kChunk / 2) / kMfmaThreads;
+  constexpr int kStage = (NBMAX * kChunk / 2) / kMfmaThreads;
   const int nstage = (nb * kChunk / 2 + kMfmaThreads - 1) / kMfmaThreads;
   typedef float f32x2 __attribute__((ext_vector_type(2)));
   typedef HT h16x2 __attribute__((ext_vector_type(2)));
-  f32x2 pre[kStage];
-  auto load_chunk = [&](long long c0) {
+  f32x2 pre[DEPTH][kStage];
+  auto load_chunk = [&](f32x2 (&buf)[kStage], long long c0) {
 #pragma unroll
     for (int u = 0; u < kStage; ++u) {
       const int q = threadIdx.x + kMfmaThreads * u;
       const int m = q / (kChunk / 2), x = 2 * (q - m * (kChunk / 2));
-      const long long p = c0 + x;   // p1 and p are even: p < p1 covers both pixels
-      pre[u] = (u < nstage && m < nb && p < p1)
-                   ? *reinterpret_cast<const f32x2*>(Fs + (long long)m * npix + p)
-                   : f32x2{0.f, 0.f};
+      // Unconditional loads from clamped addresses: entries past the last ring or past the
+      // block end (prefetch beyond the last chunk) are never staged, and loads that are all
+      // issued let the compiler wait for one buffer without waiting for the others.
+      // Blocks hold whole chunks (p0, p1 multiples of kChunk), p1 - 2 >= p0.
+      const int mc = m < nb ? m : nb - 1;
+      const long long p = c0 + x;
+      const long long pc = p < p1 ? p : p1 - 2;
+      buf[u] = *reinterpret_cast<const f32x2*>(Fs + (long long)mc * npix + pc);
     }
   };
-  if (p0 < p1) load_chunk(p0);
-  for (long long c0 = p0; c0 < p1; c0 += kChunk) {
+#pragma unroll
+  for (int b = 0; b < DEPTH; ++b) load_chunk(pre[b], p0 + (long long)b * kChunk);
+  for (long long cb = p0; cb < p1; cb += (long long)DEPTH * kChunk) {
+#pragma unroll
+  for (int b = 0; b < DEPTH; ++b) {
+    // Every phase runs, also past the block end (only blocks shorter than DEPTH chunks
+    // have such phases; they stage zeros, which add nothing): no path skips a phase's
+    // loads, so the compiler can wait for one buffer while the later ones stay in flight.
+    const long long c0 = cb + (long long)b * kChunk;
+    const bool live = c0 < p1;
     // stage the chunk: FP32 values (scaled for FP16) and their hi / lo halves
 #pragma unroll
     for (int u = 0; u < kStage; ++u) {
       const int q = threadIdx.x + kMfmaThreads * u;
       const int m = q / (kChunk / 2), x = 2 * (q - m * (kChunk / 2));
       if (u < nstage && m < nb) {
-        f32x2 v = pre[u];
+        f32x2 v = live ? pre[b][u] : f32x2{0.f, 0.f};
         if (scaled) {
           v.x = ldexpf(v.x, kF16Exp - sexp[m]);
           v.y = ldexpf(v.y, kF16Exp - sexp[m]);
@@ -219,7 +233,8 @@ mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long lon
       }
     }
     __syncthreads();
-    if (c0 + kChunk < p1) load_chunk(c0 + kChunk);
+    // the buffer is free again: load the chunk DEPTH ahead into it (masked off past p1)
+    load_chunk(pre[b], c0 + (long long)DEPTH * kChunk);
     // A operand (the row tile's pair products, split) and B operand (the tile's ring
     // columns, split) for the chunk's kChunk/32 k-steps, each kept while consecutive tiles
     // of the wave use the same rows / columns
@@ -269,6 +284,7 @@ mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long lon
     }
     __syncthreads();
   }
+  }
 
   // lane holds C[4 * quad + q][row] of each of its tiles
   double* __restrict__ out = part + (set * nblk + blockIdx.x) * (long long)ntrip;
@@ -306,27 +322,19 @@ hipError_t launch_mfma_contract(const abs_plan_s* p, const float* F, long long f
   const size_t lds = mfma_lds_bytes(p->nb);
   const dim3 grid((unsigned)p->nblk, (unsigned)nsets, (unsigned)p->mfma_groups);
   const long long npix = (long long)p->n * p->n;
-  if (p->precision == ABS_FP16X3) {
-    auto k = mfma_contract_kernel<true>;
-    if (lds > 65536) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    k<<<grid, kMfmaThreads, lds, st>>>(F, fset, npix, p->pix_per_block, part, p->nblk, (int)p->ntrip,
-                                       p->nb, pt_pairs, mt_ptile, mt_bins, mt_trip, wave_tiles,
-                                       fmax_bits);
-  } else {
-    auto k = mfma_contract_kernel<false>;
-    if (lds > 65536) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    k<<<grid, kMfmaThreads, lds, st>>>(F, fset, npix, p->pix_per_block, part, p->nblk, (int)p->ntrip,
-                                       p->nb, pt_pairs, mt_ptile, mt_bins, mt_trip, wave_tiles,
-                                       nullptr);
+  // plans of at most 32 rings: four chunks in flight (their work per chunk is short);
+  // larger plans: one, which keeps the registers for the tiles
+  const bool f16 = p->precision == ABS_FP16X3;
+  auto k = f16 ? (p->nb <= 32 ? mfma_contract_kernel<true, 32, 4> : mfma_contract_kernel<true, kMaxBins, 1>)
+               : (p->nb <= 32 ? mfma_contract_kernel<false, 32, 4> : mfma_contract_kernel<false, kMaxBins, 1>);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
   }
+  k<<<grid, kMfmaThreads, lds, st>>>(F, fset, npix, p->pix_per_block, part, p->nblk, (int)p->ntrip, p->nb,
+                                     pt_pairs, mt_ptile, mt_bins, mt_trip, wave_tiles,
+                                     f16 ? fmax_bits : nullptr);
   return hipGetLastError();
 }
 
