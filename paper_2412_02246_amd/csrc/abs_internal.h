@@ -14,6 +14,7 @@ namespace abs_impl {
 constexpr int kBlock = 256;          // threads per workgroup for every kernel here
 constexpr int kMaxBins = 64;
 constexpr int kTilesPerWave = 12;    // MFMA output tiles owned by one wave (precision form)
+constexpr int kSmallTilesPerWave = 2;   // the same for small plans (kernel variant)
 constexpr int kMaxN = 8192;
 
 // One contiguous run of uv columns gx0 .. gx0 + ncols - 1 of ring m, transformed
@@ -89,6 +90,7 @@ struct abs_plan_s {
   std::vector<int> mt_trip;      // 256 per MFMA tile: triplet index or -1
   std::vector<int> wave_tiles;   // 2 per wave: first tile, count
   int mfma_groups = 0;           // workgroups (of 8 waves) per pixel block and set
+  int mfma_tpw = 0;              // tiles per wave of the kernel variant the plan uses
   // contraction kernel (compiled at run time for this triplet list)
   int ngroups = 0;               // wave groups of the FP32 kernel; one wave per group
   int ngroups64 = 0;             // wave groups of the FP64 kernel (weight fields)

@@ -19,8 +19,11 @@
 //
 // Workgroup: 8 waves; blockIdx.x = pixel block, blockIdx.y = set, blockIdx.z = wave
 // group.  Per chunk of kChunk pixels the workgroup stages the rings' FP32 values and their
-// hi/lo halves in LDS; each wave then evaluates its MFMA tiles (at most kTilesPerWave,
-// accumulators in registers across the whole pixel block).  The A operand (the row tile's
+// hi/lo halves in LDS; each wave then evaluates its MFMA tiles (at most TPW,
+// accumulators in registers across the whole pixel block).  Variants: TPW = kTilesPerWave
+// with DEPTH chunks of loads in flight (4 for up to 32 rings, 1 above), and for small
+// plans TPW = kSmallTilesPerWave, whose 128 registers a lane let two workgroups share a
+// CU, so one workgroup's staging and barriers overlap the other's matrix work.  The A operand (the row tile's
 // pair products, split) is formed once per chunk and kept for the wave's consecutive tiles
 // of that row tile; the B operand likewise while the columns stay the same.
 #include "abs_internal.h"
@@ -118,8 +121,8 @@ size_t mfma_lds_bytes(int nb) {
   return (size_t)(nb + 1) * (kRow32 * 4 + 2 * kRow16 * 2);
 }
 
-template <bool F16, int NBMAX, int DEPTH>
-__global__ void __launch_bounds__(kMfmaThreads)
+template <bool F16, int NBMAX, int DEPTH, int TPW>
+__global__ void __launch_bounds__(kMfmaThreads, TPW <= 2 ? 4 : 2)
 mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long long npix, int ppb,
                      double* __restrict__ part, int nblk, int ntrip, int nb,
                      const int2* __restrict__ pt_pairs, const int* __restrict__ mt_ptile,
@@ -161,15 +164,15 @@ mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long lon
     dlo[nb * kRow16 + q] = (HT)0.f;
   }
 
-  f32x4 acc[kTilesPerWave];
+  f32x4 acc[TPW];
 #pragma unroll
-  for (int s = 0; s < kTilesPerWave; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int s = 0; s < TPW; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
   // this lane's row of each tile, packed j | k << 8 | column ring << 16 (rings <= kMaxBins,
   // the zero row included), read once: no global load inside the chunk loop, whose
   // in-order completion count would otherwise also wait for the next chunk's prefetch
-  unsigned meta[kTilesPerWave];
+  unsigned meta[TPW];
 #pragma unroll
-  for (int s = 0; s < kTilesPerWave; ++s) {
+  for (int s = 0; s < TPW; ++s) {
     meta[s] = 0;
     if (s < wr.y) {
       const int tile = wr.x + s;
@@ -242,7 +245,7 @@ mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long lon
     unsigned held_rows = ~0u;   // pair (j | k << 8) held by this lane (none yet)
     int held = -1;              // column ring held by this lane (-1: none yet)
 #pragma unroll
-    for (int s = 0; s < kTilesPerWave; ++s) {
+    for (int s = 0; s < TPW; ++s) {
       if (s < wr.y) {
         // opaque copy: keeps the compiler from hoisting the decoded addresses of every
         // tile out of the chunk loop (three live registers a tile instead of one)
@@ -289,7 +292,7 @@ mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long lon
   // lane holds C[4 * quad + q][row] of each of its tiles
   double* __restrict__ out = part + (set * nblk + blockIdx.x) * (long long)ntrip;
 #pragma unroll
-  for (int s = 0; s < kTilesPerWave; ++s) {
+  for (int s = 0; s < TPW; ++s) {
     if (s < wr.y) {
       const int tile = wr.x + s;
       const int pt = mt_ptile[tile];
@@ -325,8 +328,12 @@ hipError_t launch_mfma_contract(const abs_plan_s* p, const float* F, long long f
   // plans of at most 32 rings: four chunks in flight (their work per chunk is short);
   // larger plans: one, which keeps the registers for the tiles
   const bool f16 = p->precision == ABS_FP16X3;
-  auto k = f16 ? (p->nb <= 32 ? mfma_contract_kernel<true, 32, 4> : mfma_contract_kernel<true, kMaxBins, 1>)
-               : (p->nb <= 32 ? mfma_contract_kernel<false, 32, 4> : mfma_contract_kernel<false, kMaxBins, 1>);
+  auto k = f16 ? (p->mfma_tpw == kSmallTilesPerWave ? mfma_contract_kernel<true, 32, 1, kSmallTilesPerWave>
+                  : p->nb <= 32   ? mfma_contract_kernel<true, 32, 4, kTilesPerWave>
+                                  : mfma_contract_kernel<true, kMaxBins, 1, kTilesPerWave>)
+               : (p->mfma_tpw == kSmallTilesPerWave ? mfma_contract_kernel<false, 32, 1, kSmallTilesPerWave>
+                  : p->nb <= 32   ? mfma_contract_kernel<false, 32, 4, kTilesPerWave>
+                                  : mfma_contract_kernel<false, kMaxBins, 1, kTilesPerWave>);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -629,26 +629,34 @@ void build_mfma_tables(abs_plan_s* p) {
   std::vector<int> order(npt);
   for (int pt = 0; pt < npt; ++pt) order[pt] = pt;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
-  int waves = std::max(8, (T + kTilesPerWave - 1) / kTilesPerWave);
-  waves = (waves + 7) / 8 * 8;
+  // Deal the row tiles to `waves` waves of at most `cap` tiles each; false if one does
+  // not fit.
   std::vector<std::vector<int>> assign;
-  for (;; waves += 8) {
+  auto deal = [&](int waves, int cap) {
     std::vector<int> load(waves, 0), cnt(waves, 0);
     assign.assign(waves, {});
-    bool ok = true;
     for (int pt : order) {
       int best = -1;
       for (int w = 0; w < waves; ++w)
-        if (cnt[w] + (int)ctiles[pt].size() <= kTilesPerWave && (best < 0 || load[w] < load[best])) best = w;
-      if (best < 0) {
-        ok = false;
-        break;
-      }
+        if (cnt[w] + (int)ctiles[pt].size() <= cap && (best < 0 || load[w] < load[best])) best = w;
+      if (best < 0) return false;
       assign[best].push_back(pt);
       load[best] += cost(pt);
       cnt[best] += (int)ctiles[pt].size();
     }
-    if (ok) break;
+    return true;
+  };
+  // Small plans (at most 32 rings, 8 waves of at most kSmallTilesPerWave tiles) use the
+  // kernel variant with few accumulators, whose registers allow two workgroups per CU;
+  // others the one with kTilesPerWave, in as many 8-wave groups as needed.
+  int waves = 8;
+  if (nb <= 32 && deal(8, kSmallTilesPerWave)) {
+    p->mfma_tpw = kSmallTilesPerWave;
+  } else {
+    p->mfma_tpw = kTilesPerWave;
+    waves = std::max(8, (T + kTilesPerWave - 1) / kTilesPerWave);
+    waves = (waves + 7) / 8 * 8;
+    while (!deal(waves, kTilesPerWave)) waves += 8;
   }
   p->mfma_groups = waves / 8;
   p->wave_tiles.assign(2 * waves, 0);
