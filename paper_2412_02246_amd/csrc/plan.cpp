@@ -571,6 +571,41 @@ abs_status compile_jit(abs_plan_s* p, int part) {
   return ABS_OK;
 }
 
+// Row order inside a row tile.  A lane of row r reads 16 bytes of ring j_r and of ring
+// k_r at the same pixel offset; with LDS rows of 132 words, ring m starts in bank group
+// m mod 8 (of 32 banks) or m mod 16 (of 64), so two rows of one access group reading
+// different rings of the same group conflict.  Local search over row swaps minimises such
+// clashes within groups of 8 and of 16 consecutive rows (the pair list is unchanged).
+void order_rows(std::vector<std::pair<int, int>>& rows) {
+  const int R = (int)rows.size();
+  auto clash = [](int a, int b, int mod) { return a != b && a % mod == b % mod; };
+  auto cost = [&]() {
+    int c = 0;
+    for (int a = 0; a < R; ++a)
+      for (int b = a + 1; b < R; ++b) {
+        const bool same8 = a / 8 == b / 8;
+        c += clash(rows[a].second, rows[b].second, 16) + clash(rows[a].first, rows[b].first, 16);
+        if (same8) c += clash(rows[a].second, rows[b].second, 8) + clash(rows[a].first, rows[b].first, 8);
+      }
+    return c;
+  };
+  int best = cost();
+  for (bool improved = true; improved && best > 0;) {
+    improved = false;
+    for (int a = 0; a < R; ++a)
+      for (int b = a + 1; b < R; ++b) {
+        std::swap(rows[a], rows[b]);
+        const int c = cost();
+        if (c < best) {
+          best = c;
+          improved = true;
+        } else {
+          std::swap(rows[a], rows[b]);
+        }
+      }
+  }
+}
+
 // Precision-form tiling.  Each triplet i <= j <= k is split as the pair product of its two
 // largest rings, D_j D_k, times the smallest ring D_i (a pair (j, k) closes triangles with
 // a run of small rings i, which gives far fewer distinct pairs than (i, j) pairs with their
@@ -600,17 +635,18 @@ void build_mfma_tables(abs_plan_s* p) {
   int T = 0;
   for (int pt = 0; pt < npt; ++pt) {
     std::set<int> cs;
+    std::vector<std::pair<int, int>> rows(16, {nb, nb});
     for (int r = 0; r < 16; ++r) {
       const size_t q = (size_t)pt * 16 + r;
       if (q < pairs.size()) {
-        const int j = pairs[q].first, k = pairs[q].second;
-        p->pt_pairs.push_back(j);
-        p->pt_pairs.push_back(k);
-        for (int i : cset[j * nb + k]) cs.insert(i);
-      } else {
-        p->pt_pairs.push_back(nb);
-        p->pt_pairs.push_back(nb);
+        rows[r] = pairs[q];
+        for (int i : cset[pairs[q].first * nb + pairs[q].second]) cs.insert(i);
       }
+    }
+    order_rows(rows);
+    for (const auto& jk : rows) {
+      p->pt_pairs.push_back(jk.first);
+      p->pt_pairs.push_back(jk.second);
     }
     const std::vector<int> cv(cs.begin(), cs.end());
     for (size_t c0 = 0; c0 < cv.size(); c0 += 16) {
