@@ -499,11 +499,14 @@ bool build_jit_source(abs_plan_s* p) {
   auto add = [&](int kind, const std::vector<int>& ord, const std::vector<int>& start, int W,
                  bool jk, const char* R) {
     const int GZ = ((int)start.size() - 1) / W;
-    for (int z0 = 0; z0 < GZ; z0 += kSlicesPerPart) {
+    // FP64 parts hold more slices: the slices of one launch run together and can share
+    // their field reads through L2, and the weight fields are 8 bytes a value
+    const int per = kind == 1 ? 3 * kSlicesPerPart : kSlicesPerPart;
+    for (int z0 = 0; z0 < GZ; z0 += per) {
       JitPart part;
       part.kind = kind;
       part.z0 = z0;
-      part.z1 = std::min(GZ, z0 + kSlicesPerPart);
+      part.z1 = std::min(GZ, z0 + per);
       part.src = head;
       emit_kernel(p, ord, start, W, jk, part.z0, part.z1, "abs_contract", R, part.src);
       p->parts.push_back(std::move(part));
