@@ -114,16 +114,25 @@ def cpu_baseline(n, edges, trips, uv, vis, norm, budget_s):
 def copy_probe(a):
     """A plain device copy of a known size (1 GiB read + 1 GiB written per launch), run
     under the same rocprofv3 counters as the kernels to calibrate FETCH_SIZE and
-    WRITE_SIZE against bytes actually moved."""
+    WRITE_SIZE against bytes actually moved; also the copy's achieved HBM rate, the
+    practical ceiling next to the 8 TB/s datasheet figure."""
     import torch
     torch.cuda.set_device(0)
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(a.warmup + a.steps):
+    for _ in range(a.warmup):
         dst.copy_(src)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_per_launch": 2 * src.numel() * 4,
-                      "launches": a.warmup + a.steps}), flush=True)
+    t0.record()
+    for _ in range(a.steps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    nbytes = 2 * src.numel() * 4
+    print(json.dumps({"copy_probe_bytes_per_launch": nbytes, "launches": a.warmup + a.steps,
+                      "copy_gb_per_s": nbytes * a.steps / (t0.elapsed_time(t1) * 1e-3) / 1e9}),
+          flush=True)
 
 
 def serve_bench(a):
