@@ -9,7 +9,7 @@ Definition followed (Gill et al. 2024, Sec. 2):
 with l_g . theta = 2 pi g . x / n on the n x n periodic grid, so each field is a
 plain forward 2-D DFT of its masked ring (scipy.fft.fft2, FP64).
 
-Readings (also listed in the design doc):
+Readings of the paper where it is silent or ambiguous:
 * the input is defined through its Hermitian part, X(g) = (W V(g) + conj(W V(-g)))/2
   and Y(g) = (W(g) + W(-g))/2, so both fields are real; for Hermitian input this
   is exactly the paper's sum (the imaginary part of the triple sum is zero);

@@ -6,7 +6,7 @@ Source: Gill et al. 2024, Sec. 2, Eq. (9): V_g = sum_i w~(U_g - U_i) V(U_i) with
 visibility assigned to the nearest grid point, N_g the number of contributing
 visibilities, and Sec. 3: grid spacing dU_g = sqrt(ln 2) / (pi theta_0).
 
-Readings (also listed in the design doc):
+Readings of the paper where it is silent or ambiguous:
 * nearest cell = round-half-to-even of u / dU_g in FP64 (numpy.rint), a rule that
   is symmetric under U -> -U;
 * every visibility also contributes conj(V) at -g, because the sky is real and

@@ -11,7 +11,7 @@ Sources (Gill et al. 2024):
 * Sec. 2, below Eq. (3): ell_1 >= ell_2 >= ell_3, mu = (l1^2 + l2^2 - l3^2)/(2 l1 l2),
   t = l2 / l1 (Sec. 2 after Eq. 12 gives the same mu in terms of side lengths).
 
-Readings where the paper is silent (each one is also listed in the design doc):
+Readings where the paper is silent:
 * ring membership is half-open, lo <= |g| < hi, decided with the exact integer
   |g|^2 compared against the FP64 squares of the edges;
 * a triplet (i <= j <= k) exists when its rings contain at least one closed
