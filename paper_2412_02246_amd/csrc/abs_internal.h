@@ -56,7 +56,8 @@ struct WorkLayout {
   int nisets;
   size_t zd, zi, fd, fi, part, part64, fmax, xc, total;
   int64_t zset;       // complex elements per set of column-pass output
-  int64_t fset;       // values per set of fields (nbins * n * n)
+  int64_t fset;       // values per set of data fields (nbins * n * n)
+  int64_t fset64;     // values per set of weight fields (nbins * npix64)
   int64_t partset;    // doubles per data set of contraction partials (nblk * ntrip)
   int64_t partset64;  // doubles per weight set (nblk64 * ntrip)
 };
@@ -100,6 +101,11 @@ struct abs_plan_s {
   int nblk = 0;                  // contraction pixel blocks per data set
   int pix_per_block64 = 0;       // the same for the FP64 weight sets (fewer sets: smaller blocks)
   int nblk64 = 0;
+  // Weight fields are even (I(-x, -y) = I(x, y): the weights are real and symmetric), so
+  // only rows 0 .. n/2 are formed, per ring in npix64 values: block 0 holds rows 0 and
+  // n/2 (then zeros), blocks 1 .. nblk64 - 1 rows 1 .. n/2 - 1 (then zeros); the sum over
+  // all pixels is block 0 plus twice the others.
+  int64_t npix64 = 0;
   std::vector<abs_impl::JitPart> parts;   // contraction code, compiled per part
   // device binding
   abs_impl::DevLayout dl{};

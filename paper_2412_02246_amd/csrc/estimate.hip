@@ -48,6 +48,16 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
   return ((q4[0][lane] + q4[1][lane]) + q4[2][lane]) + q4[3][lane];
 }
 
+// Weight-set sum over all pixels from the half-plane partials: block 0 (rows 0 and n/2,
+// their own mirrors) plus twice blocks 1 .. nblk64 - 1 (rows 1 .. n/2 - 1, each standing
+// for itself and its mirror row).  The factor 2 is exact.
+__device__ __forceinline__ double sum_partials_half(const double* __restrict__ part64, int nblk64,
+                                                    int ntrip, const int* __restrict__ pos64, int t) {
+  const double rest = sum_partials(part64 + ntrip, nblk64 - 1, ntrip, pos64, t);
+  const double b0 = t < ntrip ? part64[pos64 ? pos64[t] : t] : 0.0;
+  return b0 + 2.0 * rest;
+}
+
 // B[b][t] = S / (A N), S and N the per-triangle sums: workgroup partials are added
 // in FP64 in a fixed order and divided by n^2 (the sum over pixels of a product of
 // three DFTs counts every closed triangle n^2 times).  Block: 64 triplets of grid b.
@@ -65,7 +75,7 @@ finalize_kernel(const double* __restrict__ part, long long partset, int nblk, co
     nn = t < ntrip ? n_given[t] : 0.0;
   } else {
     const int is = nisets > 1 ? b : 0;
-    nn = sum_partials(part64 + (long long)is * partset64, nblk64, ntrip, pos64, t) * inv_npix;
+    nn = sum_partials_half(part64 + (long long)is * partset64, nblk64, ntrip, pos64, t) * inv_npix;
   }
   if (threadIdx.x < 64 && t < ntrip) {
     B[(long long)b * ntrip + t] = s / (norm * nn);
@@ -78,7 +88,7 @@ __global__ void __launch_bounds__(kBlock)
 counts_kernel(const double* __restrict__ part64, int nblk64, const int* __restrict__ pos64, int ntrip,
               double inv_npix, double* __restrict__ N) {
   const int t = blockIdx.x * 64 + (threadIdx.x & 63);
-  const double nn = sum_partials(part64, nblk64, ntrip, pos64, t) * inv_npix;
+  const double nn = sum_partials_half(part64, nblk64, ntrip, pos64, t) * inv_npix;
   if (threadIdx.x < 64 && t < ntrip) N[t] = nn;
 }
 
@@ -150,9 +160,9 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
     double* F = reinterpret_cast<double*>(work + wl.fi);
     if (launch_colpass_weight(p, w, w_batched, wl.nisets, work + wl.xc, Z, wl.zset, st) != hipSuccess)
       return ABS_ERR_DEVICE;
-    if (launch_rowpass_f64(p, wl.nisets, Z, wl.zset, F, wl.fset, st) != hipSuccess)
+    if (launch_rowpass_f64(p, wl.nisets, Z, wl.zset, F, wl.fset64, st) != hipSuccess)
       return ABS_ERR_DEVICE;
-    return launch_contract(p, 1, p->waves64, F, wl.fset, npix, p->pix_per_block64,
+    return launch_contract(p, 1, p->waves64, F, wl.fset64, p->npix64, p->pix_per_block64,
                            p->nblk64, (int)p->ntrip, wl.nisets,
                            reinterpret_cast<double*>(work + wl.part64), st);
   }

@@ -274,12 +274,15 @@ __device__ __forceinline__ void fft_passes(typename Cx<R>::T* buf, int t, const 
 
 // Row pass with the compile-time engine.  blockIdx.x = ring m * blocks per ring + block,
 // each block covering G * iters row pairs; blockIdx.y = set.  FMAX records the largest
-// |F| per (set, ring) for the FP16 split form.
-template <typename R, int LOG2N, bool FMAX>
+// |F| per (set, ring) for the FP16 split form.  HALF (even fields, the weights): only the
+// row pairs up to row n/2 are transformed and the rows land in the half-plane layout,
+// row 0 at 0, row n/2 at n, row r in 1 .. n/2 - 1 at hb + (r - 1) n; rstride is the
+// values per ring (n^2, or the half-plane size).
+template <typename R, int LOG2N, bool FMAX, bool HALF>
 __global__ void __launch_bounds__(kBlock)
 rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename Cx<R>::T* __restrict__ tw,
                      const typename Cx<R>::T* __restrict__ Z, long long zset, R* __restrict__ F,
-                     long long fset, unsigned* __restrict__ fmax_bits, int nb) {
+                     long long fset, long long rstride, int hb, unsigned* __restrict__ fmax_bits, int nb) {
   using T = typename Cx<R>::T;
   using FF = Fft<LOG2N>;
   constexpr int n = FF::N;
@@ -297,25 +300,34 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
     twp = twl;
   }
   const int per_block = FF::G * iters;
-  const int nrb = (n / 2 + per_block - 1) / per_block;
+  constexpr int npairs = HALF ? n / 4 + 1 : n / 2;   // HALF: rows 0 .. n/2 (+ n/2 + 1)
+  const int nrb = (npairs + per_block - 1) / per_block;
   const int m = blockIdx.x / nrb, blk = blockIdx.x - m * nrb;
   const int set = blockIdx.y;
   const BinDev bin = bins[m];
   const int H = bin.h, cols = bin.cols;
-  R* __restrict__ fs = F + (long long)set * fset + (long long)m * n * n;
+  R* __restrict__ fs = F + (long long)set * fset + (long long)m * rstride;
+  // offset of row r in the ring's output, -1 for a row the layout does not keep
+  auto roff = [&](int r) -> long long {
+    if constexpr (!HALF) return (long long)r * n;
+    if (r == 0) return 0;
+    if (r == n / 2) return n;
+    if (r < n / 2) return (long long)hb + (long long)(r - 1) * n;
+    return -1;
+  };
   const T* __restrict__ zs = Z + (long long)set * zset + bin.zoff;
   Twiddles<R, LOG2N, false> twr;
   R vmax = R(0);
   constexpr int S = n / 16;
   for (int it = 0; it < iters; ++it) {
     const int pair = blk * per_block + it * FF::G + g;
-    const bool active = pair < n / 2;
+    const bool active = pair < npairs;
+    const long long o0 = active ? roff(2 * pair) : -1, o1 = active ? roff(2 * pair + 1) : -1;
     if (cols == 0) {   // ring without lattice cells: its field is zero
-      if (active)
-        for (int k = t; k < n; k += FF::TG) {
-          fs[(long long)(2 * pair) * n + k] = R(0);
-          fs[(long long)(2 * pair + 1) * n + k] = R(0);
-        }
+      for (int k = t; k < n; k += FF::TG) {
+        if (o0 >= 0) fs[o0 + k] = R(0);
+        if (o1 >= 0) fs[o1 + k] = R(0);
+      }
       continue;
     }
     // Input k of the row pair (ya, ya + 1): Z(gx, ya) + i Z(gx, ya + 1) at gx = k (k <= H)
@@ -333,13 +345,11 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
       }
       return x;
     };
-    R* __restrict__ row0 = fs + (long long)(2 * (active ? pair : 0)) * n;
-    R* __restrict__ row1 = row0 + n;
+    R* __restrict__ row0 = fs + (o0 >= 0 ? o0 : 0);
+    R* __restrict__ row1 = fs + (o1 >= 0 ? o1 : 0);
     auto out = [&](int k, int, int, T v) {
-      if (active) {
-        row0[k] = v.x;
-        row1[k] = v.y;
-      }
+      if (o0 >= 0) row0[k] = v.x;
+      if (o1 >= 0) row1[k] = v.y;
       if constexpr (FMAX)
         if (active) vmax = fmax(vmax, fmax(fabs(v.x), fabs(v.y)));
     };
@@ -578,25 +588,30 @@ hipError_t launch_rowpass_n(const abs_plan_s* p, int nsets, const typename Cx<R>
                             R* F, long long fset, unsigned* fmax_bits, const BinDev* bins,
                             const typename Cx<R>::T* tw, hipStream_t st) {
   using FF = Fft<LOG2N>;
-  const int iters = std::max(1, std::min(kRowIters, FF::N / 2 / FF::G));
+  // FP64 rows are the weight fields: even, half plane
+  constexpr bool HALF = sizeof(R) == 8;
+  constexpr int npairs = HALF ? FF::N / 4 + 1 : FF::N / 2;
+  const long long rstride = HALF ? p->npix64 : (long long)FF::N * FF::N;
+  const int hb = HALF ? p->pix_per_block64 : 0;
+  const int iters = std::max(1, std::min(kRowIters, npairs / FF::G));
   const int per_block = FF::G * iters;
-  const int nrb = (FF::N / 2 + per_block - 1) / per_block;
+  const int nrb = (npairs + per_block - 1) / per_block;
   const dim3 grid((unsigned)(p->nb * nrb), (unsigned)nsets);
   using T = typename Cx<R>::T;
   const size_t lds = (size_t)FF::G * FF::L * sizeof(T) + (FF::N * sizeof(T) <= 16384 ? FF::N * sizeof(T) : 0);
   hipError_t e;
   if constexpr (sizeof(R) == 4) {
     if (fmax_bits) {   // FP16 split form: largest |F| per (set, ring)
-      auto k = rowpass_fixed_kernel<R, LOG2N, true>;
+      auto k = rowpass_fixed_kernel<R, LOG2N, true, false>;
       if ((e = allow_lds(k, lds)) != hipSuccess) return e;
-      k<<<grid, kBlock, lds, st>>>(iters, bins, tw, Z, zset, F, fset, fmax_bits, p->nb);
+      k<<<grid, kBlock, lds, st>>>(iters, bins, tw, Z, zset, F, fset, rstride, hb, fmax_bits, p->nb);
       return hipGetLastError();
     }
   }
   {
-    auto k = rowpass_fixed_kernel<R, LOG2N, false>;
+    auto k = rowpass_fixed_kernel<R, LOG2N, false, HALF>;
     if ((e = allow_lds(k, lds)) != hipSuccess) return e;
-    k<<<grid, kBlock, lds, st>>>(iters, bins, tw, Z, zset, F, fset, nullptr, p->nb);
+    k<<<grid, kBlock, lds, st>>>(iters, bins, tw, Z, zset, F, fset, rstride, hb, nullptr, p->nb);
   }
   return hipGetLastError();
 }
@@ -622,8 +637,20 @@ hipError_t launch_rowpass_f32(const abs_plan_s* p, int nsets, const float2* Z, l
                               float* F, long long fset, unsigned* fmax_bits, hipStream_t st) {
   return launch_rowpass<float>(p, nsets, Z, zset, F, fset, fmax_bits, st);
 }
+// Zeros of the half-plane weight layout: [2n, hb) after rows 0 and n/2, and the tail
+// after rows 1 .. n/2 - 1, for every (set, ring); blockIdx.x = set * nb + ring.
+__global__ void __launch_bounds__(kBlock)
+half_pad_kernel(double* __restrict__ F, long long fset, long long rstride, int n, int hb) {
+  const int set = blockIdx.y;
+  double* f = F + (long long)set * fset + (long long)blockIdx.x * rstride;
+  for (long long i = 2ll * n + threadIdx.x; i < hb; i += kBlock) f[i] = 0.0;
+  for (long long i = hb + (long long)(n / 2 - 1) * n + threadIdx.x; i < rstride; i += kBlock) f[i] = 0.0;
+}
+
 hipError_t launch_rowpass_f64(const abs_plan_s* p, int nsets, const double2* Z, long long zset,
                               double* F, long long fset, hipStream_t st) {
+  half_pad_kernel<<<dim3((unsigned)p->nb, (unsigned)nsets), kBlock, 0, st>>>(F, fset, p->npix64, p->n,
+                                                                             p->pix_per_block64);
   return launch_rowpass<double>(p, nsets, Z, zset, F, fset, nullptr, st);
 }
 

@@ -152,6 +152,7 @@ WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_c
   const int64_t n = p->n;
   w.zset = n * p->ncols;
   w.fset = (int64_t)p->nb * n * n;
+  w.fset64 = (int64_t)p->nb * p->npix64;
   w.partset = (int64_t)p->nblk * p->ntrip;
   w.partset64 = (int64_t)p->nblk64 * p->ntrip;
   auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -163,7 +164,7 @@ WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_c
   w.fd = off;
   off = al(off + (size_t)batch * w.fset * 4);
   w.fi = off;
-  off = al(off + (size_t)w.nisets * w.fset * 8);
+  off = al(off + (size_t)w.nisets * w.fset64 * 8);
   w.part = off;
   off = al(off + (size_t)batch * w.partset * 8);
   w.part64 = off;
@@ -861,8 +862,15 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
   p->pix_per_block = (int)std::min<int64_t>(16384, std::max<int64_t>(1024, npix / 64));
   p->nblk = (int)((npix + p->pix_per_block - 1) / p->pix_per_block);
   // one weight set per call as a rule: smaller blocks keep the GPU busy
-  p->pix_per_block64 = (int)std::max<int64_t>(1024, npix / 256);
-  p->nblk64 = (int)((npix + p->pix_per_block64 - 1) / p->pix_per_block64);
+  // weight fields: half plane, block 0 = rows 0 and n/2 (so at least 2n pixels a block);
+  // about 256 blocks of the half plane
+  p->pix_per_block64 = (int)std::max<int64_t>(std::max<int64_t>(1024, 2 * (int64_t)p->n), npix / 512);
+  {
+    const int64_t b = p->pix_per_block64;
+    const int64_t rows_b = (int64_t)(p->n / 2 - 1) * p->n;
+    p->nblk64 = 1 + (int)((rows_b + b - 1) / b);
+    p->npix64 = (int64_t)p->nblk64 * b;
+  }
 
   // device layout of the plan tables
   auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };

@@ -100,11 +100,13 @@ def test_workspace_sizes():
     per = p.estimate_workspace(4, True)
     cached = p.estimate_workspace(4, False, True)
     assert cached < shared < per
-    # fields dominate: nbins n^2 values per set, FP32 for the 4 data sets and FP64 for
-    # the weight sets (one shared, or one per grid)
+    # fields dominate: nbins n^2 values per set, FP32 for the 4 data sets; the weight
+    # sets (one shared, or one per grid) are FP64 over the half plane, rows 0 .. n/2
+    # (n^2/2 + one pixel block of 4096 per ring)
     f = 20 * n * n * 4
-    assert 6 * f < shared < 6 * f * 1.2
-    assert 12 * f < per < 12 * f * 1.2
+    w = 20 * (n * n // 2 + 4096) * 8
+    assert 4 * f + w < shared < (4 * f + w) * 1.3
+    assert 4 * f + 4 * w < per < (4 * f + 4 * w) * 1.3
     assert 4 * f < cached < 4 * f * 1.2
     # gridding: cell ids, lists, counts/offsets and a realisation-minor copy of the values
     g = p.grid_workspace(1 << 20, 2)
