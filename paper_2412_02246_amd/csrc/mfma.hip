@@ -23,9 +23,10 @@
 // accumulators in registers across the whole pixel block).  Variants: TPW = kTilesPerWave
 // with DEPTH chunks of loads in flight (4 for up to 32 rings, 1 above), and for small
 // plans TPW = kSmallTilesPerWave, whose 128 registers a lane let two workgroups share a
-// CU, so one workgroup's staging and barriers overlap the other's matrix work.  The A operand (the row tile's
-// pair products, split) is formed once per chunk and kept for the wave's consecutive tiles
-// of that row tile; the B operand likewise while the columns stay the same.
+// CU, so one workgroup's staging and barriers overlap the other's matrix work.  The A
+// operand (the row tile's pair products, split) is formed once per chunk and kept for the
+// wave's consecutive tiles of that row tile; the B operand likewise while the columns stay
+// the same.
 #include "abs_internal.h"
 
 namespace abs_impl {
