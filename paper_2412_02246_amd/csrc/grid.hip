@@ -9,11 +9,12 @@
 // contributions: no floating-point atomics, and the sums are accumulated as 64-bit
 // fixed-point integers with a power-of-two scale, so the result is independent of
 // the order inside each cell (bitwise reproducible).
-//   prep:    nearest cell per visibility, per-cell counts, largest w
+//   prep:    nearest cell per visibility, per-cell counts (the count before a
+//            visibility's own increment is its rank in its cell), largest w
 //   scan:    exclusive prefix sum of the counts (three kernels)
 //   fill:    every visibility's values for all realisations copied, as one record of
-//            8*batch bytes, to its slot in cell order (and its index, when weights or
-//            the Gaussian kernel need it); largest |w V|
+//            8*batch bytes, to its slot start[cell] + rank in cell order (and its index,
+//            when weights or the Gaussian kernel need it); largest |w V|
 //   gather:  one thread per cell streams the records of its cell and of its mirror
 //            cell (7 x 7 neighbouring cells for the Gaussian kernel), 16 realisations
 //            per pass, and writes FP32.
@@ -69,8 +70,8 @@ __device__ __forceinline__ int nearest_cell(double2 U, double du, int n) {
 
 __global__ void __launch_bounds__(kBlock)
 grid_prep_kernel(int n, double du, long long nvis, const double2* __restrict__ uv,
-                 const float* __restrict__ vw, int* __restrict__ cell, int* __restrict__ cnt,
-                 GridScalars* sc) {
+                 const float* __restrict__ vw, int* __restrict__ cell, int* __restrict__ rank,
+                 int* __restrict__ cnt, GridScalars* sc) {
   float wm = 0.f;
   unsigned long long ndrop = 0;
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -81,7 +82,7 @@ grid_prep_kernel(int n, double du, long long nvis, const double2* __restrict__ u
       ++ndrop;
       continue;
     }
-    atomicAdd(&cnt[c], 1);
+    rank[i] = atomicAdd(&cnt[c], 1);
     wm = fmaxf(wm, fabsf(vw ? vw[i] : 1.0f));
   }
   wm = block_max(wm);
@@ -162,22 +163,23 @@ scan_add_kernel(int* __restrict__ start, long long ncells, const int* __restrict
   }
 }
 
-// One workgroup per kBlock consecutive visibilities.  Each visibility claims a slot in
-// its cell's run of the sorted order; the realisations' values are then copied into
+// One workgroup per kBlock consecutive visibilities.  Each visibility's slot in its
+// cell's run of the sorted order is its rank from the prep pass (no atomics here); the
+// realisations' values are then copied into
 // cell-sorted records sorted[pos * batch + b] through LDS, kRec realisations at a time,
 // so that consecutive lanes store consecutive values of whole records (a batch of 16
 // fills one 128-byte line per record).  Also finds the largest |w V| component.
 __global__ void __launch_bounds__(kBlock)
 grid_fill_kernel(long long nvis, int batch, const int* __restrict__ cell,
-                 const int* __restrict__ start, int* __restrict__ cnt,
+                 const int* __restrict__ start, const int* __restrict__ rank,
                  const float2* __restrict__ vis, const float* __restrict__ vw,
                  int* __restrict__ list, float2* __restrict__ sorted, GridScalars* sc) {
   __shared__ float2 tile[kRec][kBlock + 1];
   __shared__ int posl[kBlock];
   const long long i0 = (long long)blockIdx.x * kBlock;
   const long long i = i0 + threadIdx.x;
-  // the first kRec realisations are loaded before the slot is claimed, so that the
-  // loads and the atomic are in flight together
+  // the first kRec realisations are loaded before the slot is looked up, so that all
+  // the loads are in flight together
   float2 v0[kRec];
 #pragma unroll
   for (int bb = 0; bb < kRec; ++bb)
@@ -187,7 +189,7 @@ grid_fill_kernel(long long nvis, int batch, const int* __restrict__ cell,
   if (i < nvis) {
     const int c = cell[i];
     if (c >= 0) {
-      pos = start[c] + atomicSub(&cnt[c], 1) - 1;   // counts run down to zero
+      pos = start[c] + rank[i];
       wa = fabsf(vw ? vw[i] : 1.0f);
       if (list) list[pos] = (int)i;
     }
@@ -354,7 +356,7 @@ __global__ void grid_dropped_kernel(const GridScalars* sc, long long* dropped) {
 }
 
 struct GridWork {
-  size_t sc, cell, cnt, start, tiles, list, sorted, total;
+  size_t sc, cell, rank, cnt, start, tiles, list, sorted, total;
 };
 
 GridWork grid_layout(long long n, long long nvis, int batch) {
@@ -366,6 +368,8 @@ GridWork grid_layout(long long n, long long nvis, int batch) {
   g.sc = off;
   off = al(off + sizeof(GridScalars));
   g.cell = off;
+  off = al(off + (size_t)nvis * 4);
+  g.rank = off;
   off = al(off + (size_t)nvis * 4);
   g.cnt = off;
   off = al(off + (size_t)cells * 4);
@@ -410,6 +414,7 @@ extern "C" abs_status abs_grid(abs_plan_t p, int64_t nvis, int32_t batch, const 
   char* wk = static_cast<char*>(work);
   GridScalars* sc = reinterpret_cast<GridScalars*>(wk + gl.sc);
   int* cell = reinterpret_cast<int*>(wk + gl.cell);
+  int* rank = reinterpret_cast<int*>(wk + gl.rank);
   int* cnt = reinterpret_cast<int*>(wk + gl.cnt);
   int* start = reinterpret_cast<int*>(wk + gl.start);
   int* tsum = reinterpret_cast<int*>(wk + gl.tiles);
@@ -428,13 +433,13 @@ extern "C" abs_status abs_grid(abs_plan_t p, int64_t nvis, int32_t batch, const 
   prof_begin(p, ABS_STAGE_GRID, st);
   grid_clear_kernel<<<1024, kBlock, 0, st>>>(cnt, cells, sc);
   const unsigned gv = (unsigned)std::min<long long>(8192, std::max<long long>(1, (nvis + kBlock - 1) / kBlock));
-  if (nvis > 0) grid_prep_kernel<<<gv, kBlock, 0, st>>>(p->n, p->du, nvis, uvd, vis_w, cell, cnt, sc);
+  if (nvis > 0) grid_prep_kernel<<<gv, kBlock, 0, st>>>(p->n, p->du, nvis, uvd, vis_w, cell, rank, cnt, sc);
   scan_tiles_kernel<<<ntiles, kBlock, 0, st>>>(cnt, cells, start, tsum, sc);
   scan_sums_kernel<<<1, kBlock, 0, st>>>(tsum, ntiles, start, cells);
   scan_add_kernel<<<ntiles, kBlock, 0, st>>>(start, cells, tsum);
   if (nvis > 0)
     grid_fill_kernel<<<(unsigned)((nvis + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-        nvis, batch, cell, start, cnt, reinterpret_cast<const float2*>(vis), vis_w, lst, sorted, sc);
+        nvis, batch, cell, start, rank, reinterpret_cast<const float2*>(vis), vis_w, lst, sorted, sc);
   const bool vec = (batch & 1) == 0;
   float2* g2 = reinterpret_cast<float2*>(grid);
   // lanes per cell: enough pairs of realisations for one pass of up to kRec of them

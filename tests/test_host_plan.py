@@ -108,9 +108,10 @@ def test_workspace_sizes():
     assert 4 * f + w < shared < (4 * f + w) * 1.3
     assert 4 * f + 4 * w < per < (4 * f + 4 * w) * 1.3
     assert 4 * f < cached < 4 * f * 1.2
-    # gridding: cell ids, lists, counts/offsets and a realisation-minor copy of the values
     g = p.grid_workspace(1 << 20, 2)
-    assert (1 << 20) * (4 + 4 + 16) + 2 * n * n * 4 <= g < (1 << 20) * 24 + 2 * n * n * 4 + 8192
+    # gridding: cell ids, ranks, lists, counts/offsets and a realisation-minor copy of
+    # the values
+    assert (1 << 20) * (4 + 4 + 4 + 16) + 2 * n * n * 4 <= g < (1 << 20) * 28 + 2 * n * n * 4 + 8192
     with pytest.raises(A.AbsError):
         p.estimate_workspace(5)
 
