@@ -309,6 +309,35 @@ def main():
                 "flops_per_launch": flops,
                 "mfma_issued_tflops": issued / (con_ms * 1e-3) / 1e12,
                 "mfma_issued_frac": issued / (con_ms * 1e-3) / PEAK_MFMA_16BIT}
+    # HBM fraction of the gridding and FFT stages, from HIP events the library records
+    # around each stage on a few extra (untimed) steps; algorithmic bytes per step:
+    #   gridding: uv read once (16 B a visibility), values read (8 B a visibility and
+    #             realisation), grids written (8 B a cell and realisation), counts (4 B a cell)
+    #   column pass: the pruned intermediate written (8 B x n x ncols a set)
+    #   row pass: that intermediate read and the FP32 fields written (4 B x nbins x n^2 a set)
+    stages = {}
+    nprof = 5
+    evs = {st: HipEvents(nprof) for st in (L.STAGE_GRID, L.STAGE_COLPASS, L.STAGE_ROWPASS)}
+    for k in range(nprof):
+        for st, e in evs.items():
+            L.lib().abs_profile(plan.handle, st, *e.pair(k))
+        step()
+    torch.cuda.synchronize()
+    zbytes = 8.0 * n * plan.ncols * batch
+    alg = {L.STAGE_GRID: 16.0 * nvis + batch * (8.0 * nvis + 8.0 * n * n) + 4.0 * n * n,
+           L.STAGE_COLPASS: zbytes,
+           L.STAGE_ROWPASS: zbytes + 4.0 * nb * n * n * batch}
+    tot_b = tot_ms = 0.0
+    for st, name in ((L.STAGE_GRID, "gridding"), (L.STAGE_COLPASS, "column_pass"), (L.STAGE_ROWPASS, "row_pass")):
+        L.lib().abs_profile(plan.handle, st, None, None)
+        st_ms = float(np.mean([evs[st].elapsed_ms(k) for k in range(nprof)]))
+        evs[st].close()
+        stages[name] = {"ms": st_ms, "alg_bytes": alg[st], "gb_per_s": alg[st] / (st_ms * 1e-3) / 1e9,
+                        "frac_hbm": alg[st] / (st_ms * 1e-3) / PEAK_HBM}
+        tot_b += alg[st]
+        tot_ms += st_ms
+    stages["gridding_and_fft"] = {"ms": tot_ms, "alg_bytes": tot_b, "gb_per_s": tot_b / (tot_ms * 1e-3) / 1e9,
+                                  "frac_hbm": tot_b / (tot_ms * 1e-3) / PEAK_HBM}
     out = {
         "metric": "bispectrum grids/s at 1 GPU (gridding + estimator)",
         "value": grids_s, "unit": "grids/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -319,6 +348,7 @@ def main():
                    "nvis_per_grid": nvis, "ntrip": int(plan.ntrip), "precision": a.precision,
                    "bin_triplets_per_s": grids_s * plan.ntrip, "parallelism": "1 GPU"},
         "roofline": roof,
+        "stages_hbm": stages,
     }
     if not a.no_cpu:
         e_sample = min(batch, 2)
