@@ -136,12 +136,12 @@ __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 // the thread's base plus a constant, each thread's twiddles are fixed for the kernel's
 // lifetime (kept in registers when they are few) and the first pass reads its inputs
 // straight from global memory, skipping all-zero slabs of the pruned input.
-template <int LOG2N>
+template <int LOG2N, int BLOCK = kBlock>
 struct Fft {
   static constexpr int N = 1 << LOG2N;
-  static constexpr int U = N > 4096 ? 2 : 1;                  // radix-16 butterflies per thread
-  static constexpr int TG = N / 16 / U < kBlock ? N / 16 / U : kBlock;   // threads per transform
-  static constexpr int G = kBlock / TG;                       // transforms per block
+  static constexpr int U = N / 16 > BLOCK ? 2 : 1;            // radix-16 butterflies per thread
+  static constexpr int TG = N / 16 / U < BLOCK ? N / 16 / U : BLOCK;   // threads per transform
+  static constexpr int G = BLOCK / TG;                        // transforms per block
   static constexpr int NP16 = LOG2N / 4, LREST = LOG2N % 4;
   static constexpr int NPASS = NP16 + (LREST ? 1 : 0);
   static constexpr int L = N + N / 16;                        // padded LDS elements
@@ -172,12 +172,12 @@ __device__ __forceinline__ void fft_sync() {
 
 // Per-thread twiddles: REG keeps all of them in registers, otherwise they are read from
 // the table when used.
-template <typename R, int LOG2N, bool REG>
+template <typename R, int LOG2N, bool REG, int BLOCK = kBlock>
 struct Twiddles;
-template <typename R, int LOG2N>
-struct Twiddles<R, LOG2N, true> {
+template <typename R, int LOG2N, int BLOCK>
+struct Twiddles<R, LOG2N, true, BLOCK> {
   using T = typename Cx<R>::T;
-  using F = Fft<LOG2N>;
+  using F = Fft<LOG2N, BLOCK>;
   T w[F::NTW > 0 ? F::NTW : 1];
   __device__ __forceinline__ void load(const T* __restrict__ tw, int t) {
     load_from<1>(tw, t);
@@ -200,10 +200,10 @@ struct Twiddles<R, LOG2N, true> {
     return w[F::tw_before(P) + j * ((1 << F::lrp(P)) - 1) + r - 1];
   }
 };
-template <typename R, int LOG2N>
-struct Twiddles<R, LOG2N, false> {
+template <typename R, int LOG2N, int BLOCK>
+struct Twiddles<R, LOG2N, false, BLOCK> {
   using T = typename Cx<R>::T;
-  using F = Fft<LOG2N>;
+  using F = Fft<LOG2N, BLOCK>;
   __device__ __forceinline__ void load(const T* __restrict__, int) {}
   template <int P>
   __device__ __forceinline__ T get(const T* __restrict__ tw, int t, int j, int r) const {
@@ -216,11 +216,11 @@ struct Twiddles<R, LOG2N, false> {
 // Pass P of the length-2^LOG2N transform held by thread t of its TG threads.  Pass 0
 // takes its inputs from in(k) (natural order, any memory); the last pass hands its
 // outputs to out(k, value); passes in between read and write the padded LDS buffer.
-template <typename R, int LOG2N, int P, class TW, class In, class Out>
+template <typename R, int LOG2N, int P, int BLOCK, class TW, class In, class Out>
 __device__ __forceinline__ void fft_pass(typename Cx<R>::T* buf, int t, const typename Cx<R>::T* __restrict__ tw,
                                          const TW& twr, In& in, Out& out) {
   using T = typename Cx<R>::T;
-  using F = Fft<LOG2N>;
+  using F = Fft<LOG2N, BLOCK>;
   constexpr int LRP = F::lrp(P), RP = 1 << LRP, NB = F::nb(P);
   constexpr int LNS = 4 * P, NS = 1 << LNS, STRIDE = F::N / RP;
   constexpr bool FIRST = P == 0, LAST = P == F::NPASS - 1;
@@ -265,12 +265,16 @@ __device__ __forceinline__ void fft_pass(typename Cx<R>::T* buf, int t, const ty
   if constexpr (!LAST) fft_sync<F::WAVE>();
 }
 
-template <typename R, int LOG2N, int P, class TW, class In, class Out>
+template <typename R, int LOG2N, int P, int BLOCK, class TW, class In, class Out>
 __device__ __forceinline__ void fft_passes(typename Cx<R>::T* buf, int t, const typename Cx<R>::T* __restrict__ tw,
                                            const TW& twr, In& in, Out& out) {
-  fft_pass<R, LOG2N, P>(buf, t, tw, twr, in, out);
-  if constexpr (P + 1 < Fft<LOG2N>::NPASS) fft_passes<R, LOG2N, P + 1>(buf, t, tw, twr, in, out);
+  fft_pass<R, LOG2N, P, BLOCK>(buf, t, tw, twr, in, out);
+  if constexpr (P + 1 < Fft<LOG2N, BLOCK>::NPASS) fft_passes<R, LOG2N, P + 1, BLOCK>(buf, t, tw, twr, in, out);
 }
+
+// Threads per row-pass workgroup: 8192-point rows use 512 (one radix-16 butterfly per
+// thread, half the registers of two, so more waves fit a SIMD); others kBlock.
+constexpr int row_block(int log2n) { return log2n == 13 ? 512 : kBlock; }
 
 // Row pass with the compile-time engine.  blockIdx.x = ring m * blocks per ring + block,
 // each block covering G * iters row pairs; blockIdx.y = set.  FMAX records the largest
@@ -279,12 +283,13 @@ __device__ __forceinline__ void fft_passes(typename Cx<R>::T* buf, int t, const 
 // row 0 at 0, row n/2 at n, row r in 1 .. n/2 - 1 at hb + (r - 1) n; rstride is the
 // values per ring (n^2, or the half-plane size).
 template <typename R, int LOG2N, bool FMAX, bool HALF>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(row_block(LOG2N))
 rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename Cx<R>::T* __restrict__ tw,
                      const typename Cx<R>::T* __restrict__ Z, long long zset, R* __restrict__ F,
                      long long fset, long long rstride, int hb, unsigned* __restrict__ fmax_bits, int nb) {
   using T = typename Cx<R>::T;
-  using FF = Fft<LOG2N>;
+  constexpr int RB = row_block(LOG2N);
+  using FF = Fft<LOG2N, RB>;
   constexpr int n = FF::N;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int g = threadIdx.x / FF::TG, t = threadIdx.x - g * FF::TG;
@@ -295,7 +300,7 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
   const T* __restrict__ twp = tw;
   if constexpr (TWL) {
     T* twl = reinterpret_cast<T*>(lds_raw) + FF::G * FF::L;
-    for (int k = threadIdx.x; k < n; k += kBlock) twl[k] = tw[k];
+    for (int k = threadIdx.x; k < n; k += RB) twl[k] = tw[k];
     __syncthreads();
     twp = twl;
   }
@@ -316,7 +321,7 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
     return -1;
   };
   const T* __restrict__ zs = Z + (long long)set * zset + bin.zoff;
-  Twiddles<R, LOG2N, false> twr;
+  Twiddles<R, LOG2N, false, RB> twr;
   R vmax = R(0);
   constexpr int S = n / 16;
   for (int it = 0; it < iters; ++it) {
@@ -354,7 +359,7 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
         if (active) vmax = fmax(vmax, fmax(fabs(v.x), fabs(v.y)));
     };
     fft_sync<FF::WAVE>();   // the previous transform's last reads are done
-    fft_passes<R, LOG2N, 0>(buf, t, twp, twr, in, out);
+    fft_passes<R, LOG2N, 0, RB>(buf, t, twp, twr, in, out);
   }
   if constexpr (FMAX) {
     float v = (float)vmax;
@@ -483,7 +488,7 @@ colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, i
     T res[NBL][RPL];   // output (j, q) of the last pass is element t + TG j + q NSL
     auto out = [&](int, int j, int q, T v) { res[j][q] = v; };
     __syncthreads();   // the previous tile's stage has been written out
-    fft_passes<R, LOG2N, 0>(buf, t, tw, twr, in, out);
+    fft_passes<R, LOG2N, 0, kBlock>(buf, t, tw, twr, in, out);
     __syncthreads();   // every transform has read its buffer
 #pragma unroll
     for (int j = 0; j < NBL; ++j)
@@ -587,7 +592,8 @@ template <typename R, int LOG2N>
 hipError_t launch_rowpass_n(const abs_plan_s* p, int nsets, const typename Cx<R>::T* Z, long long zset,
                             R* F, long long fset, unsigned* fmax_bits, const BinDev* bins,
                             const typename Cx<R>::T* tw, hipStream_t st) {
-  using FF = Fft<LOG2N>;
+  constexpr int RB = row_block(LOG2N);
+  using FF = Fft<LOG2N, RB>;
   // FP64 rows are the weight fields: even, half plane
   constexpr bool HALF = sizeof(R) == 8;
   constexpr int npairs = HALF ? FF::N / 4 + 1 : FF::N / 2;
@@ -604,14 +610,14 @@ hipError_t launch_rowpass_n(const abs_plan_s* p, int nsets, const typename Cx<R>
     if (fmax_bits) {   // FP16 split form: largest |F| per (set, ring)
       auto k = rowpass_fixed_kernel<R, LOG2N, true, false>;
       if ((e = allow_lds(k, lds)) != hipSuccess) return e;
-      k<<<grid, kBlock, lds, st>>>(iters, bins, tw, Z, zset, F, fset, rstride, hb, fmax_bits, p->nb);
+      k<<<grid, RB, lds, st>>>(iters, bins, tw, Z, zset, F, fset, rstride, hb, fmax_bits, p->nb);
       return hipGetLastError();
     }
   }
   {
     auto k = rowpass_fixed_kernel<R, LOG2N, false, HALF>;
     if ((e = allow_lds(k, lds)) != hipSuccess) return e;
-    k<<<grid, kBlock, lds, st>>>(iters, bins, tw, Z, zset, F, fset, rstride, hb, nullptr, p->nb);
+    k<<<grid, RB, lds, st>>>(iters, bins, tw, Z, zset, F, fset, rstride, hb, nullptr, p->nb);
   }
   return hipGetLastError();
 }
