@@ -11,7 +11,12 @@
 
 namespace abs_impl {
 
-constexpr int kBlock = 256;          // threads per workgroup for every kernel here
+constexpr int kBlock = 256;          // threads per workgroup for most kernels here
+// Threads per column-pass workgroup: 4096-point columns use 512 (two transforms a block,
+// so a tile's outputs leave in 64-byte runs instead of 32: 4.7 -> 2.6 ms at 4096^2 x 16;
+// 8192-point columns stay at kBlock, 7.5 against 10.1 ms with 512); others kBlock.  The
+// host's column tiles hold as many columns as one workgroup transforms at once.
+constexpr int col_block(int log2n) { return log2n == 12 ? 512 : kBlock; }
 constexpr int kMaxBins = 64;
 constexpr int kTilesPerWave = 12;    // MFMA output tiles owned by one wave (precision form)
 constexpr int kSmallTilesPerWave = 2;   // the same for small plans (kernel variant)

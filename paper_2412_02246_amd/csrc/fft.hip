@@ -441,13 +441,14 @@ herm_kernel(const GT* __restrict__ grids, const float* __restrict__ w, int w_bat
 // runs of 4 ncols consecutive elements (whole 128-byte lines for 4 FP32 columns) and
 // the row pass reads each input of a row pair with one load.
 template <typename R, int LOG2N>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(col_block(LOG2N))
 colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, int hm, int lc,
                      const ColTile* __restrict__ tiles, int ntiles, int tpb,
                      const BinDev* __restrict__ bins, const typename Cx<R>::T* __restrict__ tw,
                      typename Cx<R>::T* __restrict__ Z, long long zset) {
   using T = typename Cx<R>::T;
-  using FF = Fft<LOG2N>;
+  constexpr int CB = col_block(LOG2N);
+  using FF = Fft<LOG2N, CB>;
   constexpr int n = FF::N, S = n / 16;
   constexpr bool DATA = sizeof(R) == 4;
   constexpr bool REG = DATA && FF::NTW <= 32;
@@ -455,7 +456,7 @@ colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, i
   const int g = threadIdx.x / FF::TG, t = threadIdx.x - g * FF::TG;
   T* buf = reinterpret_cast<T*>(lds_raw) + g * FF::L;
   const int set = blockIdx.y;
-  Twiddles<R, LOG2N, REG> twr;
+  Twiddles<R, LOG2N, REG, CB> twr;
   twr.load(tw, t);
   for (int it = 0; it < tpb; ++it) {
     const int ti = blockIdx.x * tpb + it;
@@ -488,7 +489,7 @@ colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, i
     T res[NBL][RPL];   // output (j, q) of the last pass is element t + TG j + q NSL
     auto out = [&](int, int j, int q, T v) { res[j][q] = v; };
     __syncthreads();   // the previous tile's stage has been written out
-    fft_passes<R, LOG2N, 0, kBlock>(buf, t, tw, twr, in, out);
+    fft_passes<R, LOG2N, 0, CB>(buf, t, tw, twr, in, out);
     __syncthreads();   // every transform has read its buffer
 #pragma unroll
     for (int j = 0; j < NBL; ++j)
@@ -500,7 +501,7 @@ colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, i
     // column -gx, one value per input
     const int nc = tile.ncols, run = 4 * nc;
     T* __restrict__ zs = Z + (long long)set * zset + bin.zoff + 4LL * tile.gx0;
-    for (int e = threadIdx.x; e < n * nc; e += kBlock) {
+    for (int e = threadIdx.x; e < n * nc; e += CB) {
       const int yb = e / run, rem = e - yb * run, c = rem >> 2, yi = rem & 3;
       const int y0 = 4 * yb + (yi & 2);
       const T a = stage[y0 * FF::G + c], b = stage[(y0 + 1) * FF::G + c];
@@ -535,7 +536,8 @@ template <typename R, int LOG2N>
 hipError_t launch_colpass_n(const abs_plan_s* p, int nsets, const typename HermT<sizeof(R) == 4>::T* xc,
                             typename Cx<R>::T* Z, long long zset, const typename Cx<R>::T* tw,
                             hipStream_t st) {
-  using FF = Fft<LOG2N>;
+  constexpr int CB = col_block(LOG2N);
+  using FF = Fft<LOG2N, CB>;
   const char* base = static_cast<const char*>(p->dev);
   const BinDev* bins = reinterpret_cast<const BinDev*>(base + p->dl.bins);
   const ColTile* tiles = reinterpret_cast<const ColTile*>(base + p->dl.tiles);
@@ -546,8 +548,8 @@ hipError_t launch_colpass_n(const abs_plan_s* p, int nsets, const typename HermT
   auto k = colpass_fixed_kernel<R, LOG2N>;
   hipError_t e = allow_lds(k, lds);
   if (e != hipSuccess) return e;
-  k<<<grid, kBlock, lds, st>>>(xc, p->hmax, 2 * p->hmax + 1, tiles, ntiles, kColTilesPerBlock, bins, tw,
-                               Z, zset);
+  k<<<grid, CB, lds, st>>>(xc, p->hmax, 2 * p->hmax + 1, tiles, ntiles, kColTilesPerBlock, bins, tw,
+                           Z, zset);
   return hipGetLastError();
 }
 

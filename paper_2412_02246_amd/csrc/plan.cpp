@@ -852,9 +852,12 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
     L[4] = l2 / l1;
   }
 
-  // FFT tiling: a column-pass block transforms ct columns of one ring at once, one
-  // transform per n/16 threads (a whole block of kBlock threads from n = 4096 on)
-  p->ct = kBlock / std::min(kBlock, std::max(1, n / 16));
+  // FFT tiling: a column-pass workgroup of col_block(log2 n) threads transforms ct columns
+  // of one ring at once, one transform per n/16 threads (at most the whole workgroup)
+  {
+    const int cb = col_block(p->log2n);
+    p->ct = cb / std::min(cb, std::max(1, n / 16));
+  }
   for (int m = 0; m < nb; ++m)
     for (int g0 = 0; g0 < p->cols[m]; g0 += p->ct)
       p->tiles.push_back({m, g0, std::min(p->ct, p->cols[m] - g0), 0});
