@@ -150,3 +150,34 @@ def test_c5_ensemble_fp32_vs_bf16x3(c5):
           "max |var ratio - 1| %.3g" % (R5, f.shape[1], z.max(), dv.max()), flush=True)
     assert z.max() <= 1e-2
     assert dv.max() <= 1e-3
+
+
+# The two power-of-two sizes between the small grids and 4096^2 that the serving mix uses
+# (512^2 and 2048^2, 16 and 24 log rings with radii scaled by n/1024), against the oracle on
+# every plan triplet within a subset of rings: each size has its own FFT kernel shapes
+# (column workgroup width, transforms per workgroup).
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("n,nb,subset", [(512, 16, {0, 5, 10, 15}), (2048, 24, {0, 8, 16, 23})])
+def test_mid_sizes(n, nb, subset, prec):
+    import torch
+    import paper_2412_02246_amd as A
+    s = n / 1024.0
+    edges = oplan.log_edges(s * 46 / (2 * np.pi), s * 1320 / (2 * np.pi), nb)
+    V, counts = synth.mwa_like(n, synth.seed_for(3, n), U0=n / 8)
+    V = V.astype(np.complex64)
+    P = {"fp32": A.FP32, "bf16x3": A.BF16X3}[prec]
+    p = A.Plan(n, edges, wmode=A.W_INV_COUNT, precision=P).bind()
+    idx = np.array([q for q, t in enumerate(p.triplets) if set(t.tolist()) <= subset])
+    ref = oest.estimate_subset(V, counts, edges, p.norm, p.triplets[idx], wmode=oest.INV_COUNT)
+    B, Nn = p.estimate(torch.from_numpy(V).cuda(), torch.from_numpy(counts.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    B = B[0].cpu().numpy()[idx]
+    Nn = Nn[0].cpu().numpy()[idx]
+    e = oest.relative_error(B, ref, p.norm)
+    en = oest.count_error(Nn, ref)
+    print("n%d/%d %s: e_t median %.3g max %.3g, e_N max %.3g over %d of %d triplets"
+          % (n, nb, prec, np.median(e), e.max(), en.max(), len(idx), p.ntrip), flush=True)
+    assert len(idx) > 0
+    assert np.all(np.isfinite(B))
+    assert e.max() <= TOL[prec]
+    assert en.max() <= 1e-5
