@@ -234,11 +234,12 @@ __device__ __forceinline__ double fixed_scale(float maxval, long long terms) {
   return ldexp(1.0, 51 - e - lg);
 }
 
-// LPC lanes per cell (iy, ix), lane q holding realisations b0 + 2q and b0 + 2q + 1: sums
-// the visibilities whose nearest cell is within R cells of it, directly (V) and through
-// the mirror (conj V).  The records of one source cell are contiguous in `sorted`
-// (VEC: one 16-byte load per record and lane, batch even).  Lane 0 of each cell also
-// sums the weights when b0 == 0.
+// Per-visibility weights or the Gaussian kernel (unit weights with the nearest cell go
+// through grid_gather_pairs_kernel).  LPC lanes per cell (iy, ix), lane q holding
+// realisations b0 + 2q and b0 + 2q + 1: sums the visibilities whose nearest cell is within
+// R cells of it, directly (V) and through the mirror (conj V).  The records of one source
+// cell are contiguous in `sorted` (VEC: one 16-byte load per record and lane, batch even).
+// Lane 0 of each cell also sums the weights when b0 == 0.
 template <int R, int LPC, bool VEC>
 __global__ void __launch_bounds__(kBlock)
 grid_gather_kernel(int n, double du, double pit2, int batch, int b0,
@@ -277,36 +278,7 @@ grid_gather_kernel(int n, double du, double pit2, int batch, int b0,
     }
   };
   const bool inside = gx > -half && gy > -half;   // row / column -n/2 receive nothing
-  if (R == 0 && vw == nullptr && inside) {
-    // Nearest cell, unit weights: the records of g and of -g form one list of
-    // cd + cm entries, walked in chunks of kG with the next chunk's loads in flight.
-    // Terms are integers in FP64, so the order of the additions does not matter.
-    constexpr int kG = 4;
-    const int s0 = (int)c, s1 = ((gy ? n - iy : 0) * n) + (gx ? n - ix : 0);
-    const int p0 = start[s0], cd = start[s0 + 1] - p0;
-    const int q0 = start[s1], cm = start[s1 + 1] - q0;
-    const int ct = cd + cm;
-    auto rec = [&](int i) { return i < cd ? p0 + i : q0 + (i - cd); };
-    float4 cur[kG], nxt[kG];
-#pragma unroll
-    for (int u = 0; u < kG; ++u) cur[u] = u < ct ? load(rec(u)) : make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int i0 = 0; i0 < ct; i0 += kG) {
-#pragma unroll
-      for (int u = 0; u < kG; ++u)
-        nxt[u] = i0 + kG + u < ct ? load(rec(i0 + kG + u)) : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-      for (int u = 0; u < kG; ++u) {
-        const double sgn = i0 + u < cd ? 1.0 : -1.0;   // entries past ct are zero
-        ar0 += rint((double)cur[u].x * sv);
-        ai0 += sgn * rint((double)cur[u].y * sv);
-        ar1 += rint((double)cur[u].z * sv);
-        ai1 += sgn * rint((double)cur[u].w * sv);
-      }
-#pragma unroll
-      for (int u = 0; u < kG; ++u) cur[u] = nxt[u];
-    }
-    if (want_w) aw = rint(sw) * (double)ct;   // sw = 1 for integer counts
-  } else if (inside) {
+  if (inside) {
     for (int mir = 0; mir < 2; ++mir) {
       const double sgn = mir ? -1.0 : 1.0;
       for (int dy = -R; dy <= R; ++dy)
@@ -349,6 +321,94 @@ grid_gather_kernel(int n, double du, double pit2, int batch, int b0,
   if (has0) grid[(long long)bq * nn + c] = make_float2((float)(ar0 * iv), (float)(ai0 * iv));
   if (has1) grid[(long long)(bq + 1) * nn + c] = make_float2((float)(ar1 * iv), (float)(ai1 * iv));
   if (want_w) wsum[c] = (float)(aw / sw);
+}
+
+// Nearest cell, unit visibility weights: one group of LPC lanes per pair of mirror cells
+// (g, -g), reading each cell's records once.  With S_g the fixed-point sum of the records
+// whose nearest cell is g, the grid gets S_g + conj S_-g at g and S_-g + conj S_g at -g
+// (exact integer sums in FP64, so the results are bit for bit those of gathering both
+// lists at each cell); the weight sum is the record count of both cells.  Representatives:
+// rows 0 .. n/2 in order (|gy| ascending: the long lists of short baselines first), and in
+// rows 0 and n/2 only columns 0 .. n/2; row and column -n/2 receive nothing.
+template <int LPC, bool VEC>
+__global__ void __launch_bounds__(kBlock)
+grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ sorted,
+                         const int* __restrict__ start, const GridScalars* sc,
+                         float2* __restrict__ grid, float* __restrict__ wsum) {
+  const long long nn = (long long)n * n;
+  const int half = n / 2;
+  const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long lc = gt / LPC;
+  const int q = (int)(gt - lc * LPC);
+  if (lc >= (long long)(half + 1) * n) return;
+  const int iy = (int)(lc / n), ix = (int)(lc - (long long)iy * n);
+  if ((iy == 0 || iy == half) && ix > half) return;   // the mirror of a representative
+  const int my = iy ? n - iy : 0, mx = ix ? n - ix : 0;
+  const long long c = (long long)iy * n + ix, m = (long long)my * n + mx;
+  const int gy = iy < half ? iy : iy - n, gx = ix < half ? ix : ix - n;
+  const bool inside = gx > -half && gy > -half;       // the mirror is inside exactly then
+  // a cell adds at most 2 maxcnt terms (its own records and its mirror's)
+  const double sv = fixed_scale(__uint_as_float(sc->vmax_bits), 2ll * (long long)sc->maxcnt);
+  const int bq = b0 + 2 * q;
+  const bool has0 = bq < batch, has1 = bq + 1 < batch;
+  auto load = [&](int p) -> float4 {
+    const float2* rec = sorted + (long long)p * batch + bq;
+    if constexpr (VEC) {
+      return has0 ? *reinterpret_cast<const float4*>(rec) : make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      const float2 a = has0 ? rec[0] : make_float2(0.f, 0.f);
+      const float2 b = has1 ? rec[1] : make_float2(0.f, 0.f);
+      return make_float4(a.x, a.y, b.x, b.y);
+    }
+  };
+  // fixed-point sum of one cell's records, walked in chunks of kG with the next chunk's
+  // loads in flight
+  auto cell_sum = [&](int p0, int cnt, double* a) {
+    constexpr int kG = 4;
+    float4 cur[kG], nxt[kG];
+#pragma unroll
+    for (int u = 0; u < kG; ++u) cur[u] = u < cnt ? load(p0 + u) : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i0 = 0; i0 < cnt; i0 += kG) {
+#pragma unroll
+      for (int u = 0; u < kG; ++u)
+        nxt[u] = i0 + kG + u < cnt ? load(p0 + i0 + kG + u) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {   // entries past cnt are zero
+        a[0] += rint((double)cur[u].x * sv);
+        a[1] += rint((double)cur[u].y * sv);
+        a[2] += rint((double)cur[u].z * sv);
+        a[3] += rint((double)cur[u].w * sv);
+      }
+#pragma unroll
+      for (int u = 0; u < kG; ++u) cur[u] = nxt[u];
+    }
+  };
+  double sc4[4] = {0.0, 0.0, 0.0, 0.0}, sm4[4] = {0.0, 0.0, 0.0, 0.0};
+  int cd = 0, cm = 0;
+  if (inside) {
+    const int p0 = start[c];
+    cd = start[c + 1] - p0;
+    cell_sum(p0, cd, sc4);
+    if (m != c) {
+      const int q0 = start[m];
+      cm = start[m + 1] - q0;
+      cell_sum(q0, cm, sm4);
+    } else {
+      cm = cd;
+      for (int k = 0; k < 4; ++k) sm4[k] = sc4[k];
+    }
+  }
+  const double iv = 1.0 / sv;  // a power of two: exact
+  auto put = [&](long long cell, const double* a, const double* b) {
+    if (has0) grid[(long long)bq * nn + cell] = make_float2((float)((a[0] + b[0]) * iv), (float)((a[1] - b[1]) * iv));
+    if (has1) grid[(long long)(bq + 1) * nn + cell] = make_float2((float)((a[2] + b[2]) * iv), (float)((a[3] - b[3]) * iv));
+  };
+  put(c, sc4, sm4);
+  if (m != c) put(m, sm4, sc4);
+  if (wsum != nullptr && b0 == 0 && q == 0) {
+    wsum[c] = (float)(cd + cm);
+    wsum[m] = (float)(cd + cm);
+  }
 }
 
 __global__ void grid_dropped_kernel(const GridScalars* sc, long long* dropped) {
@@ -459,8 +519,24 @@ extern "C" abs_status abs_grid(abs_plan_t p, int64_t nvis, int32_t batch, const 
   }
     if (kernel == ABS_GAUSS7) {
       if (vec) { ABS_GATHER_L(3, true) } else { ABS_GATHER_L(3, false) }
-    } else {
+    } else if (vis_w != nullptr) {
       if (vec) { ABS_GATHER_L(0, true) } else { ABS_GATHER_L(0, false) }
+    } else {
+      // unit weights: one lane group per mirror pair of cells
+      const unsigned gp = (unsigned)(((long long)(p->n / 2 + 1) * p->n * lpc + kBlock - 1) / kBlock);
+#define ABS_PAIRS(LL, VV)                                                                           \
+  grid_gather_pairs_kernel<LL, VV><<<gp, kBlock, 0, st>>>(p->n, batch, b0, sorted, start, sc, g2, wsum)
+      switch (lpc * 2 + (vec ? 1 : 0)) {
+        case 2: ABS_PAIRS(1, false); break;
+        case 3: ABS_PAIRS(1, true); break;
+        case 4: ABS_PAIRS(2, false); break;
+        case 5: ABS_PAIRS(2, true); break;
+        case 8: ABS_PAIRS(4, false); break;
+        case 9: ABS_PAIRS(4, true); break;
+        case 16: ABS_PAIRS(8, false); break;
+        default: ABS_PAIRS(8, true); break;
+      }
+#undef ABS_PAIRS
     }
 #undef ABS_GATHER_L
 #undef ABS_GATHER
