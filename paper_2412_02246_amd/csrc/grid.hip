@@ -15,9 +15,11 @@
 //   fill:    every visibility's values for all realisations copied, as one record of
 //            8*batch bytes, to its slot start[cell] + rank in cell order (and its index,
 //            when weights or the Gaussian kernel need it); largest |w V|
-//   gather:  one thread per cell streams the records of its cell and of its mirror
-//            cell (7 x 7 neighbouring cells for the Gaussian kernel), 16 realisations
-//            per pass, and writes FP32.
+//   gather:  unit weights, nearest cell: one lane group per mirror pair of cells
+//            (g, -g) sums each cell's records once and writes both cells; otherwise
+//            one lane group per cell streams the records of its cell and of its mirror
+//            cell (7 x 7 neighbouring cells for the Gaussian kernel).  16 realisations
+//            per pass, FP32 out.
 #include <algorithm>
 
 #include "abs_internal.h"
