@@ -106,6 +106,8 @@ abs_status ensure_device(abs_plan_s* p) {
 abs_status launch_contract(const abs_plan_s* p, int kind, int waves, const void* F, long long fset,
                            long long npix, int ppb, int nblk, int ntrip, int nsets, double* part,
                            hipStream_t st) {
+  // the generated kernels walk a block in pairs of 64-pixel chunks
+  if (ppb % 128 != 0 || npix % 128 != 0) return ABS_ERR_INVALID;
   void* Fp = const_cast<void*>(F);
   void* args[] = {&Fp, &fset, &npix, &ppb, &part, &nblk, &ntrip};
   for (const JitPart& q : p->parts) {

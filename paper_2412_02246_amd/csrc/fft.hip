@@ -213,6 +213,32 @@ struct Twiddles<R, LOG2N, false, BLOCK> {
   }
 };
 
+// Twiddles from a two-level table in LDS, for transforms whose full table is too large
+// to stage: w^a = hi[a / LO] lo[a % LO] with lo[c] = w^c (c < LO = min(64, N)) and
+// hi[b] = w^(LO b) (b < N / LO), both copied from the plan's table, so one complex
+// product (about one rounding more than the table entry) replaces a load from memory.
+template <typename R, int LOG2N, int BLOCK = kBlock>
+struct TwiddlesSplit {
+  using T = typename Cx<R>::T;
+  using F = Fft<LOG2N, BLOCK>;
+  static constexpr int LLO = LOG2N < 6 ? LOG2N : 6, LO = 1 << LLO;
+  static constexpr int ENTRIES = LO + F::N / LO;
+  const T* lo;   // LDS: lo[LO] then hi[N / LO]
+  // Copies the two tables from the natural-order table tw (N entries) into LDS at dst;
+  // the caller synchronises the block before the first get.
+  __device__ __forceinline__ void stage(const T* __restrict__ tw, T* dst, int tid, int nthreads) {
+    for (int e = tid; e < ENTRIES; e += nthreads) dst[e] = tw[e < LO ? e : (e - LO) * LO];
+    lo = dst;
+  }
+  template <int P>
+  __device__ __forceinline__ T get(const T* __restrict__, int t, int j, int r) const {
+    constexpr int LRP = F::lrp(P), LNS = 4 * P, SH = LOG2N - LNS - LRP;
+    const int m = (t + F::TG * j) & ((1 << LNS) - 1);
+    const int a = (r * m) << SH;   // < N
+    return cmul(lo[LO + (a >> LLO)], lo[a & (LO - 1)]);
+  }
+};
+
 // Pass P of the length-2^LOG2N transform held by thread t of its TG threads.  Pass 0
 // takes its inputs from in(k) (natural order, any memory); the last pass hands its
 // outputs to out(k, value); passes in between read and write the padded LDS buffer.
@@ -294,16 +320,11 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int g = threadIdx.x / FF::TG, t = threadIdx.x - g * FF::TG;
   T* buf = reinterpret_cast<T*>(lds_raw) + g * FF::L;
-  // A twiddle table of up to 16 KB is copied into LDS after the FFT buffers (registers
-  // stay free for more waves per SIMD); larger ones are read from memory.
-  constexpr bool TWL = FF::N * sizeof(T) <= 16384;
-  const T* __restrict__ twp = tw;
-  if constexpr (TWL) {
-    T* twl = reinterpret_cast<T*>(lds_raw) + FF::G * FF::L;
-    for (int k = threadIdx.x; k < n; k += RB) twl[k] = tw[k];
-    __syncthreads();
-    twp = twl;
-  }
+  // The two-level twiddle table sits in LDS after the FFT buffers: a few hundred bytes
+  // instead of the full table (n/16 + 1 KB less LDS per block, so more blocks per CU).
+  TwiddlesSplit<R, LOG2N, RB> twr;
+  twr.stage(tw, reinterpret_cast<T*>(lds_raw) + FF::G * FF::L, threadIdx.x, RB);
+  __syncthreads();
   const int per_block = FF::G * iters;
   constexpr int npairs = HALF ? n / 4 + 1 : n / 2;   // HALF: rows 0 .. n/2 (+ n/2 + 1)
   const int nrb = (npairs + per_block - 1) / per_block;
@@ -321,7 +342,6 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
     return -1;
   };
   const T* __restrict__ zs = Z + (long long)set * zset + bin.zoff;
-  Twiddles<R, LOG2N, false, RB> twr;
   R vmax = R(0);
   constexpr int S = n / 16;
   for (int it = 0; it < iters; ++it) {
@@ -359,7 +379,12 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
         if (active) vmax = fmax(vmax, fmax(fabs(v.x), fabs(v.y)));
     };
     fft_sync<FF::WAVE>();   // the previous transform's last reads are done
-    fft_passes<R, LOG2N, 0, RB>(buf, t, twp, twr, in, out);
+    // The thread index is hidden from loop-invariant code motion: the twiddle and LDS
+    // offsets derived from it are recomputed per transform instead of being held in
+    // registers across the loop.
+    int tl = t;
+    asm volatile("" : "+v"(tl));
+    fft_passes<R, LOG2N, 0, RB>(buf, tl, tw, twr, in, out);
   }
   if constexpr (FMAX) {
     float v = (float)vmax;
@@ -440,6 +465,11 @@ herm_kernel(const GT* __restrict__ grids, const float* __restrict__ w, int w_bat
 // Z_m[y / 4][gx][y % 4] (zidx), so that the tile's outputs, gathered in LDS, leave as
 // runs of 4 ncols consecutive elements (whole 128-byte lines for 4 FP32 columns) and
 // the row pass reads each input of a row pair with one load.
+// Column-pass twiddles: held in registers when a thread needs few (FP32), otherwise the
+// two-level LDS table.
+template <typename R, int LOG2N>
+constexpr bool col_tw_reg() { return sizeof(R) == 4 && Fft<LOG2N, col_block(LOG2N)>::NTW <= 32; }
+
 template <typename R, int LOG2N>
 __global__ void __launch_bounds__(col_block(LOG2N))
 colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, int hm, int lc,
@@ -451,13 +481,15 @@ colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, i
   using FF = Fft<LOG2N, CB>;
   constexpr int n = FF::N, S = n / 16;
   constexpr bool DATA = sizeof(R) == 4;
-  constexpr bool REG = DATA && FF::NTW <= 32;
+  constexpr bool REG = col_tw_reg<R, LOG2N>();
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int g = threadIdx.x / FF::TG, t = threadIdx.x - g * FF::TG;
   T* buf = reinterpret_cast<T*>(lds_raw) + g * FF::L;
   const int set = blockIdx.y;
-  Twiddles<R, LOG2N, REG, CB> twr;
-  twr.load(tw, t);
+  using TW = std::conditional_t<REG, Twiddles<R, LOG2N, true, CB>, TwiddlesSplit<R, LOG2N, CB>>;
+  TW twr;
+  if constexpr (REG) twr.load(tw, t);
+  else twr.stage(tw, reinterpret_cast<T*>(lds_raw) + FF::G * FF::L, threadIdx.x, CB);   // the loop's first barrier publishes it
   for (int it = 0; it < tpb; ++it) {
     const int ti = blockIdx.x * tpb + it;
     if (ti >= ntiles) break;   // the same for the whole block
@@ -489,7 +521,9 @@ colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, i
     T res[NBL][RPL];   // output (j, q) of the last pass is element t + TG j + q NSL
     auto out = [&](int, int j, int q, T v) { res[j][q] = v; };
     __syncthreads();   // the previous tile's stage has been written out
-    fft_passes<R, LOG2N, 0, CB>(buf, t, tw, twr, in, out);
+    int tl = t;   // hidden from loop-invariant code motion, as in the row pass
+    asm volatile("" : "+v"(tl));
+    fft_passes<R, LOG2N, 0, CB>(buf, tl, tw, twr, in, out);
     __syncthreads();   // every transform has read its buffer
 #pragma unroll
     for (int j = 0; j < NBL; ++j)
@@ -544,7 +578,13 @@ hipError_t launch_colpass_n(const abs_plan_s* p, int nsets, const typename HermT
   const int ntiles = (int)p->tiles.size();
   if (ntiles == 0) return hipSuccess;
   const dim3 grid((unsigned)((ntiles + kColTilesPerBlock - 1) / kColTilesPerBlock), (unsigned)nsets);
-  const size_t lds = (size_t)FF::G * FF::L * sizeof(typename Cx<R>::T);
+  size_t lds = (size_t)FF::G * FF::L * sizeof(typename Cx<R>::T) +
+               (col_tw_reg<R, LOG2N>() ? 0 : TwiddlesSplit<R, LOG2N, CB>::ENTRIES * sizeof(typename Cx<R>::T));
+  // FP32 8192-point columns: one block per CU.  Their outputs leave in 32-byte runs spread
+  // over the whole field, and a second block per CU makes the pass slower (8192^2 x 4:
+  // 9.1 ms with two blocks per CU, 7.3 ms with one); asking for more than half of the
+  // CU's 160 KB of LDS keeps a second block off.
+  if (LOG2N == 13 && sizeof(R) == 4) lds = std::max<size_t>(lds, 84 * 1024);
   auto k = colpass_fixed_kernel<R, LOG2N>;
   hipError_t e = allow_lds(k, lds);
   if (e != hipSuccess) return e;
@@ -606,7 +646,7 @@ hipError_t launch_rowpass_n(const abs_plan_s* p, int nsets, const typename Cx<R>
   const int nrb = (npairs + per_block - 1) / per_block;
   const dim3 grid((unsigned)(p->nb * nrb), (unsigned)nsets);
   using T = typename Cx<R>::T;
-  const size_t lds = (size_t)FF::G * FF::L * sizeof(T) + (FF::N * sizeof(T) <= 16384 ? FF::N * sizeof(T) : 0);
+  const size_t lds = (size_t)(FF::G * FF::L + TwiddlesSplit<R, LOG2N, RB>::ENTRIES) * sizeof(T);
   hipError_t e;
   if constexpr (sizeof(R) == 4) {
     if (fmax_bits) {   // FP16 split form: largest |F| per (set, ring)

@@ -866,11 +866,15 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
   p->nblk = (int)((npix + p->pix_per_block - 1) / p->pix_per_block);
   // one weight set per call as a rule: smaller blocks keep the GPU busy
   // weight fields: half plane, block 0 = rows 0 and n/2 (so at least 2n pixels a block);
-  // about 256 blocks of the half plane
-  p->pix_per_block64 = (int)std::max<int64_t>(std::max<int64_t>(1024, 2 * (int64_t)p->n), npix / 512);
+  // at most 256 blocks of the half plane, so that the slices of the weight kernel, one
+  // 8-wave workgroup per CU, fill whole rounds of the 256 CUs rather than leaving a round
+  // with a few workgroups.  Blocks are multiples of 128 pixels: the contraction walks
+  // them in pairs of 64-pixel chunks.
   {
-    const int64_t b = p->pix_per_block64;
     const int64_t rows_b = (int64_t)(p->n / 2 - 1) * p->n;
+    const int64_t want = std::max<int64_t>(std::max<int64_t>(1024, 2 * (int64_t)p->n), (rows_b + 254) / 255);
+    p->pix_per_block64 = (int)((want + 127) / 128 * 128);
+    const int64_t b = p->pix_per_block64;
     p->nblk64 = 1 + (int)((rows_b + b - 1) / b);
     p->npix64 = (int64_t)p->nblk64 * b;
   }
