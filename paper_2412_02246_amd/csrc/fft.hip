@@ -552,10 +552,13 @@ hipError_t allow_lds(K kernel, size_t bytes) {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
-constexpr int kRowIters = 4;
+// Row pairs (per transform) a row-pass block walks in turn, and column tiles a column-pass
+// block takes: measured per size (1024^2 x 16: 2 iterations 316 against 326 us with 4, one
+// tile 70 against 75 us with 2; 4096^2 x 16: 8 iterations 8.65 against 8.92 ms with 4, two
+// tiles 2.0 against 2.2 ms with 1); other sizes keep 4 and 2.
+constexpr int row_iters(int log2n) { return log2n <= 10 ? 2 : log2n == 12 ? 8 : 4; }
+constexpr int col_tiles_per_block(int log2n) { return log2n <= 10 ? 1 : 2; }
 }  // namespace
-
-constexpr int kColTilesPerBlock = 2;
 
 template <bool DATA, typename GT>
 hipError_t launch_herm(const abs_plan_s* p, const GT* grids, const float* w, int w_batched, int nsets,
@@ -577,7 +580,8 @@ hipError_t launch_colpass_n(const abs_plan_s* p, int nsets, const typename HermT
   const ColTile* tiles = reinterpret_cast<const ColTile*>(base + p->dl.tiles);
   const int ntiles = (int)p->tiles.size();
   if (ntiles == 0) return hipSuccess;
-  const dim3 grid((unsigned)((ntiles + kColTilesPerBlock - 1) / kColTilesPerBlock), (unsigned)nsets);
+  constexpr int tpb = col_tiles_per_block(LOG2N);
+  const dim3 grid((unsigned)((ntiles + tpb - 1) / tpb), (unsigned)nsets);
   size_t lds = (size_t)FF::G * FF::L * sizeof(typename Cx<R>::T) +
                (col_tw_reg<R, LOG2N>() ? 0 : TwiddlesSplit<R, LOG2N, CB>::ENTRIES * sizeof(typename Cx<R>::T));
   // FP32 8192-point columns: one block per CU.  Their outputs leave in 32-byte runs spread
@@ -588,7 +592,7 @@ hipError_t launch_colpass_n(const abs_plan_s* p, int nsets, const typename HermT
   auto k = colpass_fixed_kernel<R, LOG2N>;
   hipError_t e = allow_lds(k, lds);
   if (e != hipSuccess) return e;
-  k<<<grid, CB, lds, st>>>(xc, p->hmax, 2 * p->hmax + 1, tiles, ntiles, kColTilesPerBlock, bins, tw,
+  k<<<grid, CB, lds, st>>>(xc, p->hmax, 2 * p->hmax + 1, tiles, ntiles, tpb, bins, tw,
                            Z, zset);
   return hipGetLastError();
 }
@@ -641,7 +645,7 @@ hipError_t launch_rowpass_n(const abs_plan_s* p, int nsets, const typename Cx<R>
   constexpr int npairs = HALF ? FF::N / 4 + 1 : FF::N / 2;
   const long long rstride = HALF ? p->npix64 : (long long)FF::N * FF::N;
   const int hb = HALF ? p->pix_per_block64 : 0;
-  const int iters = std::max(1, std::min(kRowIters, npairs / FF::G));
+  const int iters = std::max(1, std::min(row_iters(LOG2N), npairs / FF::G));
   const int per_block = FF::G * iters;
   const int nrb = (npairs + per_block - 1) / per_block;
   const dim3 grid((unsigned)(p->nb * nrb), (unsigned)nsets);

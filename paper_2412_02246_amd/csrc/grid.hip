@@ -141,8 +141,10 @@ scan_tiles_kernel(const int* __restrict__ cnt, long long ncells, int* __restrict
 }
 
 __global__ void __launch_bounds__(kBlock)
-scan_sums_kernel(int* __restrict__ tile_sum, int ntiles, int* __restrict__ start, long long ncells) {
-  // one block: exclusive scan of the tile totals, in chunks of kBlock
+scan_sums_kernel(int* __restrict__ tile_sum, int ntiles, int* __restrict__ start, long long ncells,
+                 const GridScalars* __restrict__ sc, long long* __restrict__ dropped) {
+  // one block: exclusive scan of the tile totals, in chunks of kBlock; also hands out the
+  // count of dropped visibilities (final once the prep pass has run), if asked for
   int carry = 0;
   for (int c0 = 0; c0 < ntiles; c0 += kBlock) {
     const int i = c0 + threadIdx.x;
@@ -152,7 +154,10 @@ scan_sums_kernel(int* __restrict__ tile_sum, int ntiles, int* __restrict__ start
     if (i < ntiles) tile_sum[i] = carry + ex;
     carry += total;
   }
-  if (threadIdx.x == 0) start[ncells] = carry;
+  if (threadIdx.x == 0) {
+    start[ncells] = carry;
+    if (dropped) *dropped = (long long)sc->dropped;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -413,10 +418,6 @@ grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ so
   }
 }
 
-__global__ void grid_dropped_kernel(const GridScalars* sc, long long* dropped) {
-  *dropped = (long long)sc->dropped;
-}
-
 struct GridWork {
   size_t sc, cell, rank, cnt, start, tiles, list, sorted, total;
 };
@@ -497,7 +498,7 @@ extern "C" abs_status abs_grid(abs_plan_t p, int64_t nvis, int32_t batch, const 
   const unsigned gv = (unsigned)std::min<long long>(8192, std::max<long long>(1, (nvis + kBlock - 1) / kBlock));
   if (nvis > 0) grid_prep_kernel<<<gv, kBlock, 0, st>>>(p->n, p->du, nvis, uvd, vis_w, cell, rank, cnt, sc);
   scan_tiles_kernel<<<ntiles, kBlock, 0, st>>>(cnt, cells, start, tsum, sc);
-  scan_sums_kernel<<<1, kBlock, 0, st>>>(tsum, ntiles, start, cells);
+  scan_sums_kernel<<<1, kBlock, 0, st>>>(tsum, ntiles, start, cells, sc, reinterpret_cast<long long*>(dropped));
   scan_add_kernel<<<ntiles, kBlock, 0, st>>>(start, cells, tsum);
   if (nvis > 0)
     grid_fill_kernel<<<(unsigned)((nvis + kBlock - 1) / kBlock), kBlock, 0, st>>>(
@@ -543,7 +544,6 @@ extern "C" abs_status abs_grid(abs_plan_t p, int64_t nvis, int32_t batch, const 
 #undef ABS_GATHER_L
 #undef ABS_GATHER
   }
-  if (dropped) grid_dropped_kernel<<<1, 1, 0, st>>>(sc, reinterpret_cast<long long*>(dropped));
   prof_end(p, ABS_STAGE_GRID, st);
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
