@@ -555,8 +555,9 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 // Row pairs (per transform) a row-pass block walks in turn, and column tiles a column-pass
 // block takes: measured per size (1024^2 x 16: 2 iterations 316 against 326 us with 4, one
 // tile 70 against 75 us with 2; 4096^2 x 16: 8 iterations 8.65 against 8.92 ms with 4, two
-// tiles 2.0 against 2.2 ms with 1); other sizes keep 4 and 2.
-constexpr int row_iters(int log2n) { return log2n <= 10 ? 2 : log2n == 12 ? 8 : 4; }
+// tiles 2.0 against 2.2 ms with 1; 8192^2 x 4: 8 iterations 20.4 ms, 2 iterations 21.6 ms);
+// 2048 keeps 4 and 2.
+constexpr int row_iters(int log2n) { return log2n <= 10 ? 2 : log2n >= 12 ? 8 : 4; }
 constexpr int col_tiles_per_block(int log2n) { return log2n <= 10 ? 1 : 2; }
 }  // namespace
 
