@@ -170,8 +170,8 @@ __device__ __forceinline__ void fft_sync() {
   }
 }
 
-// Per-thread twiddles: REG keeps all of them in registers, otherwise they are read from
-// the table when used.
+// Per-thread twiddles held in registers (REG = true, the only form defined here), loaded
+// once per block; transforms that need more take TwiddlesSplit below.
 template <typename R, int LOG2N, bool REG, int BLOCK = kBlock>
 struct Twiddles;
 template <typename R, int LOG2N, int BLOCK>
@@ -198,18 +198,6 @@ struct Twiddles<R, LOG2N, true, BLOCK> {
   template <int P>
   __device__ __forceinline__ T get(const T* __restrict__, int, int j, int r) const {
     return w[F::tw_before(P) + j * ((1 << F::lrp(P)) - 1) + r - 1];
-  }
-};
-template <typename R, int LOG2N, int BLOCK>
-struct Twiddles<R, LOG2N, false, BLOCK> {
-  using T = typename Cx<R>::T;
-  using F = Fft<LOG2N, BLOCK>;
-  __device__ __forceinline__ void load(const T* __restrict__, int) {}
-  template <int P>
-  __device__ __forceinline__ T get(const T* __restrict__ tw, int t, int j, int r) const {
-    constexpr int LRP = F::lrp(P), LNS = 4 * P, SH = LOG2N - LNS - LRP;
-    const int m = (t + F::TG * j) & ((1 << LNS) - 1);
-    return tw[(r * m) << SH];
   }
 };
 
