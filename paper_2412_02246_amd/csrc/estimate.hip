@@ -30,22 +30,25 @@ hipError_t launch_rowpass_f64(const abs_plan_s* p, int nsets, const double2* Z, 
 
 // Sum of nblk workgroup partials part[k * ntrip + pos[t]] of triplet t (pos: the
 // triplet's position in the writing kernel's order, NULL for t itself) for the block's
-// 64 triplets, in a fixed order: wave w adds its quarter of k in sequence, then the
-// quarters are added in order w = 0 .. 3.  Every thread of the block must call it.
+// 64 triplets, in a fixed order: wave w of the kFinWaves adds its share of k in sequence,
+// then the shares are added in order w = 0, 1, ...  Every thread of the block must call it.
+constexpr int kFinWaves = 16, kFinBlock = 64 * kFinWaves;
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nblk, int ntrip,
                                                const int* __restrict__ pos, int t) {
-  __shared__ double q4[4][64];
+  __shared__ double q[kFinWaves][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int k0 = (int)((long long)nblk * wave / 4), k1 = (int)((long long)nblk * (wave + 1) / 4);
+  const int k0 = (int)((long long)nblk * wave / kFinWaves), k1 = (int)((long long)nblk * (wave + 1) / kFinWaves);
   double s = 0.0;
   if (t < ntrip) {
     const int c = pos ? pos[t] : t;
     for (int k = k0; k < k1; ++k) s += part[(long long)k * ntrip + c];
   }
-  __syncthreads();   // q4 is reused by the next call
-  q4[wave][lane] = s;
+  __syncthreads();   // q is reused by the next call
+  q[wave][lane] = s;
   __syncthreads();
-  return ((q4[0][lane] + q4[1][lane]) + q4[2][lane]) + q4[3][lane];
+  double r = q[0][lane];
+  for (int w = 1; w < kFinWaves; ++w) r += q[w][lane];
+  return r;
 }
 
 // Weight-set sum over all pixels from the half-plane partials: block 0 (rows 0 and n/2,
@@ -61,7 +64,7 @@ __device__ __forceinline__ double sum_partials_half(const double* __restrict__ p
 // B[b][t] = S / (A N), S and N the per-triangle sums: workgroup partials are added
 // in FP64 in a fixed order and divided by n^2 (the sum over pixels of a product of
 // three DFTs counts every closed triangle n^2 times).  Block: 64 triplets of grid b.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kFinBlock)
 finalize_kernel(const double* __restrict__ part, long long partset, int nblk, const int* __restrict__ pos,
                 const double* __restrict__ part64, long long partset64, int nblk64,
                 const int* __restrict__ pos64, int ntrip, int batch, int nisets,
@@ -84,7 +87,7 @@ finalize_kernel(const double* __restrict__ part, long long partset, int nblk, co
 }
 
 // abs_counts: N_t alone from the weight-set partials.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kFinBlock)
 counts_kernel(const double* __restrict__ part64, int nblk64, const int* __restrict__ pos64, int ntrip,
               double inv_npix, double* __restrict__ N) {
   const int t = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -265,7 +268,7 @@ abs_status abs_estimate(abs_plan_t p, int32_t batch, int32_t dtype, const void* 
   // by triplet index
   const int* pos = p->precision == ABS_FP32 ? reinterpret_cast<const int*>(base + p->dl.pos32) : nullptr;
   const int* pos64 = reinterpret_cast<const int*>(base + p->dl.pos64);
-  finalize_kernel<<<g, kBlock, 0, st>>>(part, wl.partset, p->nblk, pos, part64, wl.partset64, p->nblk64,
+  finalize_kernel<<<g, kFinBlock, 0, st>>>(part, wl.partset, p->nblk, pos, part64, wl.partset64, p->nblk64,
                                         pos64, (int)p->ntrip, batch, wl.nisets, n_given, inv, p->norm, B, N);
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
@@ -287,7 +290,7 @@ abs_status abs_counts(abs_plan_t p, const float* w, void* work, size_t work_byte
   if (s != ABS_OK) return s;
   const double inv = 1.0 / ((double)p->n * (double)p->n);
   const int* pos64 = reinterpret_cast<const int*>(static_cast<const char*>(p->dev) + p->dl.pos64);
-  counts_kernel<<<(unsigned)((p->ntrip + 63) / 64), kBlock, 0, st>>>(
+  counts_kernel<<<(unsigned)((p->ntrip + 63) / 64), kFinBlock, 0, st>>>(
       reinterpret_cast<const double*>(wk + wl.part64), p->nblk64, pos64, (int)p->ntrip, inv, N);
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
