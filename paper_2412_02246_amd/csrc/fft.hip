@@ -201,8 +201,8 @@ struct Twiddles<R, LOG2N, true, BLOCK> {
   }
 };
 
-// Twiddles from a two-level table in LDS, for transforms whose full table is too large
-// to stage: w^a = hi[a / LO] lo[a % LO] with lo[c] = w^c (c < LO = min(64, N)) and
+// Twiddles from a two-level table in LDS (row passes, and column passes whose threads need
+// more twiddles than registers hold): w^a = hi[a / LO] lo[a % LO] with lo[c] = w^c (c < LO = min(64, N)) and
 // hi[b] = w^(LO b) (b < N / LO), both copied from the plan's table, so one complex
 // product (about one rounding more than the table entry) replaces a load from memory.
 template <typename R, int LOG2N, int BLOCK = kBlock>
@@ -308,8 +308,8 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int g = threadIdx.x / FF::TG, t = threadIdx.x - g * FF::TG;
   T* buf = reinterpret_cast<T*>(lds_raw) + g * FF::L;
-  // The two-level twiddle table sits in LDS after the FFT buffers: a few hundred bytes
-  // instead of the full table (n/16 + 1 KB less LDS per block, so more blocks per CU).
+  // The two-level twiddle table sits in LDS after the FFT buffers: at most 1.5 KB instead
+  // of the full table (8 or 16 bytes per point), so more blocks fit a CU.
   TwiddlesSplit<R, LOG2N, RB> twr;
   twr.stage(tw, reinterpret_cast<T*>(lds_raw) + FF::G * FF::L, threadIdx.x, RB);
   __syncthreads();
