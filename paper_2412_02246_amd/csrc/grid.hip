@@ -337,23 +337,44 @@ grid_gather_kernel(int n, double du, double pit2, int batch, int b0,
 // lists at each cell); the weight sum is the record count of both cells.  Representatives:
 // rows 0 .. n/2 in order (|gy| ascending: the long lists of short baselines first), and in
 // rows 0 and n/2 only columns 0 .. n/2; row and column -n/2 receive nothing.
+// The block's results go out through LDS, one realisation plane at a time, so that each
+// plane receives runs of PB consecutive cells (and PB mirror cells) rather than runs of
+// 64 / LPC.
+template <int LPC>
+struct PairCell {
+  bool valid;        // a representative (not a mirror, not past the half plane)
+  long long c, m;    // the cell and its mirror
+};
+template <int LPC>
+__device__ __forceinline__ PairCell<LPC> pair_cell(long long lc, int n) {
+  const int half = n / 2;
+  PairCell<LPC> r{false, 0, 0};
+  if (lc >= (long long)(half + 1) * n) return r;
+  const int iy = (int)(lc / n), ix = (int)(lc - (long long)iy * n);
+  if ((iy == 0 || iy == half) && ix > half) return r;   // the mirror of a representative
+  const int my = iy ? n - iy : 0, mx = ix ? n - ix : 0;
+  r.valid = true;
+  r.c = (long long)iy * n + ix;
+  r.m = (long long)my * n + mx;
+  return r;
+}
+
 template <int LPC, bool VEC>
 __global__ void __launch_bounds__(kBlock)
 grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ sorted,
                          const int* __restrict__ start, const GridScalars* sc,
                          float2* __restrict__ grid, float* __restrict__ wsum) {
+  constexpr int PB = kBlock / LPC;   // pairs per block
+  __shared__ float2 out_c[2 * LPC][PB + 1], out_m[2 * LPC][PB + 1];   // padded: rows 2q start in different banks
   const long long nn = (long long)n * n;
   const int half = n / 2;
-  const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long lc = gt / LPC;
-  const int q = (int)(gt - lc * LPC);
-  if (lc >= (long long)(half + 1) * n) return;
-  const int iy = (int)(lc / n), ix = (int)(lc - (long long)iy * n);
-  if ((iy == 0 || iy == half) && ix > half) return;   // the mirror of a representative
-  const int my = iy ? n - iy : 0, mx = ix ? n - ix : 0;
-  const long long c = (long long)iy * n + ix, m = (long long)my * n + mx;
+  const int kp = threadIdx.x / LPC, q = threadIdx.x - kp * LPC;
+  const long long lc = (long long)blockIdx.x * PB + kp;
+  const PairCell<LPC> pc = pair_cell<LPC>(lc, n);
+  const long long c = pc.c, m = pc.m;
+  const int iy = (int)(c / n), ix = (int)(c - (long long)iy * n);
   const int gy = iy < half ? iy : iy - n, gx = ix < half ? ix : ix - n;
-  const bool inside = gx > -half && gy > -half;       // the mirror is inside exactly then
+  const bool inside = pc.valid && gx > -half && gy > -half;   // the mirror is inside exactly then
   // a cell adds at most 2 maxcnt terms (its own records and its mirror's)
   const double sv = fixed_scale(__uint_as_float(sc->vmax_bits), 2ll * (long long)sc->maxcnt);
   const int bq = b0 + 2 * q;
@@ -406,15 +427,24 @@ grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ so
     }
   }
   const double iv = 1.0 / sv;  // a power of two: exact
-  auto put = [&](long long cell, const double* a, const double* b) {
-    if (has0) grid[(long long)bq * nn + cell] = make_float2((float)((a[0] + b[0]) * iv), (float)((a[1] - b[1]) * iv));
-    if (has1) grid[(long long)(bq + 1) * nn + cell] = make_float2((float)((a[2] + b[2]) * iv), (float)((a[3] - b[3]) * iv));
-  };
-  put(c, sc4, sm4);
-  if (m != c) put(m, sm4, sc4);
-  if (wsum != nullptr && b0 == 0 && q == 0) {
+  out_c[2 * q][kp] = make_float2((float)((sc4[0] + sm4[0]) * iv), (float)((sc4[1] - sm4[1]) * iv));
+  out_c[2 * q + 1][kp] = make_float2((float)((sc4[2] + sm4[2]) * iv), (float)((sc4[3] - sm4[3]) * iv));
+  out_m[2 * q][kp] = make_float2((float)((sm4[0] + sc4[0]) * iv), (float)((sm4[1] - sc4[1]) * iv));
+  out_m[2 * q + 1][kp] = make_float2((float)((sm4[2] + sc4[2]) * iv), (float)((sm4[3] - sc4[3]) * iv));
+  if (pc.valid && wsum != nullptr && b0 == 0 && q == 0) {
     wsum[c] = (float)(cd + cm);
     wsum[m] = (float)(cd + cm);
+  }
+  __syncthreads();
+  // plane r of the pass, pair k: consecutive threads take consecutive pairs
+  for (int e = threadIdx.x; e < 2 * LPC * PB; e += kBlock) {
+    const int r = e / PB, k = e - r * PB;
+    if (b0 + r >= batch) continue;
+    const PairCell<LPC> w = pair_cell<LPC>((long long)blockIdx.x * PB + k, n);
+    if (!w.valid) continue;
+    float2* plane = grid + (long long)(b0 + r) * nn;
+    plane[w.c] = out_c[r][k];
+    if (w.m != w.c) plane[w.m] = out_m[r][k];
   }
 }
 
