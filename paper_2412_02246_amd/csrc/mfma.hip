@@ -164,6 +164,9 @@ mfma_contract_kernel(const float* __restrict__ F, long long set_stride, long lon
     dhi[nb * kRow16 + q] = (HT)0.f;
     dlo[nb * kRow16 + q] = (HT)0.f;
   }
+  // sexp (written by the first nb + 1 threads, all in wave 0) is read by every wave while
+  // it stages the first chunk, before the chunk loop's first barrier: publish it here
+  __syncthreads();
 
   f32x4 acc[TPW];
 #pragma unroll
