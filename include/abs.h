@@ -22,7 +22,13 @@
  *     one closed lattice triangle (decided exactly on the host);
  *   - reported sums are per triangle: S_t = (1/n^2) sum_theta D_i D_j D_k equals the sum
  *     of X(g1) X(g2) X(g3) over closed triangles, N_t likewise with Y, and
- *     B_t = S_t / (A N_t); where N_t is exactly zero B_t is the IEEE quotient;
+ *     B_t = S_t / (A N_t);
+ *   - empty triplets (Eq. 12 has no weighted triangle to average): weights are taken to
+ *     be non-negative, so every closed triangle whose three cells carry weight adds at
+ *     least w_min^3 to N_t, w_min being the smallest non-zero Y over the cells of all
+ *     rings (1 for unit weights); where N_t < w_min^3 / 2 the triplet has no weighted
+ *     triangle, its N_t is rounding noise of an exact zero, and B_t is NaN (N_t is still
+ *     reported);
  *   - device pointers are caller-owned and must stay valid until the stream work that
  *     uses them has finished; the library never allocates device memory;
  *   - every function returns a status code; none aborts or prints.  Launch or device
@@ -94,8 +100,8 @@ typedef struct abs_plan_info {
 } abs_plan_info;
 
 /* Build a plan on the host: rings (Sec. 2), the triplet list with an exact lattice
- * test (Sec. 3, "every possible combination of three annular rings"), per-triplet
- * labels and the device tables.  No HIP call is made.
+ * test (Sec. 3: all ring triplets, each kept when its rings hold a closed lattice
+ * triangle), per-triplet labels and the device tables.  No HIP call is made.
  * Errors: ABS_ERR_INVALID (n not a power of two in [16, 8192], nbins out of range,
  * edges not strictly increasing or negative, edges[0] == 0 without ABS_ALLOW_DC,
  * bad mode, max_batch < 1), ABS_ERR_ALIAS (edges[nbins] > n/3 without ABS_ALLOW_WRAP,

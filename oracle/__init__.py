@@ -9,8 +9,7 @@ Gill, Bharadwaj, Ali & Elahi (2024), "A visibility-based angular bispectrum
 estimator for radio-interferometric data":
 
 * ``plan``      -- annular rings and the list of ring triplets (Sec. 2, the ring
-                   partition of the uv plane; Sec. 3, "every possible combination
-                   of three annular rings").
+                   partition of the uv plane; Sec. 3, all ring triplets).
 * ``estimator`` -- Eqs. (10) D, (11) I and (12) B-hat, computed with numpy FFTs in
                    FP64 and a chunked FP64 matrix product.
 * ``brute``     -- the same sums by direct enumeration of closed grid triangles

@@ -17,7 +17,12 @@ Readings of the paper where it is silent or ambiguous:
   choice with N_g the gridded count) or GIVEN (W supplied);
 * reported sums are normalised per triangle: S_t = sum_theta D_i D_j D_k / n^2 and
   N_t = sum_theta I_i I_j I_k / n^2, which equal the sums over closed triangles
-  (mod n) of X X X and Y Y Y; B_t = S_t / (A N_t).
+  (mod n) of X X X and Y Y Y; B_t = S_t / (A N_t);
+* empty triplets: with non-negative weights every closed triangle whose three cells
+  are weighted adds at least w_min^3 to N_t, w_min being the smallest non-zero |Y|
+  over the cells of all rings (1 for unit weights).  A triplet with
+  N_t < w_min^3 / 2 therefore holds no weighted triangle (its N_t is rounding noise
+  of an exact zero) and its B_t is NaN; N_t is still reported.
 
 Pins: tests/test_oracle_estimator.py (brute force over closed triangles on
 n = 8, 16, 32 in cyclic and planar form, integer counts, invariants, the
@@ -54,6 +59,22 @@ def effective_weights(n, w, wmode):
     if wmode == GIVEN:
         return w.copy()
     raise ValueError("unknown weight mode")
+
+
+def min_weight(Y, masks):
+    """w_min of the empty-triplet rule: the smallest non-zero |Y| over the cells that
+    lie in any ring (inf when every ring cell has zero weight)."""
+    inring = np.any(masks, axis=0)
+    a = np.abs(Y[inring])
+    a = a[a > 0]
+    return float(a.min()) if a.size else np.inf
+
+
+def ratio(S, N, norm, wmin):
+    """B_t = S_t / (A N_t), NaN where N_t < w_min^3 / 2 (no weighted triangle)."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        B = S / (norm * N)
+    return np.where(N < 0.5 * wmin ** 3, np.nan, B)
 
 
 def ring_fields(Xfull, masks):
@@ -117,9 +138,9 @@ def estimate(grid, w, edges, norm, wmode=UNIT, trips=None, with_scales=False, ch
     I = ring_fields(Y, masks)
     S = triple_sums(D, trips, chunk)
     N = triple_sums(I, trips, chunk)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        B = S / (norm * N)
-    out = dict(B=B, S=S, N=N, trips=trips)
+    wmin = min_weight(Y.real, masks)
+    B = ratio(S, N, norm, wmin)
+    out = dict(B=B, S=S, N=N, trips=trips, wmin=wmin)
     if with_scales:
         out["rhoS"] = np.sqrt(np.maximum(triple_sums(D, trips, chunk, power=2), 0.0) / n ** 2)
         out["rhoN"] = np.sqrt(np.maximum(triple_sums(I, trips, chunk, power=2), 0.0) / n ** 2)
@@ -151,8 +172,8 @@ def estimate_subset(grid, w, edges, norm, trips, wmode=UNIT):
         out["N"][q] = e.sum() / npix
         out["rhoS"][q] = np.sqrt((d * d).sum()) / npix
         out["rhoN"][q] = np.sqrt((e * e).sum()) / npix
-    with np.errstate(divide="ignore", invalid="ignore"):
-        out["B"] = out["S"] / (norm * out["N"])
+    out["wmin"] = wmin = min_weight(Y.real, np.asarray([rc >= 0]))
+    out["B"] = ratio(out["S"], out["N"], norm, wmin)
     out["trips"] = trips
     return out
 

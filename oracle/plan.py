@@ -5,9 +5,9 @@ TEST INFRASTRUCTURE ONLY (see the package header).
 Sources (Gill et al. 2024):
 * Sec. 2, the paragraph introducing Eq. (10): the uv plane is divided into
   annular rings a_m with mean radii U_m, and ell_m = 2 pi U_m.
-* Sec. 3, the ring scheme paragraph: B-hat is evaluated for "every possible
-  combination of three annular rings", each estimate being the average over all
-  closed triangles with one vertex in each ring.
+* Sec. 3, the ring scheme paragraph: B-hat is evaluated for all triplets of rings,
+  each estimate being the average over all closed triangles with one vertex in
+  each ring.
 * Sec. 2, below Eq. (3): ell_1 >= ell_2 >= ell_3, mu = (l1^2 + l2^2 - l3^2)/(2 l1 l2),
   t = l2 / l1 (Sec. 2 after Eq. 12 gives the same mu in terms of side lengths).
 

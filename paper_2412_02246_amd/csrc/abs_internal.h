@@ -59,7 +59,7 @@ struct JitPart {
 struct WorkLayout {
   int nsets;          // D sets (one per grid) followed by I sets
   int nisets;
-  size_t zd, zi, fd, fi, part, part64, fmax, xc, total;
+  size_t zd, zi, fd, fi, part, part64, fmax, wmin, xc, total;
   int64_t zset;       // complex elements per set of column-pass output
   int64_t fset;       // values per set of data fields (nbins * n * n)
   int64_t fset64;     // values per set of weight fields (nbins * npix64)

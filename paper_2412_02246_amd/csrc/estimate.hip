@@ -13,9 +13,10 @@
 namespace abs_impl {
 hipError_t launch_colpass_data(const abs_plan_s* p, const void* grids, int dtype, const float* w,
                                int w_batched, int batch, void* xc, float2* Z, long long zset,
-                               hipStream_t st);
+                               unsigned long long* wmin, hipStream_t st);
 hipError_t launch_colpass_weight(const abs_plan_s* p, const float* w, int w_batched, int nsets,
-                                 void* xc, double2* Z, long long zset, hipStream_t st);
+                                 void* xc, double2* Z, long long zset, unsigned long long* wmin,
+                                 hipStream_t st);
 hipError_t launch_rowpass_f32(const abs_plan_s* p, int nsets, const float2* Z, long long zset,
                               float* F, long long fset, unsigned* fmax_bits, hipStream_t st);
 hipError_t launch_mfma_contract(const abs_plan_s* p, const float* F, long long fset, int nsets,
@@ -25,6 +26,11 @@ __global__ void fill_u32_kernel(unsigned* __restrict__ a, int n, unsigned v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;
 }
+__global__ void fill_u64_kernel(unsigned long long* __restrict__ a, int n, unsigned long long v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;   // FP64 +inf
 hipError_t launch_rowpass_f64(const abs_plan_s* p, int nsets, const double2* Z, long long zset,
                               double* F, long long fset, hipStream_t st);
 
@@ -64,12 +70,16 @@ __device__ __forceinline__ double sum_partials_half(const double* __restrict__ p
 // B[b][t] = S / (A N), S and N the per-triangle sums: workgroup partials are added
 // in FP64 in a fixed order and divided by n^2 (the sum over pixels of a product of
 // three DFTs counts every closed triangle n^2 times).  Block: 64 triplets of grid b.
+// Empty triplets: with non-negative weights each closed triangle whose three cells carry
+// weight adds at least w_min^3 to N_t (w_min: the smallest non-zero ring-cell weight of
+// grid b, recorded by the Hermitian-part pass), so N_t < w_min^3 / 2 means no weighted
+// triangle (N_t is then rounding noise of an exact zero) and B_t is NaN.
 __global__ void __launch_bounds__(kFinBlock)
 finalize_kernel(const double* __restrict__ part, long long partset, int nblk, const int* __restrict__ pos,
                 const double* __restrict__ part64, long long partset64, int nblk64,
                 const int* __restrict__ pos64, int ntrip, int batch, int nisets,
-                const double* __restrict__ n_given, double inv_npix, double norm,
-                double* __restrict__ B, double* __restrict__ N) {
+                const double* __restrict__ n_given, const unsigned long long* __restrict__ wmin_bits,
+                double inv_npix, double norm, double* __restrict__ B, double* __restrict__ N) {
   const int t = blockIdx.x * 64 + (threadIdx.x & 63);
   const int b = blockIdx.y;
   const double s = sum_partials(part + (long long)b * partset, nblk, ntrip, pos, t) * inv_npix;
@@ -81,7 +91,8 @@ finalize_kernel(const double* __restrict__ part, long long partset, int nblk, co
     nn = sum_partials_half(part64 + (long long)is * partset64, nblk64, ntrip, pos64, t) * inv_npix;
   }
   if (threadIdx.x < 64 && t < ntrip) {
-    B[(long long)b * ntrip + t] = s / (norm * nn);
+    const double wm = __longlong_as_double((long long)wmin_bits[b]);
+    B[(long long)b * ntrip + t] = nn < 0.5 * wm * wm * wm ? __builtin_nan("") : s / (norm * nn);
     if (N) N[(long long)b * ntrip + t] = nn;
   }
 }
@@ -130,11 +141,16 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
                                    hipStream_t st) {
   double* part = reinterpret_cast<double*>(work + wl.part);
   const long long npix = (long long)p->n * p->n;
+  unsigned long long* wmin = reinterpret_cast<unsigned long long*>(work + wl.wmin);
+  {
+    const int cnt = batch + wl.nisets;
+    fill_u64_kernel<<<(cnt + kBlock - 1) / kBlock, kBlock, 0, st>>>(wmin, cnt, kInfBits);
+  }
   if (batch > 0) {
     float2* Z = reinterpret_cast<float2*>(work + wl.zd);
     float* F = reinterpret_cast<float*>(work + wl.fd);
     prof_begin(p, ABS_STAGE_COLPASS, st);
-    if (launch_colpass_data(p, grids, dtype, w, w_batched, batch, work + wl.xc, Z, wl.zset, st) !=
+    if (launch_colpass_data(p, grids, dtype, w, w_batched, batch, work + wl.xc, Z, wl.zset, wmin, st) !=
         hipSuccess)
       return ABS_ERR_DEVICE;
     prof_end(p, ABS_STAGE_COLPASS, st);
@@ -163,7 +179,8 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
   if (wl.nisets > 0) {
     double2* Z = reinterpret_cast<double2*>(work + wl.zi);
     double* F = reinterpret_cast<double*>(work + wl.fi);
-    if (launch_colpass_weight(p, w, w_batched, wl.nisets, work + wl.xc, Z, wl.zset, st) != hipSuccess)
+    if (launch_colpass_weight(p, w, w_batched, wl.nisets, work + wl.xc, Z, wl.zset, wmin + batch, st) !=
+        hipSuccess)
       return ABS_ERR_DEVICE;
     if (launch_rowpass_f64(p, wl.nisets, Z, wl.zset, F, wl.fset64, st) != hipSuccess)
       return ABS_ERR_DEVICE;
@@ -268,8 +285,10 @@ abs_status abs_estimate(abs_plan_t p, int32_t batch, int32_t dtype, const void* 
   // by triplet index
   const int* pos = p->precision == ABS_FP32 ? reinterpret_cast<const int*>(base + p->dl.pos32) : nullptr;
   const int* pos64 = reinterpret_cast<const int*>(base + p->dl.pos64);
+  const unsigned long long* wmin = reinterpret_cast<const unsigned long long*>(wk + wl.wmin);
   finalize_kernel<<<g, kFinBlock, 0, st>>>(part, wl.partset, p->nblk, pos, part64, wl.partset64, p->nblk64,
-                                        pos64, (int)p->ntrip, batch, wl.nisets, n_given, inv, p->norm, B, N);
+                                        pos64, (int)p->ntrip, batch, wl.nisets, n_given, wmin, inv, p->norm,
+                                        B, N);
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
 

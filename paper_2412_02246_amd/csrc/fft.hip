@@ -408,18 +408,27 @@ template <bool DATA> struct HermT;
 template <> struct HermT<true> { using T = float2; };
 template <> struct HermT<false> { using T = double; };
 
+//
+// Each block also records, for the empty-triplet rule of the finaliser, the smallest
+// non-zero Y(g) over its cells that lie in some ring (lo2 <= |g|^2 < hi2: the rings are
+// contiguous), as a running minimum of FP64 bit patterns in wmin[set] (non-negative
+// doubles order like their bits; the caller sets it to +inf first).  Y is even, so the
+// half plane gx >= 0 holds every value.
 template <bool DATA, typename GT>
 __global__ void __launch_bounds__(kBlock)
 herm_kernel(const GT* __restrict__ grids, const float* __restrict__ w, int w_batched, int wmode,
-            int n, int hm, int lc, typename HermT<DATA>::T* __restrict__ xc) {
+            int n, int hm, int lc, double lo2, double hi2, typename HermT<DATA>::T* __restrict__ xc,
+            unsigned long long* __restrict__ wmin) {
   using OT = typename HermT<DATA>::T;
   __shared__ OT tile[kHy][kHx + 1];
+  __shared__ double wred[kBlock / 64];
   const int set = blockIdx.z;
   const int gx0 = blockIdx.x * kHx, gy0 = blockIdx.y * kHy - hm;
   const long long nn = (long long)n * n;
   const GT* __restrict__ gs = DATA ? grids + (long long)set * nn : nullptr;
   const float* __restrict__ ws = (w && w_batched) ? w + (long long)set * nn : w;
   const int tx = threadIdx.x & (kHx - 1), ty = threadIdx.x / kHx;
+  double ymin = __builtin_inf();
   for (int yy = ty; yy < kHy; yy += kBlock / kHx) {
     const int gx = gx0 + tx, gy = gy0 + yy;
     OT v{};
@@ -427,17 +436,27 @@ herm_kernel(const GT* __restrict__ grids, const float* __restrict__ w, int w_bat
       const int iy = gy < 0 ? gy + n : gy;
       const int my = gy > 0 ? n - gy : -gy, mx = gx > 0 ? n - gx : 0;
       const long long i0 = (long long)iy * n + gx, i1 = (long long)my * n + mx;
+      const double y = 0.5 * (weight_of<double>(ws, wmode, i0) + weight_of<double>(ws, wmode, i1));
+      const double r2 = (double)((long long)gx * gx + (long long)gy * gy);
+      if (r2 >= lo2 && r2 < hi2 && y != 0.0) ymin = fmin(ymin, fabs(y));
       if constexpr (DATA) {
         const float w0 = weight_of<float>(ws, wmode, i0), w1 = weight_of<float>(ws, wmode, i1);
         const float2 a = load_vis(gs, i0), b = load_vis(gs, i1);
         v = make_float2(0.5f * (w0 * a.x + w1 * b.x), 0.5f * (w0 * a.y - w1 * b.y));
       } else {
-        v = 0.5 * (weight_of<double>(ws, wmode, i0) + weight_of<double>(ws, wmode, i1));
+        v = y;
       }
     }
     tile[yy][tx] = v;
   }
+  for (int o = 32; o > 0; o >>= 1) ymin = fmin(ymin, __shfl_xor(ymin, o));
+  if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = ymin;
   __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = wred[0];
+    for (int k = 1; k < kBlock / 64; ++k) m = fmin(m, wred[k]);
+    if (m < __builtin_inf()) atomicMin(&wmin[set], (unsigned long long)__double_as_longlong(m));
+  }
   for (int e = threadIdx.x; e < kHx * kHy; e += kBlock) {
     const int c = e / kHy, yy = e - c * kHy;
     const int gx = gx0 + c, gy = gy0 + yy;
@@ -551,10 +570,11 @@ constexpr int col_tiles_per_block(int log2n) { return log2n <= 10 ? 1 : 2; }
 
 template <bool DATA, typename GT>
 hipError_t launch_herm(const abs_plan_s* p, const GT* grids, const float* w, int w_batched, int nsets,
-                       typename HermT<DATA>::T* xc, hipStream_t st) {
+                       typename HermT<DATA>::T* xc, unsigned long long* wmin, hipStream_t st) {
   const int hm = p->hmax, lc = 2 * p->hmax + 1;
   const dim3 grid((unsigned)((hm + kHx) / kHx), (unsigned)((lc + kHy - 1) / kHy), (unsigned)nsets);
-  herm_kernel<DATA, GT><<<grid, kBlock, 0, st>>>(grids, w, w_batched, p->wmode, p->n, hm, lc, xc);
+  herm_kernel<DATA, GT><<<grid, kBlock, 0, st>>>(grids, w, w_batched, p->wmode, p->n, hm, lc, p->lo2[0],
+                                                 p->hi2[p->nb - 1], xc, wmin);
   return hipGetLastError();
 }
 
@@ -602,23 +622,26 @@ hipError_t launch_colpass(const abs_plan_s* p, int nsets, const typename HermT<s
 
 hipError_t launch_colpass_data(const abs_plan_s* p, const void* grids, int dtype, const float* w,
                                int w_batched, int batch, void* xc, float2* Z, long long zset,
-                               hipStream_t st) {
+                               unsigned long long* wmin, hipStream_t st) {
   const char* base = static_cast<const char*>(p->dev);
   const float2* tw = reinterpret_cast<const float2*>(base + p->dl.tw);
   float2* x = static_cast<float2*>(xc);
   hipError_t e = dtype == ABS_C128
-                     ? launch_herm<true, double2>(p, static_cast<const double2*>(grids), w, w_batched, batch, x, st)
-                     : launch_herm<true, float2>(p, static_cast<const float2*>(grids), w, w_batched, batch, x, st);
+                     ? launch_herm<true, double2>(p, static_cast<const double2*>(grids), w, w_batched, batch, x,
+                                                  wmin, st)
+                     : launch_herm<true, float2>(p, static_cast<const float2*>(grids), w, w_batched, batch, x,
+                                                 wmin, st);
   if (e != hipSuccess) return e;
   return launch_colpass<float>(p, batch, x, Z, zset, tw, st);
 }
 
 hipError_t launch_colpass_weight(const abs_plan_s* p, const float* w, int w_batched, int nsets,
-                                 void* xc, double2* Z, long long zset, hipStream_t st) {
+                                 void* xc, double2* Z, long long zset, unsigned long long* wmin,
+                                 hipStream_t st) {
   const char* base = static_cast<const char*>(p->dev);
   const double2* tw = reinterpret_cast<const double2*>(base + p->dl.tw64);
   double* x = static_cast<double*>(xc);
-  hipError_t e = launch_herm<false, float2>(p, nullptr, w, w_batched, nsets, x, st);
+  hipError_t e = launch_herm<false, float2>(p, nullptr, w, w_batched, nsets, x, wmin, st);
   if (e != hipSuccess) return e;
   return launch_colpass<double>(p, nsets, x, Z, zset, tw, st);
 }

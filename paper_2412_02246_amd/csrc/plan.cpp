@@ -171,6 +171,9 @@ WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_c
   off = al(off + (size_t)w.nisets * w.partset64 * 8);
   w.fmax = off;
   off = al(off + (size_t)batch * p->nb * 4);
+  // smallest non-zero ring-cell weight per data set, then per weight set (FP64 bits)
+  w.wmin = off;
+  off = al(off + (size_t)(batch + w.nisets) * 8);
   // column-major Hermitian part for the column pass: 8 bytes per cell (FP32 complex for
   // the data sets, FP64 real for the weight sets), reused by both in turn
   w.xc = off;

@@ -12,6 +12,7 @@ from oracle import plan as oplan
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
+PREC_TOL = 1e-4     # precision forms (split BF16 / FP16 products)
 
 
 def _torch():
@@ -36,11 +37,12 @@ def _run(plan, grids, w=None, w_batched=False, dtype=None, n_given=None):
 
 def _check(B, N, ref, norm, tol=TOL, label=""):
     # A triplet whose rings close triangles only through zero-weight cells has an empty
-    # weighted set: N_t = 0 exactly, so both sides hold rounding noise there and B_t is
-    # not defined (any real triangle contributes at least w_min^3 > 0 to N_t).  Such
-    # triplets must be empty on the GPU too; B is compared on the others.
-    empty = np.abs(ref["N"]) <= 1e-9 * np.maximum(ref["rhoN"], 1e-300)
-    assert np.all(np.abs(N[empty]) <= 1e-9 * ref["rhoN"][empty]), label
+    # weighted set: N_t is rounding noise of an exact zero and B_t is NaN (N_t below
+    # w_min^3 / 2, since any weighted triangle adds at least w_min^3).  The GPU must mark
+    # exactly the oracle's empty triplets; B is compared on the others.
+    empty = np.isnan(ref["B"])
+    assert np.array_equal(np.isnan(B), empty), (label, int(np.isnan(B).sum()), int(empty.sum()))
+    assert np.all(np.abs(N[empty]) <= 1e-9 * np.maximum(ref["rhoN"][empty], ref["wmin"] ** 3)), label
     keep = ~empty
     e = oest.relative_error(B, ref, norm)[keep]
     en = oest.count_error(N, ref)
@@ -105,6 +107,31 @@ def test_parseval_dc_ring():
     B, N = _run(p, V[None])
     ref = oest.estimate(V, None, edges, 1.0, trips=p.triplets, with_scales=True)
     _check(B[0], N[0], ref, 1.0, label="dc")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
+def test_empty_weighted_triplets(prec):
+    """Hand-built weights (ring 0 weighted only on the v axis, ring 1 only on the u axis)
+    leave plan triplets such as (0, 1, 1) without any weighted triangle: B_t must be NaN on
+    exactly the oracle's empty triplets, in every precision form, and N_t is still reported."""
+    A = _A()
+    n, edges = 16, [1.0, 2.0, 3.1, 4.2, 5.3]
+    g = oplan.signed_index(n)
+    gx, gy = np.meshgrid(g, g)
+    rc = oplan.ring_of_cell(n, edges)
+    rng = np.random.default_rng(11)
+    w = synth.symmetrize(rng.uniform(0.5, 1.5, (n, n)))
+    w[(rc == 0) & (gx != 0)] = 0.0
+    w[(rc == 1) & (gy != 0)] = 0.0
+    V = rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n))
+    P = {"fp32": A.FP32, "bf16x3": A.BF16X3, "fp16x3": A.FP16X3}[prec]
+    p = A.Plan(n, edges, norm=1.0, wmode=A.W_GIVEN, max_batch=2, precision=P).bind()
+    B, N = _run(p, V, w)
+    for b in range(2):
+        ref = oest.estimate(V[b], w, edges, 1.0, wmode=2, trips=p.triplets, with_scales=True)
+        assert np.isnan(ref["B"]).sum() >= 1
+        _check(B[b], N[b], ref, 1.0, tol=TOL if prec == "fp32" else PREC_TOL,
+               label="empty %s [%d]" % (prec, b))
 
 
 def _mwa_inputs(n, batch, cfg, seed0=0):
@@ -238,7 +265,6 @@ def test_argument_errors():
 
 
 # ---- precision form: BF16 / FP16 hi+lo split products on MFMA, FP32 accumulation ----
-PREC_TOL = 1e-4
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
