@@ -30,7 +30,8 @@
  *     triangle, its N_t is rounding noise of an exact zero, and B_t is NaN (N_t is still
  *     reported);
  *   - device pointers are caller-owned and must stay valid until the stream work that
- *     uses them has finished; the library never allocates device memory;
+ *     uses them has finished; the library never allocates device memory (the one static
+ *     array it holds is the scratch of abs_estimate_noalloc);
  *   - every function returns a status code; none aborts or prints.  Launch or device
  *     errors surface as ABS_ERR_DEVICE from the call that saw them or from abs_sync;
  *   - `stream` arguments are hipStream_t values passed as void* (NULL = default stream).
@@ -53,7 +54,8 @@ typedef enum abs_status {
   ABS_ERR_DEVICE = 4,   /* a HIP runtime call or kernel launch failed */
   ABS_ERR_JIT = 5,      /* run-time compilation of the plan's contraction kernel failed */
   ABS_ERR_NOMEM = 6,    /* host allocation failed, or a caller buffer is too small */
-  ABS_ERR_EMPTY = 7     /* no ring triplet contains a closed lattice triangle */
+  ABS_ERR_EMPTY = 7,    /* no ring triplet contains a closed lattice triangle */
+  ABS_ERR_SCRATCH = 8   /* abs_estimate_noalloc: the call needs more than its static scratch */
 } abs_status;
 
 /* precision of the triplet contraction (the ring FFTs are always FP32) */
@@ -199,6 +201,22 @@ abs_status abs_grid(abs_plan_t plan, int64_t nvis, int32_t batch, const double* 
 abs_status abs_estimate(abs_plan_t plan, int32_t batch, int32_t dtype, const void* grids,
                         const float* w, int32_t w_batched, const double* n_given,
                         void* work, size_t work_bytes, double* B, double* N, void* stream);
+
+/* abs_estimate without a caller workspace and without any device allocation, for callers
+ * that cannot allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The arguments are those of abs_estimate minus work / work_bytes; the
+ * workspace is a static device array of 256 MiB (ABS_NOALLOC_SCRATCH_BYTES), one per GPU,
+ * held from the first such call on that GPU until the process ends.  A call whose
+ * workspace (abs_estimate_workspace) exceeds it returns ABS_ERR_SCRATCH and launches
+ * nothing; e.g. one 1024^2 grid with 20 rings and its own weights fits, 1024^2 batches of
+ * more than one do not.  Every call on one GPU shares that GPU's array: calls that overlap
+ * on one GPU (on different streams, or from several threads) race and must be serialised
+ * by the caller.  Nothing in the array needs to start at zero (each call writes what it
+ * reads).  Errors: those of abs_estimate, ABS_ERR_SCRATCH. */
+#define ABS_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+abs_status abs_estimate_noalloc(abs_plan_t plan, int32_t batch, int32_t dtype, const void* grids,
+                                const float* w, int32_t w_batched, const double* n_given,
+                                double* B, double* N, void* stream);
 
 /* Weighted triangle counts N_t (the denominator of Eq. 12 per triangle) for one
  * weight array, for reuse as abs_estimate's n_given.  work: abs_estimate_workspace

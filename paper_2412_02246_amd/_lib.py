@@ -7,7 +7,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libabs.so")
 
-OK, ERR_INVALID, ERR_ALIAS, ERR_UNBOUND, ERR_DEVICE, ERR_JIT, ERR_NOMEM, ERR_EMPTY = range(8)
+OK, ERR_INVALID, ERR_ALIAS, ERR_UNBOUND, ERR_DEVICE, ERR_JIT, ERR_NOMEM, ERR_EMPTY, ERR_SCRATCH = range(9)
 FP32, BF16X3, FP16X3 = 0, 1, 2
 W_UNIT, W_INV_COUNT, W_GIVEN = 0, 1, 2
 C64, C128 = 0, 1
@@ -65,6 +65,7 @@ def lib():
         "abs_grid_workspace": [_P, i64, i32, ctypes.POINTER(sz)],
         "abs_grid": [_P, i64, i32, _P, _P, _P, i32, _P, sz, _P, _P, _P, _P],
         "abs_estimate": [_P, i32, i32, _P, _P, i32, _P, _P, sz, _P, _P, _P],
+        "abs_estimate_noalloc": [_P, i32, i32, _P, _P, i32, _P, _P, _P, _P],
         "abs_counts": [_P, _P, _P, sz, _P, _P],
         "abs_sync": [_P, _P],
         "abs_profile": [_P, i32, _P, _P],

@@ -5,6 +5,7 @@
 //   -> finaliser (FP64 sum over workgroups, per-triangle normalisation, B = S / (A N)).
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -257,24 +258,32 @@ abs_status abs_plan_bind(abs_plan_t p, void* mem, size_t bytes, void* stream) {
   return ABS_OK;
 }
 
-abs_status abs_estimate(abs_plan_t p, int32_t batch, int32_t dtype, const void* grids,
-                        const float* w, int32_t w_batched, const double* n_given, void* work,
-                        size_t work_bytes, double* B, double* N, void* stream) {
+}  // extern "C"
+
+namespace abs_impl {
+
+// Argument checks shared by abs_estimate and abs_estimate_noalloc (everything but the
+// workspace).
+abs_status check_estimate_args(abs_plan_t p, int32_t batch, int32_t dtype, const void* grids,
+                               const float* w, int32_t w_batched, const double* n_given, double* B) {
   if (!p) return ABS_ERR_INVALID;
   abs_status s = ensure_device(p);
   if (s != ABS_OK) return s;
   if (batch < 1 || batch > p->max_batch) return ABS_ERR_INVALID;
   if (dtype != ABS_C64 && dtype != ABS_C128) return ABS_ERR_INVALID;
-  if (!grids || !work || !B) return ABS_ERR_INVALID;
+  if (!grids || !B) return ABS_ERR_INVALID;
   if (!w && p->wmode != ABS_W_UNIT) return ABS_ERR_INVALID;
   if (n_given && w_batched) return ABS_ERR_INVALID;
-  if ((reinterpret_cast<uintptr_t>(grids) | reinterpret_cast<uintptr_t>(work)) & 15) return ABS_ERR_INVALID;
-  const WorkLayout wl = work_layout(p, batch, w_batched, n_given != nullptr);
-  if (work_bytes < wl.total) return ABS_ERR_NOMEM;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (reinterpret_cast<uintptr_t>(grids) & 15) return ABS_ERR_INVALID;
+  return ABS_OK;
+}
+
+// The launches of one estimate on a workspace of at least work_layout(...).total bytes.
+abs_status estimate_on(abs_plan_t p, const WorkLayout& wl, int32_t batch, int32_t dtype, const void* grids,
+                       const float* w, int32_t w_batched, const double* n_given, char* wk, double* B,
+                       double* N, hipStream_t st) {
   (void)hipGetLastError();
-  char* wk = static_cast<char*>(work);
-  s = run_fields_and_contract(p, wl, batch, dtype, grids, w, w_batched, wk, st);
+  abs_status s = run_fields_and_contract(p, wl, batch, dtype, grids, w, w_batched, wk, st);
   if (s != ABS_OK) return s;
   const double* part = reinterpret_cast<const double*>(wk + wl.part);
   const double* part64 = reinterpret_cast<const double*>(wk + wl.part64);
@@ -290,6 +299,59 @@ abs_status abs_estimate(abs_plan_t p, int32_t batch, int32_t dtype, const void* 
                                         pos64, (int)p->ntrip, batch, wl.nisets, n_given, wmin, inv, p->norm,
                                         B, N);
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
+}
+
+// Scratch of the allocation-free entry point: one static array per GPU (each device holds
+// its own copy at its own address until the process ends).  Host code never passes the
+// array's name to a kernel: that names a host-side stand-in.  Its device address is
+// looked up once per device with hipGetSymbolAddress and kept in scratch_ptr.
+constexpr size_t kScratchBytes = ABS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on first use there).
+abs_status scratch_on_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return ABS_ERR_DEVICE;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return ABS_ERR_DEVICE;
+    scratch_ptr[dev] = ptr;
+  }
+  *out = scratch_ptr[dev];
+  return ABS_OK;
+}
+
+}  // namespace abs_impl
+
+extern "C" {
+
+abs_status abs_estimate(abs_plan_t p, int32_t batch, int32_t dtype, const void* grids,
+                        const float* w, int32_t w_batched, const double* n_given, void* work,
+                        size_t work_bytes, double* B, double* N, void* stream) {
+  abs_status s = check_estimate_args(p, batch, dtype, grids, w, w_batched, n_given, B);
+  if (s != ABS_OK) return s;
+  if (!work || (reinterpret_cast<uintptr_t>(work) & 15)) return ABS_ERR_INVALID;
+  const WorkLayout wl = work_layout(p, batch, w_batched, n_given != nullptr);
+  if (work_bytes < wl.total) return ABS_ERR_NOMEM;
+  return estimate_on(p, wl, batch, dtype, grids, w, w_batched, n_given, static_cast<char*>(work), B, N,
+                     static_cast<hipStream_t>(stream));
+}
+
+abs_status abs_estimate_noalloc(abs_plan_t p, int32_t batch, int32_t dtype, const void* grids,
+                                const float* w, int32_t w_batched, const double* n_given, double* B,
+                                double* N, void* stream) {
+  abs_status s = check_estimate_args(p, batch, dtype, grids, w, w_batched, n_given, B);
+  if (s != ABS_OK) return s;
+  const WorkLayout wl = work_layout(p, batch, w_batched, n_given != nullptr);
+  if (wl.total > kScratchBytes) return ABS_ERR_SCRATCH;
+  void* work = nullptr;
+  if ((s = scratch_on_current_device(&work)) != ABS_OK) return s;
+  return estimate_on(p, wl, batch, dtype, grids, w, w_batched, n_given, static_cast<char*>(work), B, N,
+                     static_cast<hipStream_t>(stream));
 }
 
 abs_status abs_counts(abs_plan_t p, const float* w, void* work, size_t work_bytes, double* N,

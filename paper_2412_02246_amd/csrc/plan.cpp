@@ -741,6 +741,8 @@ const char* abs_status_str(abs_status s) {
     case ABS_ERR_JIT: return "run-time compilation of the contraction kernel failed";
     case ABS_ERR_NOMEM: return "out of host memory or caller buffer too small";
     case ABS_ERR_EMPTY: return "no ring triplet contains a closed lattice triangle";
+    case ABS_ERR_SCRATCH:
+      return "the estimate needs more workspace than the 256 MiB static scratch of abs_estimate_noalloc";
   }
   return "unknown status";
 }
