@@ -3,7 +3,13 @@
 One step = gridding of nvis = n^2 visibilities for a batch of realisations of one
 MWA-shaped channel (shared baselines, Eq. 9) followed by the estimator of Eq. (12)
 for the batch (ring FFTs, triplet contraction, normalisation), with the gridded
-counts as shared INV_COUNT weights.  Inputs are resident in HBM before timing.
+counts as INV_COUNT weights: every step recomputes the weight fields and the triangle
+counts N_t from its own gridded counts.  Inputs are resident in HBM before timing.
+
+The default line is the large-ensemble shapes (8192^2 grids, 64 log rings, 15,229
+triplets, realisations in batches of 8) in the plain FP32 form; it also carries, as
+extra keys, the same workload in the BF16x3 precision form, the 1024^2 / 20-ring
+single-channel workload, and the serving form's saturated rate and latencies.
 
 Prints one JSON line: grids/s, bin-triplets/s, the roofline of the dominant kernel
 (the triplet contraction; its duration comes from HIP events recorded by the library
@@ -24,15 +30,20 @@ sys.path.insert(0, ROOT)
 WORKLOADS = {
     # MWA-shaped single channel: 1024^2 complex64, 20 log rings over 46 <= l < 1320
     "mwa1024": dict(n=1024, nbins=20, lmin=46.0, lmax=1320.0, batch=16, cfg=1,
-                    desc="MWA-shaped single channel: 1024x1024 c64 grid, 20 log rings 46<=l<1320, "
-                         "Poisson baseline mask + SNR-5 noise, INV_COUNT weights"),
+                    desc="MWA-shaped single channel: 1024x1024 c64 grids, 20 log rings 46<=l<1320, "
+                         "Poisson-density baselines + SNR-5 noise, INV_COUNT weights, 16 realisations a step"),
     # precision-form shapes: 4096^2, 32 log rings, edges x4
     "mwa4096": dict(n=4096, nbins=32, lmin=4 * 46.0, lmax=4 * 1320.0, batch=16, cfg=2,
-                    desc="MWA-shaped 4096x4096 c64 grid, 32 log rings 4x(46<=l<1320), INV_COUNT weights"),
-    # large ensemble shapes: 8192^2, 64 log rings, edges x8 (realisations in batches of 4)
-    "mwa8192": dict(n=8192, nbins=64, lmin=8 * 46.0, lmax=8 * 1320.0, batch=4, cfg=4,
-                    desc="MWA-shaped 8192x8192 c64 grid, 64 log rings 8x(46<=l<1320), INV_COUNT weights"),
+                    desc="MWA-shaped 4096x4096 c64 grids, 32 log rings 4x(46<=l<1320), INV_COUNT weights, "
+                         "16 realisations a step"),
+    # large ensemble shapes: 8192^2, 64 log rings, edges x8 (realisations in batches of 8)
+    "mwa8192": dict(n=8192, nbins=64, lmin=8 * 46.0, lmax=8 * 1320.0, batch=8, cfg=4,
+                    desc="large ensemble: 8192x8192 c64 grids, 64 log rings 8x(46<=l<1320) (15229 triplets), "
+                         "realisations of one channel, 8 a step, INV_COUNT weights from the gridded counts"),
 }
+DEFAULT_WORKLOAD = "mwa8192"
+
+
 class HipEvents:
     """Raw HIP events (the library records them on the call's stream)."""
 
@@ -63,15 +74,24 @@ class HipEvents:
         self.ev = []
 
 
-PEAK_VALU_FP32 = 78.6e12   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
-PEAK_MFMA_16BIT = 2.5e15   # dense BF16 / FP16 matrix peak
+# MI355X published peaks
+PEAK_FP32_VECTOR = 157.3e12   # FP32 vector (counts packed dual-issue FP32)
+PEAK_VALU_NONPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz: one FP32 FMA a lane
+                               # and clock, the ceiling without packed FP32, which this library
+                               # does not use
+PEAK_MFMA_16BIT = 2.5e15       # dense BF16 / FP16 matrix peak
 PEAK_HBM = 8.0e12
 
 # HBM bytes per launch of the timed contraction kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by a 1 GiB copy (2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE), for the
-# kernel as it stands in this tree (profiles/counters_mwa1024_batch16.md); a workload or
-# precision without an entry reports null.
-MEASURED_TRAFFIC = {("mwa1024", "fp32"): 1348.6e6}
+# kernel as it stands in this tree and the workload's default batch (profiles/counters_mwa8192_batch8_fp32.md); keyed by
+# (workload, precision).  A workload or precision without an entry reports null.
+MEASURED_TRAFFIC = {("mwa8192", "fp32"): 417.4e9}
+
+
+def edges_of(W):
+    nb = W["nbins"]
+    return (W["lmin"] / (2 * np.pi)) * ((W["lmax"] / W["lmin"]) ** (np.arange(nb + 1) / nb))
 
 
 def parse():
@@ -79,25 +99,36 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mwa1024", choices=sorted(WORKLOADS) + ["serve", "copy"])
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + ["serve", "copy"])
     ap.add_argument("--requests", type=int, default=512, help="serve: number of requests")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serve: admission budget")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the workload itself (no precision-form, 1024^2 or serving keys)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
 
-def cpu_baseline(n, edges, trips, uv, vis, norm, budget_s):
-    """The FP64 oracle as it stands (gridding + estimator) on a bounded sample."""
-    from oracle import estimator as oest
-    from oracle import gridding as ogrid
+def _cores():
     try:
         from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        blas = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
-        cores = 1
+        blas = 1
+    try:
+        fft = len(os.sched_getaffinity(0))
+    except Exception:
+        fft = os.cpu_count() or 1
+    return blas, fft
+
+
+def cpu_baseline_full(n, edges, trips, uv, vis, norm, budget_s):
+    """The FP64 oracle as it stands (gridding + estimator) on whole realisations."""
+    from oracle import estimator as oest
+    from oracle import gridding as ogrid
+    blas, fft = _cores()
     done, t0 = 0, time.perf_counter()
     while True:
         g, w, _ = ogrid.grid_visibilities(n, 1.0, uv, vis[done % len(vis)])
@@ -106,9 +137,64 @@ def cpu_baseline(n, edges, trips, uv, vis, norm, budget_s):
         if time.perf_counter() - t0 >= budget_s or done >= 16:
             break
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "grids/s", "cores": int(cores), "kind": "oracle",
-            "sample": "%d realisation(s): FP64 gridding of %d visibilities + estimator "
-                      "(numpy FFT, BLAS %d threads), %.1f s" % (done, len(uv), cores, dt)}
+    return {"value": done / dt, "unit": "grids/s", "cores": int(max(blas, fft)), "kind": "oracle",
+            "sample": "%d whole realisation(s): FP64 gridding of %d visibilities + estimator "
+                      "(scipy FFT on %d threads, BLAS on %d threads), %.1f s" % (done, len(uv), fft, blas, dt)}
+
+
+def cpu_baseline_sampled(n, edges, trips, uv, vis0, norm):
+    """The FP64 oracle as it stands, timed on bounded samples of one realisation and
+    scaled to one whole grid (a whole 8192^2 realisation takes the oracle minutes):
+      gridding   grid_visibilities on 2^21 of the visibilities, minus its cost with none,
+                 scaled by nvis / 2^21, plus that fixed cost;
+      fields     the Hermitian parts of W V and W, and ring_fields (FP64 FFT) of 2 rings
+                 (after one untimed call at the same size), scaled to the 2 x nbins data and
+                 weight fields;
+      sums       triple_sums (chunked FP64 GEMM) of all plan triplets over a slab of 128
+                 rows of fields, scaled by n / 128, twice (numerator and denominator)."""
+    from oracle import estimator as oest
+    from oracle import gridding as ogrid
+    from oracle import plan as oplan
+    blas, fft = _cores()
+    nb = len(edges) - 1
+    nvis = len(uv)
+    S = min(nvis, 1 << 21)
+    T0 = time.perf_counter()
+    t = time.perf_counter()
+    ogrid.grid_visibilities(n, 1.0, uv[:0], vis0[:0])
+    t_fix = time.perf_counter() - t
+    t = time.perf_counter()
+    g, w, _ = ogrid.grid_visibilities(n, 1.0, uv[:S], vis0[:S])
+    t_s = time.perf_counter() - t
+    t_grid = t_fix + max(t_s - t_fix, 0.0) * nvis / S
+    t = time.perf_counter()
+    W = oest.effective_weights(n, w, oest.INV_COUNT)
+    X = oest.hermitian_part(W * g)
+    Y = oest.hermitian_part(W.astype(np.complex128))
+    t_herm = time.perf_counter() - t
+    del Y, g, w
+    rc = oplan.ring_of_cell(n, edges)
+    k = 2
+    ms = np.stack([rc == m for m in (0, nb - 1)][:k])
+    oest.ring_fields(X, ms[:1])          # untimed: FFT plan and thread start-up at this size
+    t = time.perf_counter()
+    F = oest.ring_fields(X, ms)
+    t_ring = (time.perf_counter() - t) / k
+    del X, ms, rc
+    R = 128
+    slab = np.ascontiguousarray(np.concatenate([F[:, :R, :]] * ((nb + k - 1) // k))[:nb])
+    del F
+    t = time.perf_counter()
+    oest.triple_sums(slab, trips)
+    t_sum = time.perf_counter() - t
+    t_total = t_grid + t_herm + t_ring * 2 * nb + 2 * t_sum * (n / R)
+    return {"value": 1.0 / t_total, "unit": "grids/s", "cores": int(max(blas, fft)), "kind": "oracle",
+            "sample": "one realisation in bounded pieces, %.1f s of CPU work, scaled to a whole grid "
+                      "(%.0f s): gridding of %d of %d visibilities (%.2f s, scaled %.1f s); Hermitian parts "
+                      "%.2f s; FP64 FFT of %d ring fields %.2f s each, x %d fields; FP64 GEMM triple sums of "
+                      "all %d triplets over %d of %d rows %.2f s, x %d x 2; scipy FFT on %d threads, BLAS on "
+                      "%d threads" % (time.perf_counter() - T0, t_total, S, nvis, t_s, t_grid, t_herm, k,
+                                      t_ring, 2 * nb, len(trips), R, n, t_sum, n // R, fft, blas)}
 
 
 def copy_probe(a):
@@ -135,38 +221,43 @@ def copy_probe(a):
           flush=True)
 
 
-def serve_bench(a):
-    """Serving form: a Poisson stream of requests, each one channel or one realisation,
-    grid sizes uniform over {512, 1024, 2048, 4096}^2 complex64 with 16..32 log rings
-    (46 <= l < 1320, radii scaled by n/1024); half the requests are realisations sharing
-    their channel's weights (cached triangle counts), half channels with their own.
+def serve_specs(nreq, seed=4242):
+    """The serving stream: grid sizes uniform over {512, 1024, 2048, 4096}^2 with 16..32
+    log rings (46 <= l < 1320, radii scaled by n/1024); half the requests are realisations
+    sharing their channel's weights, half channels with their own."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for _ in range(nreq):
+        n = int(rng.choice([512, 1024, 2048, 4096]))
+        nb = int(rng.integers(16, 33))
+        s = n / 1024.0
+        edges = tuple((46.0 * s / (2 * np.pi)) * (1320.0 / 46.0) ** (np.arange(nb + 1) / nb))
+        specs.append((n, edges, bool(rng.random() < 0.5)))
+    return specs, rng
+
+
+def serve_run(precision, nreq, budget_gib, compiled=None, log=sys.stderr):
+    """Serving form: a Poisson stream of requests, each one channel or one realisation.
     The saturated rate mu is measured first (all requests at t = 0), then streams at
-    rho mu, rho in {0.5, 0.8, 0.95}, report p50/p99 latency and grids/s."""
+    rho mu, rho in {0.5, 0.8, 0.95}, report p50/p99 latency, grids/s and the mean batch."""
     import torch
 
     import paper_2412_02246_amd as A
     from paper_2412_02246_amd.serve import GpuExecutor, Request, Scheduler, latency_stats, run_stream
 
-    rng = np.random.default_rng(4242)
-    sizes = [512, 1024, 2048, 4096]
-    specs = []
-    for k in range(a.requests):
-        n = int(rng.choice(sizes))
-        nb = int(rng.integers(16, 33))
-        s = n / 1024.0
-        edges = tuple((46.0 * s / (2 * np.pi)) * (1320.0 / 46.0) ** (np.arange(nb + 1) / nb))
-        specs.append((n, edges, bool(rng.random() < 0.5)))
-    prec = {"fp32": A.FP32, "bf16x3": A.BF16X3, "fp16x3": A.FP16X3}[a.precision]
+    specs, rng = serve_specs(nreq)
+    prec = {"fp32": A.FP32, "bf16x3": A.BF16X3, "fp16x3": A.FP16X3}[precision]
     slots, max_batch = 4, 8
-    # compile every plan in worker processes before the GPU is touched
-    from paper_2412_02246_amd.jit import compile_parts
     keys = list(dict.fromkeys((n, e) for n, e, _ in specs))
     kw = dict(wmode=A.W_INV_COUNT, precision=prec, max_batch=max_batch)
-    t0 = time.perf_counter()
-    plans = [A.Plan(n, e, **kw) for n, e in keys]
-    compile_parts(plans, [(n, e, kw) for n, e in keys], workers=16)
-    print("serve: %d plans compiled in %.1f s" % (len(plans), time.perf_counter() - t0),
-          file=sys.stderr, flush=True)
+    if compiled is None:
+        from paper_2412_02246_amd.jit import compile_parts
+        t0 = time.perf_counter()
+        plans = [A.Plan(n, e, **kw) for n, e in keys]
+        compile_parts(plans, [(n, e, kw) for n, e in keys], workers=16)
+        print("serve: %d plans compiled in %.1f s" % (len(plans), time.perf_counter() - t0), file=log, flush=True)
+    else:
+        plans = compiled
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     ex = GpuExecutor(A.W_INV_COUNT, precision=prec, max_batch=max_batch, slots=slots)
@@ -177,7 +268,7 @@ def serve_bench(a):
     gen = torch.Generator(device=dev)
     gen.manual_seed(4242)
     pool, chan, own = {}, {}, {}
-    for n in sizes:
+    for n in (512, 1024, 2048, 4096):
         g = torch.arange(n, device=dev)
         g = torch.where(g < n // 2, g, g - n).double()
         r = torch.sqrt(g[:, None] ** 2 + g[None, :] ** 2)
@@ -197,14 +288,13 @@ def serve_bench(a):
                 out.append(Request(k, n, e, grid, own[n][k % 4], None, t))
         return out
 
-    budget = int(a.budget_gib * (1 << 30))
+    budget = int(budget_gib * (1 << 30))
     # warm-up pass (first launches, cached counts), then the saturated rate
     run_stream(Scheduler(ex, budget, max_batch, slots), requests(np.zeros(len(specs)))[:32])
     torch.cuda.synchronize()
-    sat = latency_stats(run_stream(Scheduler(ex, budget, max_batch, slots),
-                                   requests(np.zeros(len(specs)))))
+    sat = latency_stats(run_stream(Scheduler(ex, budget, max_batch, slots), requests(np.zeros(len(specs)))))
     mu = sat["grids_per_s"]
-    print("serve: saturated %.1f grids/s" % mu, file=sys.stderr, flush=True)
+    print("serve %s: saturated %.1f grids/s" % (precision, mu), file=log, flush=True)
     loads = {}
     for rho in (0.5, 0.8, 0.95):
         arr = np.cumsum(rng.exponential(1.0 / (rho * mu), len(specs)))
@@ -213,19 +303,143 @@ def serve_bench(a):
         st["peak_budget_gib"] = sch.peak_used / (1 << 30)
         st["rejected"] = len(sch.rejected)
         loads["rho=%.2f" % rho] = st
-        print("serve: rho %.2f -> %s" % (rho, st), file=sys.stderr, flush=True)
-    out = {
+        print("serve %s: rho %.2f -> %s" % (precision, rho, st), file=log, flush=True)
+    for p in plans:
+        p.close()
+    del ex
+    torch.cuda.empty_cache()
+    return {"saturated": sat, "poisson": loads, "slots": slots, "max_batch": max_batch,
+            "requests": len(specs), "plans": len(keys)}
+
+
+def serve_child(precision, nreq, budget_gib):
+    """Run the serving bench (--workload serve) as a child process and return its
+    measurements; its progress lines are passed on to stderr."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", "serve", "--precision", precision,
+           "--requests", str(nreq), "--budget-gib", str(budget_gib)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    sys.stderr.write(r.stderr)
+    sys.stderr.flush()
+    if r.returncode != 0:
+        raise RuntimeError("serving bench failed (%d)" % r.returncode)
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    res = dict(line["config"])
+    res.pop("workload", None)
+    res["saturated_grids_per_s"] = line["value"]
+    return res
+
+
+def serve_bench(a):
+    out = serve_run(a.precision, a.requests, a.budget_gib)
+    mu = out["saturated"]["grids_per_s"]
+    line = {
         "metric": "bispectrum grids/s at 1 GPU (serving, continuous batching)",
-        "value": mu, "unit": "grids/s", "n_gpus": 1, "steps": len(specs), "warmup": 32,
+        "value": mu, "unit": "grids/s", "n_gpus": 1, "steps": a.requests, "warmup": 32,
         "ms_per_step": 1e3 / mu, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16x3": "bf16x3 (f32 acc)", "fp16x3": "fp16x3 (f32 acc)"}[a.precision],
         "data": "synthetic",
         "config": {"workload": "serving: %d requests, n in {512,1024,2048,4096}, 16-32 log rings, "
                                "50%% shared-mask realisations / 50%% channels, budget %.0f GiB"
-                               % (len(specs), a.budget_gib),
-                   "slots": slots, "max_batch": max_batch, "saturated": sat, "poisson": loads},
+                               % (a.requests, a.budget_gib), **out},
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(line), flush=True)
+
+
+def measure(name, precision, plan, uv_d, vis_d, steps, warmup, log=sys.stderr):
+    """Time `steps` gridding + estimator steps of one workload after `warmup` untimed ones;
+    the contraction's launches are bracketed by HIP events on every timed step, and a few
+    extra steps carry events around the gridding, column-pass and row-pass stages."""
+    import torch
+
+    import paper_2412_02246_amd as A
+    W = WORKLOADS[name]
+    n, nb = W["n"], W["nbins"]
+    batch = vis_d.shape[0]
+    nvis = uv_d.shape[0]
+
+    def step():
+        g, w, _ = plan.grid(uv_d, vis_d)
+        return plan.estimate(g, w)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    L = A._lib
+    ev = HipEvents(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        L.lib().abs_profile(plan.handle, L.STAGE_CONTRACT, *ev.pair(k))
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    L.lib().abs_profile(plan.handle, L.STAGE_CONTRACT, None, None)
+    con_ms = float(np.mean([ev.elapsed_ms(k) for k in range(steps)]))
+    ev.close()
+    ms = 1e3 * dt / steps
+    grids_s = batch * steps / dt
+    print("bench: %s %s %.3f ms/step, %.2f grids/s, contraction %.3f ms" % (name, precision, ms, grids_s, con_ms),
+          file=log, flush=True)
+    nsets = batch   # the contraction launch timed is the data-set one (the weight set runs in FP64)
+    # algorithmic flops per pixel: two per triplet (product with the pair, add) plus the
+    # pair products, counted for the orientation with the fewest distinct pairs ((i, j) or
+    # (j, k) of i <= j <= k)
+    ijk = np.asarray(plan.triplets).reshape(-1, 3)
+    pairs = min(len({(int(x[0]), int(x[1])) for x in ijk}), len({(int(x[1]), int(x[2])) for x in ijk}))
+    flops = float(nsets) * n * n * (pairs + 2 * plan.ntrip)
+    achieved = flops / (con_ms * 1e-3)
+    traffic = MEASURED_TRAFFIC.get((name, precision)) if batch == W["batch"] else None
+    if precision == "fp32":
+        roof = {"kernel": "abs_contract (plan-specialised FP32 triplet contraction)", "bound": "alu",
+                "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic, "avg_ms": con_ms,
+                "flops_per_launch": flops,
+                "peak_nonpacked_valu": PEAK_VALU_NONPACKED / 1e12,
+                "frac_nonpacked_valu": achieved / PEAK_VALU_NONPACKED}
+    else:
+        issued = float(nsets) * n * n * plan.mfma_tiles * 3 * 512   # 3 split MFMAs per tile
+        roof = {"kernel": "mfma_contract_kernel (%s triplet contraction)" % precision, "bound": "mfma",
+                "achieved": achieved / 1e12, "peak": PEAK_MFMA_16BIT / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_MFMA_16BIT, "traffic": traffic, "avg_ms": con_ms,
+                "flops_per_launch": flops,
+                "mfma_issued_tflops": issued / (con_ms * 1e-3) / 1e12,
+                "mfma_issued_frac": issued / (con_ms * 1e-3) / PEAK_MFMA_16BIT}
+    # HBM fraction of the gridding and FFT stages, from HIP events the library records
+    # around each stage on a few extra (untimed) steps; algorithmic bytes per step:
+    #   gridding: uv read once (16 B a visibility), values read (8 B a visibility and
+    #             realisation), grids written (8 B a cell and realisation), counts (4 B a cell)
+    #   column pass: the pruned intermediate written (8 B x n x ncols a set)
+    #   row pass: that intermediate read and the FP32 fields written (4 B x nbins x n^2 a set)
+    stages = {}
+    nprof = 3
+    evs = {st: HipEvents(nprof) for st in (L.STAGE_GRID, L.STAGE_COLPASS, L.STAGE_ROWPASS)}
+    for k in range(nprof):
+        for st, e in evs.items():
+            L.lib().abs_profile(plan.handle, st, *e.pair(k))
+        step()
+    torch.cuda.synchronize()
+    zbytes = 8.0 * n * plan.ncols * batch
+    alg = {L.STAGE_GRID: 16.0 * nvis + batch * (8.0 * nvis + 8.0 * n * n) + 4.0 * n * n,
+           L.STAGE_COLPASS: zbytes,
+           L.STAGE_ROWPASS: zbytes + 4.0 * nb * n * n * batch}
+    tot_b = tot_ms = 0.0
+    for st, sname in ((L.STAGE_GRID, "gridding"), (L.STAGE_COLPASS, "column_pass"), (L.STAGE_ROWPASS, "row_pass")):
+        L.lib().abs_profile(plan.handle, st, None, None)
+        st_ms = float(np.mean([evs[st].elapsed_ms(k) for k in range(nprof)]))
+        evs[st].close()
+        stages[sname] = {"ms": st_ms, "alg_bytes": alg[st], "gb_per_s": alg[st] / (st_ms * 1e-3) / 1e9,
+                         "frac_hbm": alg[st] / (st_ms * 1e-3) / PEAK_HBM}
+        tot_b += alg[st]
+        tot_ms += st_ms
+    stages["gridding_and_fft"] = {"ms": tot_ms, "alg_bytes": tot_b, "gb_per_s": tot_b / (tot_ms * 1e-3) / 1e9,
+                                  "frac_hbm": tot_b / (tot_ms * 1e-3) / PEAK_HBM}
+    return {"grids_per_s": grids_s, "ms_per_step": ms, "grids_per_step": batch,
+            "bin_triplets_per_s": grids_s * plan.ntrip, "roofline": roof, "stages_hbm": stages}
+
+
+def _dtype(precision):
+    return {"fp32": "f32", "bf16x3": "bf16x3 (f32 acc)", "fp16x3": "fp16x3 (f32 acc)"}[precision]
 
 
 def main():
@@ -242,119 +456,101 @@ def main():
 
     import paper_2412_02246_amd as A
     import synth
+    from paper_2412_02246_amd.jit import compile_parts
 
-    W = WORKLOADS[a.workload]
+    P = {"fp32": A.FP32, "bf16x3": A.BF16X3, "fp16x3": A.FP16X3}
+    name = a.workload
+    W = WORKLOADS[name]
     n, nb, batch = W["n"], W["nbins"], (a.batch or W["batch"])
-    edges = (W["lmin"] / (2 * np.pi)) * ((W["lmax"] / W["lmin"]) ** (np.arange(nb + 1) / nb))
+    edges = edges_of(W)
     nvis = n * n
-    print("bench: workload %s n=%d rings=%d batch=%d nvis=%d" % (a.workload, n, nb, batch, nvis),
+    extras = not a.no_extras and name == DEFAULT_WORKLOAD and not a.batch
+    print("bench: workload %s n=%d rings=%d batch=%d nvis=%d precision %s" % (name, n, nb, batch, nvis, a.precision),
           file=sys.stderr, flush=True)
-    prec = {"fp32": A.FP32, "bf16x3": A.BF16X3, "fp16x3": A.FP16X3}[a.precision]
-    # the plan's contraction code is compiled in worker processes before this process
+    # every plan's contraction code is compiled in worker processes before this process
     # touches the GPU
+    jobs = [(name, a.precision, batch)]
+    if extras:
+        jobs += [(name, "bf16x3", batch), ("mwa1024", "fp32", WORKLOADS["mwa1024"]["batch"])]
     t0 = time.perf_counter()
-    plan = A.Plan(n, edges, wmode=A.W_INV_COUNT, max_batch=batch, precision=prec)
-    plan.compile(workers=16)
-    print("bench: plan ntrip=%d npairs=%d, %d code parts compiled in %.1f s" %
-          (plan.ntrip, plan.npairs, plan.jit_parts, time.perf_counter() - t0), file=sys.stderr, flush=True)
-    uv, vis = synth.mwa_visibilities(n, nvis, edges[-1], synth.seed_for(W["cfg"], 0), batch=batch)
+    plans, specs = [], []
+    for wname, prec, b in jobs:
+        Wj = WORKLOADS[wname]
+        kw = dict(wmode=A.W_INV_COUNT, max_batch=b, precision=P[prec])
+        plans.append(A.Plan(Wj["n"], edges_of(Wj), **kw))
+        specs.append((Wj["n"], tuple(edges_of(Wj)), kw))
+    compile_parts(plans, specs, workers=16)
+    print("bench: %d plans (%d code parts) compiled in %.1f s" %
+          (len(plans), sum(p.jit_parts for p in plans), time.perf_counter() - t0), file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    plan.bind()
-    print("bench: inputs generated", file=sys.stderr, flush=True)
-    uv_d = torch.from_numpy(uv).to(dev)
-    vis_d = torch.from_numpy(vis).to(dev)
 
-    def step():
-        g, w, _ = plan.grid(uv_d, vis_d)
-        return plan.estimate(g, w)
+    def inputs(wname, b):
+        Wj = WORKLOADS[wname]
+        t = time.perf_counter()
+        uv_d, vis_d = synth.mwa_visibilities_device(Wj["n"], Wj["n"] ** 2, edges_of(Wj)[-1],
+                                                    synth.seed_for(Wj["cfg"], 0), batch=b, device=dev)
+        torch.cuda.synchronize()
+        print("bench: %s inputs drawn on the device in %.1f s" % (wname, time.perf_counter() - t),
+              file=sys.stderr, flush=True)
+        return uv_d, vis_d
 
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    L = A._lib
-    ev = HipEvents(a.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(a.steps):
-        L.lib().abs_profile(plan.handle, L.STAGE_CONTRACT, *ev.pair(k))
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    L.lib().abs_profile(plan.handle, L.STAGE_CONTRACT, None, None)
-    con_ms = float(np.mean([ev.elapsed_ms(k) for k in range(a.steps)]))
-    ev.close()
-    ms = 1e3 * dt / a.steps
-    grids_s = batch * a.steps / dt
-    nsets = batch  # the contraction launch timed is the data-set one (the weight set runs in FP64)
-    # algorithmic flops per pixel: two per triplet (product with the pair, add) plus the
-    # pair products, counted for the orientation with the fewest distinct pairs ((i, j) or
-    # (j, k) of i <= j <= k)
-    ijk = np.asarray(plan.triplets).reshape(-1, 3)
-    pairs = min(len({(int(x[0]), int(x[1])) for x in ijk}), len({(int(x[1]), int(x[2])) for x in ijk}))
-    flops = float(nsets) * n * n * (pairs + 2 * plan.ntrip)
-    achieved = flops / (con_ms * 1e-3)
-    if a.precision == "fp32":
-        roof = {"kernel": "abs_contract (plan-specialised FP32 triplet contraction)", "bound": "alu",
-                "achieved": achieved / 1e12, "peak": PEAK_VALU_FP32 / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_VALU_FP32, "avg_ms": con_ms,
-                "traffic": MEASURED_TRAFFIC.get((a.workload, a.precision)) if batch == W["batch"] else None,
-                "flops_per_launch": flops}
-    else:
-        issued = float(nsets) * n * n * plan.mfma_tiles * 3 * 512   # 3 split MFMAs per tile
-        roof = {"kernel": "mfma_contract_kernel (%s triplet contraction)" % a.precision, "bound": "mfma",
-                "achieved": achieved / 1e12, "peak": PEAK_MFMA_16BIT / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_MFMA_16BIT, "avg_ms": con_ms,
-                "traffic": MEASURED_TRAFFIC.get((a.workload, a.precision)) if batch == W["batch"] else None,
-                "flops_per_launch": flops,
-                "mfma_issued_tflops": issued / (con_ms * 1e-3) / 1e12,
-                "mfma_issued_frac": issued / (con_ms * 1e-3) / PEAK_MFMA_16BIT}
-    # HBM fraction of the gridding and FFT stages, from HIP events the library records
-    # around each stage on a few extra (untimed) steps; algorithmic bytes per step:
-    #   gridding: uv read once (16 B a visibility), values read (8 B a visibility and
-    #             realisation), grids written (8 B a cell and realisation), counts (4 B a cell)
-    #   column pass: the pruned intermediate written (8 B x n x ncols a set)
-    #   row pass: that intermediate read and the FP32 fields written (4 B x nbins x n^2 a set)
-    stages = {}
-    nprof = 5
-    evs = {st: HipEvents(nprof) for st in (L.STAGE_GRID, L.STAGE_COLPASS, L.STAGE_ROWPASS)}
-    for k in range(nprof):
-        for st, e in evs.items():
-            L.lib().abs_profile(plan.handle, st, *e.pair(k))
-        step()
-    torch.cuda.synchronize()
-    zbytes = 8.0 * n * plan.ncols * batch
-    alg = {L.STAGE_GRID: 16.0 * nvis + batch * (8.0 * nvis + 8.0 * n * n) + 4.0 * n * n,
-           L.STAGE_COLPASS: zbytes,
-           L.STAGE_ROWPASS: zbytes + 4.0 * nb * n * n * batch}
-    tot_b = tot_ms = 0.0
-    for st, name in ((L.STAGE_GRID, "gridding"), (L.STAGE_COLPASS, "column_pass"), (L.STAGE_ROWPASS, "row_pass")):
-        L.lib().abs_profile(plan.handle, st, None, None)
-        st_ms = float(np.mean([evs[st].elapsed_ms(k) for k in range(nprof)]))
-        evs[st].close()
-        stages[name] = {"ms": st_ms, "alg_bytes": alg[st], "gb_per_s": alg[st] / (st_ms * 1e-3) / 1e9,
-                        "frac_hbm": alg[st] / (st_ms * 1e-3) / PEAK_HBM}
-        tot_b += alg[st]
-        tot_ms += st_ms
-    stages["gridding_and_fft"] = {"ms": tot_ms, "alg_bytes": tot_b, "gb_per_s": tot_b / (tot_ms * 1e-3) / 1e9,
-                                  "frac_hbm": tot_b / (tot_ms * 1e-3) / PEAK_HBM}
+    uv_d, vis_d = inputs(name, batch)
+    main_plan = plans[0].bind()
+    res = measure(name, a.precision, main_plan, uv_d, vis_d, a.steps, a.warmup)
+    ntrip = int(main_plan.ntrip)
+    main_plan.close()
+    main_plan._work = None
+    torch.cuda.empty_cache()
     out = {
         "metric": "bispectrum grids/s at 1 GPU (gridding + estimator)",
-        "value": grids_s, "unit": "grids/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16x3": "bf16x3 (f32 acc)", "fp16x3": "fp16x3 (f32 acc)"}[a.precision],
-        "data": "synthetic",
+        "value": res["grids_per_s"], "unit": "grids/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": _dtype(a.precision), "data": "synthetic",
         "config": {"workload": W["desc"], "n": n, "nbins": nb, "grids_per_step": batch,
-                   "nvis_per_grid": nvis, "ntrip": int(plan.ntrip), "precision": a.precision,
-                   "bin_triplets_per_s": grids_s * plan.ntrip, "parallelism": "1 GPU"},
-        "roofline": roof,
-        "stages_hbm": stages,
+                   "nvis_per_grid": nvis, "ntrip": ntrip, "precision": a.precision,
+                   "bin_triplets_per_s": res["bin_triplets_per_s"], "parallelism": "1 GPU"},
+        "roofline": res["roofline"],
+        "stages_hbm": res["stages_hbm"],
     }
+    if extras:
+        p16 = plans[1].bind()
+        r16 = measure(name, "bf16x3", p16, uv_d, vis_d, a.steps, a.warmup)
+        p16.close()
+        p16._work = None
+        torch.cuda.empty_cache()
+        r16["speedup_vs_fp32"] = r16["grids_per_s"] / res["grids_per_s"]
+        out["precision_form_bf16x3"] = r16
+    uv_h = vis_h = None
     if not a.no_cpu:
-        e_sample = min(batch, 2)
-        out["cpu_baseline"] = cpu_baseline(n, edges, plan.triplets, uv, vis[:e_sample], plan.norm,
-                                           a.cpu_seconds)
+        uv_h = uv_d.cpu().numpy()
+        vis_h = vis_d[:1].cpu().numpy()
+    del uv_d, vis_d
+    torch.cuda.empty_cache()
+    if extras:
+        uv1, vis1 = inputs("mwa1024", WORKLOADS["mwa1024"]["batch"])
+        p1 = plans[2].bind()
+        r1 = measure("mwa1024", "fp32", p1, uv1, vis1, a.steps, a.warmup)
+        r1["workload"] = WORKLOADS["mwa1024"]["desc"]
+        p1.close()
+        del uv1, vis1
+        torch.cuda.empty_cache()
+        out["mwa1024_fp32"] = r1
+        # the serving form in a process of its own (as a server would run), one per precision
+        out["serving"] = {prec: serve_child(prec, a.requests, a.budget_gib) for prec in ("fp32", "bf16x3")}
+    if not a.no_cpu:
+        from oracle import plan as oplan   # noqa: F401  (oracle import only for the baseline)
+        trips = A.Plan(n, edges).triplets
+        if n <= 2048:
+            out["cpu_baseline"] = cpu_baseline_full(n, edges, trips, uv_h, vis_h, out_norm(A, n, edges),
+                                                    a.cpu_seconds)
+        else:
+            out["cpu_baseline"] = cpu_baseline_sampled(n, edges, trips, uv_h, vis_h[0], out_norm(A, n, edges))
     print(json.dumps(out), flush=True)
+
+
+def out_norm(A, n, edges):
+    return A.Plan(n, edges).norm
 
 
 if __name__ == "__main__":

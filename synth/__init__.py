@@ -147,3 +147,49 @@ def mwa_visibilities(n, nvis, rmax, seed, batch=1, du=1.0, f_ng=0.17, U0=None, s
         noise = (rng.standard_normal(nvis) + 1j * rng.standard_normal(nvis)) * (amp / np.sqrt(2.0))
         vis[b] = (S[gy, gx] + noise).astype(np.complex64)
     return uv, vis
+
+
+def mwa_visibilities_device(n, nvis, rmax, seed, batch=1, du=1.0, f_ng=0.17, U0=None, snr=5.0,
+                            device="cuda"):
+    """The recipe of ``mwa_visibilities`` drawn with torch on a device (for workloads too
+    large to draw on the host in reasonable time): baselines with radius density
+    proportional to r exp(-r / U0) on [0, rmax) (a gamma(2) radius, the sum of two
+    exponentials, redrawn where it falls outside) and uniform angle; per realisation a
+    Gaussian sky with the paper's C_l, the local quadratic term with f = f_NG / sigma_T,
+    sampled at each baseline's nearest cell, plus complex thermal noise at amplitude SNR
+    ``snr``.  Seeded by a torch generator on the device; the draws differ from the numpy
+    recipe's.  Returns (uv float64 [nvis][2], vis complex64 [batch][nvis]) on the device."""
+    import torch
+    dev = torch.device(device)
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(seed))
+    U0 = n / 8.0 if U0 is None else U0
+    f64 = torch.float64
+    r = torch.empty(nvis, dtype=f64, device=dev)
+    todo = torch.arange(nvis, device=dev)
+    while todo.numel():
+        e = torch.empty((2, todo.numel()), dtype=f64, device=dev).exponential_(1.0, generator=g)
+        c = U0 * (e[0] + e[1])
+        ok = c < rmax
+        r[todo[ok]] = c[ok]
+        todo = todo[~ok]
+    phi = torch.rand(nvis, dtype=f64, device=dev, generator=g) * (2.0 * np.pi)
+    uv = torch.stack([r * torch.cos(phi), r * torch.sin(phi)], dim=1) * du
+    del r, phi, todo
+    C = torch.from_numpy(paper_spectrum(n, du)).to(dev)
+    var = C.sum() / n ** 2
+    f = f_ng / float(torch.sqrt(var))
+    gx = torch.remainder(torch.round(uv[:, 0] / du).long(), n)
+    gy = torch.remainder(torch.round(uv[:, 1] / du).long(), n)
+    lin = gy * n + gx
+    amp = (torch.sqrt(n ** 2 * C.reshape(-1)[lin]) / snr / np.sqrt(2.0)).float()
+    sq = torch.sqrt(C)
+    vis = torch.empty((batch, nvis), dtype=torch.complex64, device=dev)
+    for b in range(batch):
+        white = torch.randn((n, n), dtype=f64, device=dev, generator=g)
+        phi_s = torch.fft.ifft2(torch.fft.fft2(white) * sq).real
+        S = torch.fft.fft2(phi_s + f * (phi_s * phi_s - var)).reshape(-1)
+        noise = torch.randn((2, nvis), dtype=torch.float32, device=dev, generator=g) * amp
+        vis[b] = S[lin].to(torch.complex64) + torch.complex(noise[0], noise[1])
+        del white, phi_s, S, noise
+    return uv.contiguous(), vis
