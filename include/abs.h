@@ -99,6 +99,14 @@ typedef struct abs_plan_info {
   double norm;          /* the A actually used                                        */
   int64_t mfma_tiles;   /* 16 x 16 output tiles of the precision-form contraction     */
   int32_t jit_parts;    /* separately compiled pieces of the contraction code         */
+  /* code variants the plan selected (reported for tests and tuning):                  */
+  int32_t contract_parts;  /* code parts of the FP32 data kernel (0: precision form)   */
+  int32_t contract_jk;     /* 1: triplets formed as (D_j D_k) D_i, 0: as (D_i D_j) D_k */
+  int32_t contract_block;  /* triplet order in blocks of this many j (0: none)         */
+  int32_t contract_waves;  /* waves per workgroup (triplet groups of one slice)        */
+  int32_t weight_parts, weight_jk, weight_block, weight_waves;  /* same, FP64 kernel  */
+  int32_t mfma_tiles_per_wave;  /* precision form: output tiles a wave owns (2 or 12)  */
+  int32_t mfma_depth;           /* precision form: chunks of loads in flight (1 or 4)  */
 } abs_plan_info;
 
 /* Build a plan on the host: rings (Sec. 2), the triplet list with an exact lattice

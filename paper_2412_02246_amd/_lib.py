@@ -28,7 +28,12 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nbins", ctypes.c_int32), ("ntrip", ctypes.c_int64),
                 ("npairs", ctypes.c_int64), ("ncols", ctypes.c_int64),
                 ("plan_bytes", ctypes.c_int64), ("norm", ctypes.c_double),
-                ("mfma_tiles", ctypes.c_int64), ("jit_parts", ctypes.c_int32)]
+                ("mfma_tiles", ctypes.c_int64), ("jit_parts", ctypes.c_int32),
+                ("contract_parts", ctypes.c_int32), ("contract_jk", ctypes.c_int32),
+                ("contract_block", ctypes.c_int32), ("contract_waves", ctypes.c_int32),
+                ("weight_parts", ctypes.c_int32), ("weight_jk", ctypes.c_int32),
+                ("weight_block", ctypes.c_int32), ("weight_waves", ctypes.c_int32),
+                ("mfma_tiles_per_wave", ctypes.c_int32), ("mfma_depth", ctypes.c_int32)]
 
 
 class AbsError(RuntimeError):

@@ -97,10 +97,13 @@ struct abs_plan_s {
   std::vector<int> wave_tiles;   // 2 per wave: first tile, count
   int mfma_groups = 0;           // workgroups (of 8 waves) per pixel block and set
   int mfma_tpw = 0;              // tiles per wave of the kernel variant the plan uses
+  int mfma_depth = 1;            // chunks of loads in flight in that variant
   // contraction kernel (compiled at run time for this triplet list)
   int ngroups = 0;               // wave groups of the FP32 kernel; one wave per group
   int ngroups64 = 0;             // wave groups of the FP64 kernel (weight fields)
   int waves = 4, waves64 = 4;    // waves (groups) per workgroup of the two kernels
+  bool jk32 = false, jk64 = false;   // triplets formed as (D_j D_k) D_i (else (D_i D_j) D_k)
+  int block32 = 0, block64 = 0;      // triplet order in blocks of this many j (0: none)
   std::vector<int> pos32, pos64; // position of each triplet in the kernels' triplet orders
   int pix_per_block = 0;         // pixels per contraction workgroup (data sets)
   int nblk = 0;                  // contraction pixel blocks per data set

@@ -3,7 +3,7 @@
 // For a chunk of K pixels the sums S_(ij)k = sum_theta P_ij(theta) D_k(theta), with pair
 // products P_ij = D_i D_j, form a (pairs x K) by (K x rings) matrix product.  Both
 // operands are split into two 16-bit halves, x = hi + lo (BF16, or FP16 after scaling every
-// ring by a power of two so its largest value is below 1), and each 16 x 16 output tile
+// ring by a power of two so that its largest |value| lies in [64, 128)), and each 16 x 16 output tile
 // accumulates hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_{bf16,f16} in FP32; the lo*lo term
 // is below the split's own rounding.  Each chunk's products start from zero and are then
 // added to the tile's running FP32 sum (long FP32 accumulation chains, not the split,
@@ -329,15 +329,17 @@ hipError_t launch_mfma_contract(const abs_plan_s* p, const float* F, long long f
   const size_t lds = mfma_lds_bytes(p->nb);
   const dim3 grid((unsigned)p->nblk, (unsigned)nsets, (unsigned)p->mfma_groups);
   const long long npix = (long long)p->n * p->n;
-  // plans of at most 32 rings: four chunks in flight (their work per chunk is short);
-  // larger plans: one, which keeps the registers for the tiles
+  // the variant the plan chose (mfma_tpw, mfma_depth): small plans two tiles a wave; up
+  // to 32 rings four chunks in flight; larger plans one
   const bool f16 = p->precision == ABS_FP16X3;
-  auto k = f16 ? (p->mfma_tpw == kSmallTilesPerWave ? mfma_contract_kernel<true, 32, 1, kSmallTilesPerWave>
-                  : p->nb <= 32   ? mfma_contract_kernel<true, 32, 4, kTilesPerWave>
-                                  : mfma_contract_kernel<true, kMaxBins, 1, kTilesPerWave>)
-               : (p->mfma_tpw == kSmallTilesPerWave ? mfma_contract_kernel<false, 32, 1, kSmallTilesPerWave>
-                  : p->nb <= 32   ? mfma_contract_kernel<false, 32, 4, kTilesPerWave>
-                                  : mfma_contract_kernel<false, kMaxBins, 1, kTilesPerWave>);
+  const bool small = p->mfma_tpw == kSmallTilesPerWave, deep = p->mfma_depth == 4;
+  if (!small && p->nb > 32 && deep) return hipErrorInvalidValue;
+  auto k = f16 ? (small  ? mfma_contract_kernel<true, 32, 1, kSmallTilesPerWave>
+                  : deep ? mfma_contract_kernel<true, 32, 4, kTilesPerWave>
+                         : mfma_contract_kernel<true, kMaxBins, 1, kTilesPerWave>)
+               : (small  ? mfma_contract_kernel<false, 32, 1, kSmallTilesPerWave>
+                  : deep ? mfma_contract_kernel<false, 32, 4, kTilesPerWave>
+                         : mfma_contract_kernel<false, kMaxBins, 1, kTilesPerWave>);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

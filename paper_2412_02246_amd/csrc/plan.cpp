@@ -271,6 +271,7 @@ struct KernelOrder {
   std::vector<int> ord, start;
   int waves = 4;
   bool jk = false;
+  int block = 0;    // blocks of this many consecutive j (0: none)
 };
 constexpr int64_t kStagedRingCost = 16;
 KernelOrder choose_order(const abs_plan_s* p, int rw) {
@@ -289,6 +290,7 @@ KernelOrder choose_order(const abs_plan_s* p, int rw) {
     for (int B : {0, 4, 8, 16}) {
       KernelOrder o;
       o.jk = jk;
+      o.block = B;
       o.ord = base;
       if (B > 0)
         std::stable_sort(o.ord.begin(), o.ord.end(),
@@ -487,6 +489,10 @@ bool build_jit_source(abs_plan_s* p) {
   p->ngroups64 = (int)g64.size() - 1;
   p->waves = w32;
   p->waves64 = w64;
+  p->jk32 = o32.jk;
+  p->jk64 = o64.jk;
+  p->block32 = o32.block;
+  p->block64 = o64.block;
   // partial sums are written in kernel order: position of every triplet in each order
   p->pos32.assign(p->ntrip, 0);
   p->pos64.assign(p->ntrip, 0);
@@ -698,8 +704,12 @@ void build_mfma_tables(abs_plan_s* p) {
   int waves = 8;
   if (nb <= 32 && deal(8, kSmallTilesPerWave)) {
     p->mfma_tpw = kSmallTilesPerWave;
+    p->mfma_depth = 1;
   } else {
     p->mfma_tpw = kTilesPerWave;
+    // plans of at most 32 rings keep four chunks of loads in flight (their work per chunk
+    // is short); larger plans one, which keeps the registers for the tiles
+    p->mfma_depth = nb <= 32 ? 4 : 1;
     waves = std::max(8, (T + kTilesPerWave - 1) / kTilesPerWave);
     waves = (waves + 7) / 8 * 8;
     while (!deal(waves, kTilesPerWave)) waves += 8;
@@ -931,6 +941,16 @@ abs_status abs_plan_info_get(abs_plan_t p, abs_plan_info* o) {
   o->norm = p->norm;
   o->mfma_tiles = (int64_t)p->mt_ptile.size();
   o->jit_parts = (int32_t)p->parts.size();
+  o->contract_parts = o->weight_parts = 0;
+  for (const JitPart& q : p->parts) ++(q.kind == 0 ? o->contract_parts : o->weight_parts);
+  o->contract_jk = p->jk32 ? 1 : 0;
+  o->contract_block = p->block32;
+  o->contract_waves = p->waves;
+  o->weight_jk = p->jk64 ? 1 : 0;
+  o->weight_block = p->block64;
+  o->weight_waves = p->waves64;
+  o->mfma_tiles_per_wave = p->mfma_tpw;
+  o->mfma_depth = p->mfma_depth;
   return ABS_OK;
 }
 

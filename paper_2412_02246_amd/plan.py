@@ -53,6 +53,12 @@ class Plan:
         self.plan_bytes, self.norm = info.plan_bytes, info.norm
         self.mfma_tiles = info.mfma_tiles
         self.jit_parts = info.jit_parts
+        # code variants the plan selected: {"contract": (parts, jk, block, waves),
+        # "weight": (parts, jk, block, waves), "mfma": (tiles per wave, depth)}
+        self.variants = {
+            "contract": (info.contract_parts, info.contract_jk, info.contract_block, info.contract_waves),
+            "weight": (info.weight_parts, info.weight_jk, info.weight_block, info.weight_waves),
+            "mfma": (info.mfma_tiles_per_wave, info.mfma_depth)}
         self.precision = int(precision)
         self.wmode, self.max_batch = int(wmode), int(max_batch)
         ijk = np.zeros((self.ntrip, 3), np.int32)

@@ -138,3 +138,38 @@ def test_jit_parts_code_roundtrip_and_parallel_compile():
     w = A.Plan(n, e)
     compile_parts([w], [w._spec], workers=2)
     assert [w.code(k) for k in range(w.jit_parts)] == codes
+
+
+def test_code_variants_selected_by_each_plan():
+    """Pins which contraction variant every test plan selects (the GPU variant tests compare
+    each of them with the oracle on every triplet)."""
+    from variant_plans import PLANS, VARIANTS
+    A = _A()
+    seen = {"contract": set(), "weight": set(), "mfma": set()}
+    for name, (n, e) in PLANS.items():
+        p = A.Plan(n, e)
+        q = A.Plan(n, e, precision=A.BF16X3)
+        got = dict(contract=p.variants["contract"], weight=p.variants["weight"], mfma=q.variants["mfma"])
+        assert got == VARIANTS[name], (name, got)
+        assert q.variants["contract"][0] == 0           # the precision form has no FP32 kernel
+        assert q.variants["weight"] == p.variants["weight"]
+        for k in seen:
+            seen[k].add(got[k][1:] if k != "mfma" else got[k])
+    # every order (jk plain, ij plain, ij in blocks of 4 / 8 / 16), both workgroup widths,
+    # multi-part code and the three precision-form variants occur
+    assert {(1, 0, 4), (1, 0, 8), (0, 0, 8), (0, 16, 8)} <= seen["contract"]
+    assert {(1, 0, 4), (1, 0, 8), (0, 0, 8), (0, 4, 8), (0, 8, 8), (0, 16, 8)} <= seen["weight"]
+    assert seen["mfma"] == {(2, 1), (12, 4), (12, 1)}
+    assert any(VARIANTS[k]["contract"][0] > 1 for k in VARIANTS)
+    assert any(VARIANTS[k]["weight"][0] > 2 for k in VARIANTS)
+
+
+def test_4096_plan_triplets_match_oracle():
+    """The 4096^2 / 32-ring plan's triplet list (2309 of 5984 combinations) equals the
+    oracle's exact FFT lattice counts."""
+    A = _A()
+    e = oplan.log_edges(4 * 46 / (2 * np.pi), 4 * 1320 / (2 * np.pi), 32)
+    p = A.Plan(4096, e)
+    trips, counts = oplan.plan_triplets(4096, e)
+    assert np.array_equal(p.triplets, trips)
+    assert p.ntrip == 2309 and np.all(counts >= 1)
