@@ -17,7 +17,9 @@ estimator for radio-interferometric data":
 * ``gridding``  -- nearest-cell gridding, Eq. (9).
 * ``theory``    -- the closed-form local-quadratic bispectrum, Eq. (14) and its
                    discretely-sampled average, plus the paper's constants.
+* ``analysis``  -- the (ell1, mu, t) re-binning of the triplet estimates, ensemble mean
+                   and sigma, and the deviation metrics of Secs. 3-4.
 
 Parity status per function is stated in each module header.
 """
-from . import plan, estimator, brute, gridding, theory  # noqa: F401
+from . import plan, estimator, brute, gridding, theory, analysis  # noqa: F401
