@@ -232,6 +232,65 @@ abs_status abs_estimate_noalloc(abs_plan_t plan, int32_t batch, int32_t dtype, c
 abs_status abs_counts(abs_plan_t plan, const float* w, void* work, size_t work_bytes,
                       double* N, void* stream);
 
+/* ---- after the estimator: re-binning, ensemble statistics, model prediction ---------
+ * Secs. 3-4: the triplet estimates are averaged in bins of (ell1, mu, t), ell1 in bins of
+ * equal logarithmic width and mu, t in equal linear bins of [0.5, 1], weighted by their
+ * triangle counts; an ensemble of realisations gives the mean and sigma per bin, compared
+ * with the local quadratic model averaged over the same lattice triangles, [B_Ana]_d. */
+
+/* Bin of every triplet, from the plan's labels (host only).
+ *   nl1, l1_edges  host double [nl1 + 1] increasing ell1 edges; bins are [lo, hi)
+ *   nmu, nt        equal bins of 0.5 <= mu, t <= 1 (the paper uses 5 and 5); a label
+ *                  below 0.5 or above 1 (mean radii of wide rings need not close a
+ *                  triangle) counts in the end bin
+ *   bin_of_triplet host int32 [ntrip]: (l1_bin * nmu + mu_bin) * nt + t_bin, or -1 when
+ *                  ell1 lies outside the edges
+ * Errors: ABS_ERR_INVALID. */
+abs_status abs_rebin_table(abs_plan_t plan, int32_t nl1, const double* l1_edges, int32_t nmu, int32_t nt,
+                           int32_t* bin_of_triplet);
+
+/* Triangle-weighted bin averages for `batch` grids: Bbin[g][k] = sum N_t B_t / sum N_t over
+ * the triplets of bin k whose B_t is not NaN (Eq. 12 over the union of the bin's
+ * triangles), Nbin[g][k] = sum N_t; a bin without triplets gets NaN and 0.  Sums run in
+ * triplet order (FP64).  All pointers are device memory:
+ *   bin_of_triplet int32 [ntrip] (abs_rebin_table), B, N double [batch][ntrip] (from
+ *   abs_estimate), Bbin, Nbin double [batch][nbins].
+ * Asynchronous on `stream`.  Errors: ABS_ERR_INVALID, ABS_ERR_DEVICE. */
+abs_status abs_rebin(abs_plan_t plan, int32_t nbins, const int32_t* bin_of_triplet, int32_t batch,
+                     const double* B, const double* N, double* Bbin, double* Nbin, void* stream);
+
+/* Ensemble statistics over realisations (Sec. 3) and deviations from a model (Sec. 4):
+ *   X       device double [nreal][nvals] (e.g. abs_rebin's Bbin of nreal realisations)
+ *   mean    device double [nvals]: mean over the realisations
+ *   sigma   device double [nvals]: sqrt(<X^2> - mean^2) (the ensemble sigma, no Bessel
+ *           correction)
+ *   model   device double [nvals] or NULL; with it, dB = |mean - model| / model and
+ *           dsigma = |mean - model| / sigma (either may be NULL)
+ * Realisations are added in order (FP64).  Asynchronous.  Errors: ABS_ERR_INVALID
+ * (dB or dsigma without model), ABS_ERR_DEVICE. */
+abs_status abs_ensemble(int32_t nreal, int32_t nvals, const double* X, const double* model, double* mean,
+                        double* sigma, double* dB, double* dsigma, void* stream);
+
+/* Device workspace of abs_model_discrete. */
+abs_status abs_model_workspace(abs_plan_t plan, size_t* bytes);
+
+/* [B_Ana]_d per triplet: the first-order bispectrum of the local quadratic model (Eq. 14),
+ * 2 f (C1 C2 + C2 C3 + C3 C1), averaged over the triplet's closed lattice triangles with
+ * the weights Y1 Y2 Y3 of Eq. (12)'s denominator (Sec. 4, the discretely sampled
+ * prediction).  The weighted triangle sum is trilinear in the weights, so the pair term is
+ * taken from three runs of the FP64 weight path with weights Y (1 + s C / max C),
+ * s = +1, -1, 0.
+ *   w      device float [n][n] weights as the plan's wmode reads them (NULL for unit)
+ *   c      device float [n][n] the model C at every cell (e.g. C_ell at ell = 2 pi du |g|),
+ *          taken through its even part (c(g) + c(-g)) / 2, non-negative
+ *   f      f_NG / sigma_T of Eq. (13)
+ *   work   device, abs_model_workspace bytes, 256-byte aligned
+ *   out    device double [ntrip]; NaN for empty triplets (as B_t)
+ * Asynchronous on `stream`.  Errors: ABS_ERR_INVALID, ABS_ERR_UNBOUND, ABS_ERR_NOMEM,
+ * ABS_ERR_DEVICE. */
+abs_status abs_model_discrete(abs_plan_t plan, const float* w, const float* c, double f, void* work,
+                              size_t work_bytes, double* out, void* stream);
+
 /* Timing hook: record the caller's HIP events (hipEvent_t passed as void*) on the
  * call's stream immediately before and after the launches of one stage in every later
  * abs_estimate / abs_counts / abs_grid call, until replaced (NULL clears a stage).

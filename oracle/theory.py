@@ -82,9 +82,10 @@ def b_ana(c1, c2, c3, f):
 
 def b_ana_discrete(n, edges, trips, C, f, Y=None, chunk=1 << 16):
     """[B_Ana]_d per triplet: Eq. (14) averaged over the triplet's closed lattice
-    triangles with weight Y1 Y2 Y3 (Y = 1 when not given)."""
+    triangles with weight Y1 Y2 Y3 (Y = 1 when not given); NaN for a triplet without any
+    weighted triangle (the empty-triplet rule of the estimator)."""
     from .plan import ring_masks
-    from .estimator import _pairs_of
+    from .estimator import min_weight
     masks = ring_masks(n, edges)
     Y = np.ones((n, n)) if Y is None else np.asarray(Y, dtype=np.float64)
     I = np.stack([np.fft.fft2(np.where(m, Y, 0.0)).real for m in masks])
@@ -100,4 +101,6 @@ def b_ana_discrete(n, edges, trips, C, f, Y=None, chunk=1 << 16):
         for q, (i, j, k) in enumerate(trips):
             num[q] += np.dot(Jc[i] * Jc[j], Ic[k]) + np.dot(Ic[i] * Jc[j], Jc[k]) + np.dot(Jc[i] * Ic[j], Jc[k])
             den[q] += np.dot(Ic[i] * Ic[j], Ic[k])
-    return 2.0 * f * num / den
+    wmin = min_weight(Y, masks)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.where(den < 0.5 * wmin ** 3, np.nan, 2.0 * f * num / den)

@@ -72,6 +72,11 @@ def lib():
         "abs_estimate": [_P, i32, i32, _P, _P, i32, _P, _P, sz, _P, _P, _P],
         "abs_estimate_noalloc": [_P, i32, i32, _P, _P, i32, _P, _P, _P, _P],
         "abs_counts": [_P, _P, _P, sz, _P, _P],
+        "abs_rebin_table": [_P, i32, _P, i32, i32, _P],
+        "abs_rebin": [_P, i32, _P, i32, _P, _P, _P, _P, _P],
+        "abs_ensemble": [i32, i32, _P, _P, _P, _P, _P, _P, _P],
+        "abs_model_workspace": [_P, ctypes.POINTER(sz)],
+        "abs_model_discrete": [_P, _P, _P, dbl, _P, sz, _P, _P],
         "abs_sync": [_P, _P],
         "abs_profile": [_P, i32, _P, _P],
         "abs_destroy": [_P],

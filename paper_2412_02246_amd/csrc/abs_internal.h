@@ -124,12 +124,24 @@ struct abs_plan_s {
 };
 
 namespace abs_impl {
+// A modulation of the weights for the model's discrete prediction: every weight-set cell's
+// Y(g) becomes Y(g) (1 + sgn Cs(g) / cmax), Cs(g) = (c(g) + c(-g)) / 2, cmax = the float
+// whose bits *cmax_bits holds (on the device).
+struct WeightMod {
+  const float* c = nullptr;
+  const unsigned* cmax_bits = nullptr;
+  double sgn = 0.0;
+};
 // plan.cpp
 bool build_jit_source(abs_plan_s* p);
 abs_status compile_jit(abs_plan_s* p, int part);
 uint64_t jit_key(const abs_plan_s* p, int part);
 WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_counts);
 void build_mfma_tables(abs_plan_s* p);
+// estimate.hip
+abs_status ensure_device(abs_plan_s* p);
+abs_status counts_into(abs_plan_s* p, const float* w, char* wk, const WeightMod* mod, double* N,
+                       hipStream_t st);
 inline void prof_begin(const abs_plan_s* p, int stage, hipStream_t st) {
   if (p->prof[stage][0]) (void)hipEventRecord(p->prof[stage][0], st);
 }

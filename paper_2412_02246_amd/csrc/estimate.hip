@@ -17,7 +17,7 @@ hipError_t launch_colpass_data(const abs_plan_s* p, const void* grids, int dtype
                                unsigned long long* wmin, hipStream_t st);
 hipError_t launch_colpass_weight(const abs_plan_s* p, const float* w, int w_batched, int nsets,
                                  void* xc, double2* Z, long long zset, unsigned long long* wmin,
-                                 hipStream_t st);
+                                 hipStream_t st, const WeightMod* mod);
 hipError_t launch_rowpass_f32(const abs_plan_s* p, int nsets, const float2* Z, long long zset,
                               float* F, long long fset, unsigned* fmax_bits, hipStream_t st);
 hipError_t launch_mfma_contract(const abs_plan_s* p, const float* F, long long fset, int nsets,
@@ -139,7 +139,7 @@ abs_status launch_contract(const abs_plan_s* p, int kind, int waves, const void*
 // the data sets first, weight sets after them.
 abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batch, int dtype,
                                    const void* grids, const float* w, int w_batched, char* work,
-                                   hipStream_t st) {
+                                   hipStream_t st, const WeightMod* mod) {
   double* part = reinterpret_cast<double*>(work + wl.part);
   const long long npix = (long long)p->n * p->n;
   unsigned long long* wmin = reinterpret_cast<unsigned long long*>(work + wl.wmin);
@@ -180,7 +180,7 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
   if (wl.nisets > 0) {
     double2* Z = reinterpret_cast<double2*>(work + wl.zi);
     double* F = reinterpret_cast<double*>(work + wl.fi);
-    if (launch_colpass_weight(p, w, w_batched, wl.nisets, work + wl.xc, Z, wl.zset, wmin + batch, st) !=
+    if (launch_colpass_weight(p, w, w_batched, wl.nisets, work + wl.xc, Z, wl.zset, wmin + batch, st, mod) !=
         hipSuccess)
       return ABS_ERR_DEVICE;
     if (launch_rowpass_f64(p, wl.nisets, Z, wl.zset, F, wl.fset64, st) != hipSuccess)
@@ -283,7 +283,7 @@ abs_status estimate_on(abs_plan_t p, const WorkLayout& wl, int32_t batch, int32_
                        const float* w, int32_t w_batched, const double* n_given, char* wk, double* B,
                        double* N, hipStream_t st) {
   (void)hipGetLastError();
-  abs_status s = run_fields_and_contract(p, wl, batch, dtype, grids, w, w_batched, wk, st);
+  abs_status s = run_fields_and_contract(p, wl, batch, dtype, grids, w, w_batched, wk, st, nullptr);
   if (s != ABS_OK) return s;
   const double* part = reinterpret_cast<const double*>(wk + wl.part);
   const double* part64 = reinterpret_cast<const double*>(wk + wl.part64);
@@ -354,6 +354,31 @@ abs_status abs_estimate_noalloc(abs_plan_t p, int32_t batch, int32_t dtype, cons
                      static_cast<hipStream_t>(stream));
 }
 
+}  // extern "C"
+
+namespace abs_impl {
+
+// N_t of one weight set into N (device, ntrip), on a workspace of work_layout(p, 0, 0, 0)
+// bytes, with the weights optionally modulated (mod); the smallest non-zero ring-cell
+// weight of the set lands in the workspace's wmin slot 0.
+abs_status counts_into(abs_plan_s* p, const float* w, char* wk, const WeightMod* mod, double* N,
+                       hipStream_t st) {
+  const WorkLayout wl = work_layout(p, 0, 0, 0);
+  (void)hipGetLastError();
+  // batch 0: the single set is the weight set
+  abs_status s = run_fields_and_contract(p, wl, 0, ABS_C64, nullptr, w, 0, wk, st, mod);
+  if (s != ABS_OK) return s;
+  const double inv = 1.0 / ((double)p->n * (double)p->n);
+  const int* pos64 = reinterpret_cast<const int*>(static_cast<const char*>(p->dev) + p->dl.pos64);
+  counts_kernel<<<(unsigned)((p->ntrip + 63) / 64), kFinBlock, 0, st>>>(
+      reinterpret_cast<const double*>(wk + wl.part64), p->nblk64, pos64, (int)p->ntrip, inv, N);
+  return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
+}
+
+}  // namespace abs_impl
+
+extern "C" {
+
 abs_status abs_counts(abs_plan_t p, const float* w, void* work, size_t work_bytes, double* N,
                       void* stream) {
   if (!p) return ABS_ERR_INVALID;
@@ -361,19 +386,8 @@ abs_status abs_counts(abs_plan_t p, const float* w, void* work, size_t work_byte
   if (s != ABS_OK) return s;
   if (!work || !N || (!w && p->wmode != ABS_W_UNIT)) return ABS_ERR_INVALID;
   if (reinterpret_cast<uintptr_t>(work) & 15) return ABS_ERR_INVALID;
-  const WorkLayout wl = work_layout(p, 0, 0, 0);
-  if (work_bytes < wl.total) return ABS_ERR_NOMEM;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  (void)hipGetLastError();
-  char* wk = static_cast<char*>(work);
-  // batch 0: the single set is the weight set
-  s = run_fields_and_contract(p, wl, 0, ABS_C64, nullptr, w, 0, wk, st);
-  if (s != ABS_OK) return s;
-  const double inv = 1.0 / ((double)p->n * (double)p->n);
-  const int* pos64 = reinterpret_cast<const int*>(static_cast<const char*>(p->dev) + p->dl.pos64);
-  counts_kernel<<<(unsigned)((p->ntrip + 63) / 64), kFinBlock, 0, st>>>(
-      reinterpret_cast<const double*>(wk + wl.part64), p->nblk64, pos64, (int)p->ntrip, inv, N);
-  return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
+  if (work_bytes < work_layout(p, 0, 0, 0).total) return ABS_ERR_NOMEM;
+  return counts_into(p, w, static_cast<char*>(work), nullptr, N, static_cast<hipStream_t>(stream));
 }
 
 abs_status abs_profile(abs_plan_t p, int32_t stage, void* ev_begin, void* ev_end) {

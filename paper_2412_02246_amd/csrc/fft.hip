@@ -418,7 +418,7 @@ template <bool DATA, typename GT>
 __global__ void __launch_bounds__(kBlock)
 herm_kernel(const GT* __restrict__ grids, const float* __restrict__ w, int w_batched, int wmode,
             int n, int hm, int lc, double lo2, double hi2, typename HermT<DATA>::T* __restrict__ xc,
-            unsigned long long* __restrict__ wmin) {
+            unsigned long long* __restrict__ wmin, WeightMod mod) {
   using OT = typename HermT<DATA>::T;
   __shared__ OT tile[kHy][kHx + 1];
   __shared__ double wred[kBlock / 64];
@@ -436,7 +436,12 @@ herm_kernel(const GT* __restrict__ grids, const float* __restrict__ w, int w_bat
       const int iy = gy < 0 ? gy + n : gy;
       const int my = gy > 0 ? n - gy : -gy, mx = gx > 0 ? n - gx : 0;
       const long long i0 = (long long)iy * n + gx, i1 = (long long)my * n + mx;
-      const double y = 0.5 * (weight_of<double>(ws, wmode, i0) + weight_of<double>(ws, wmode, i1));
+      double y = 0.5 * (weight_of<double>(ws, wmode, i0) + weight_of<double>(ws, wmode, i1));
+      if (!DATA && mod.c) {
+        const double cs = 0.5 * ((double)mod.c[i0] + (double)mod.c[i1]);
+        const double cmax = (double)__uint_as_float(*mod.cmax_bits);
+        if (cmax > 0.0) y *= 1.0 + mod.sgn * cs / cmax;
+      }
       const double r2 = (double)((long long)gx * gx + (long long)gy * gy);
       if (r2 >= lo2 && r2 < hi2 && y != 0.0) ymin = fmin(ymin, fabs(y));
       if constexpr (DATA) {
@@ -570,11 +575,12 @@ constexpr int col_tiles_per_block(int log2n) { return log2n <= 10 ? 1 : 2; }
 
 template <bool DATA, typename GT>
 hipError_t launch_herm(const abs_plan_s* p, const GT* grids, const float* w, int w_batched, int nsets,
-                       typename HermT<DATA>::T* xc, unsigned long long* wmin, hipStream_t st) {
+                       typename HermT<DATA>::T* xc, unsigned long long* wmin, hipStream_t st,
+                       const WeightMod* mod = nullptr) {
   const int hm = p->hmax, lc = 2 * p->hmax + 1;
   const dim3 grid((unsigned)((hm + kHx) / kHx), (unsigned)((lc + kHy - 1) / kHy), (unsigned)nsets);
   herm_kernel<DATA, GT><<<grid, kBlock, 0, st>>>(grids, w, w_batched, p->wmode, p->n, hm, lc, p->lo2[0],
-                                                 p->hi2[p->nb - 1], xc, wmin);
+                                                 p->hi2[p->nb - 1], xc, wmin, mod ? *mod : WeightMod{});
   return hipGetLastError();
 }
 
@@ -637,11 +643,11 @@ hipError_t launch_colpass_data(const abs_plan_s* p, const void* grids, int dtype
 
 hipError_t launch_colpass_weight(const abs_plan_s* p, const float* w, int w_batched, int nsets,
                                  void* xc, double2* Z, long long zset, unsigned long long* wmin,
-                                 hipStream_t st) {
+                                 hipStream_t st, const WeightMod* mod) {
   const char* base = static_cast<const char*>(p->dev);
   const double2* tw = reinterpret_cast<const double2*>(base + p->dl.tw64);
   double* x = static_cast<double*>(xc);
-  hipError_t e = launch_herm<false, float2>(p, nullptr, w, w_batched, nsets, x, wmin, st);
+  hipError_t e = launch_herm<false, float2>(p, nullptr, w, w_batched, nsets, x, wmin, st, mod);
   if (e != hipSuccess) return e;
   return launch_colpass<double>(p, nsets, x, Z, zset, tw, st);
 }

@@ -220,5 +220,68 @@ class Plan:
                                  _ptr(dropped), _stream(stream)), "abs_grid")
         return grid, wsum, dropped
 
+    # -- after the estimator (Secs. 3-4) ------------------------------------------
+    def rebin_table(self, l1_edges, nmu=5, nt=5):
+        """Bin of every triplet (host int32 [ntrip], -1 outside the ell1 edges) and the
+        number of bins."""
+        e = np.ascontiguousarray(l1_edges, dtype=np.float64)
+        out = np.zeros(self.ntrip, np.int32)
+        L.check(L.lib().abs_rebin_table(self.handle, len(e) - 1, e.ctypes.data_as(ctypes.c_void_p), int(nmu),
+                                        int(nt), out.ctypes.data_as(ctypes.c_void_p)), "abs_rebin_table")
+        return out, (len(e) - 1) * int(nmu) * int(nt)
+
+    def rebin(self, B, N, bins, nbins, stream=None):
+        """Triangle-weighted bin averages of B [batch][ntrip] (device): (Bbin, Nbin) torch
+        float64 [batch][nbins].  bins: device int32 [ntrip] from rebin_table."""
+        import torch
+        if B.dim() == 1:
+            B, N = B.unsqueeze(0), N.unsqueeze(0)
+        for t in (B, N):
+            if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape[1:]) != (self.ntrip,):
+                raise ValueError("B and N must be contiguous float64 [batch][ntrip]")
+        if bins.dtype != torch.int32 or bins.numel() != self.ntrip:
+            raise ValueError("bins must be int32 [ntrip]")
+        Bbin = torch.empty((B.shape[0], nbins), dtype=torch.float64, device=B.device)
+        Nbin = torch.empty_like(Bbin)
+        L.check(L.lib().abs_rebin(self.handle, int(nbins), _ptr(bins), B.shape[0], _ptr(B), _ptr(N), _ptr(Bbin),
+                                  _ptr(Nbin), _stream(stream)), "abs_rebin")
+        return Bbin, Nbin
+
+    def model_discrete(self, c, f, w=None, stream=None):
+        """[B_Ana]_d per triplet (torch float64 [ntrip]) for the model C at every cell
+        (float32 [n][n], device) and f = f_NG / sigma_T, with the plan's weights w."""
+        import torch
+        for t in (c, w):
+            if t is not None and (t.dtype != torch.float32 or tuple(t.shape) != (self.n, self.n)
+                                  or not t.is_contiguous()):
+                raise ValueError("c and w must be contiguous float32 [n][n]")
+        b = ctypes.c_size_t()
+        L.check(L.lib().abs_model_workspace(self.handle, ctypes.byref(b)), "abs_model_workspace")
+        work = self._workspace(b.value)
+        out = torch.empty(self.ntrip, dtype=torch.float64, device=c.device)
+        L.check(L.lib().abs_model_discrete(self.handle, _ptr(w), _ptr(c), float(f), _ptr(work), work.numel(),
+                                           _ptr(out), _stream(stream)), "abs_model_discrete")
+        return out
+
     def sync(self, stream=None):
         L.check(L.lib().abs_sync(self.handle, _stream(stream)), "abs_sync")
+
+
+def ensemble(X, model=None, stream=None):
+    """Ensemble mean and sigma over axis 0 of X (device float64 [nreal][nvals]), and with a
+    model (device float64 [nvals]) Delta_B and Delta_sigma: four torch tensors (the last two
+    None without a model)."""
+    import torch
+    if X.dtype != torch.float64 or X.dim() != 2 or not X.is_contiguous():
+        raise ValueError("X must be a contiguous float64 [nreal][nvals] tensor")
+    nreal, nv = X.shape
+    mean = torch.empty(nv, dtype=torch.float64, device=X.device)
+    sigma = torch.empty_like(mean)
+    dB = dS = None
+    if model is not None:
+        if model.dtype != torch.float64 or model.numel() != nv:
+            raise ValueError("model must be float64 [nvals]")
+        dB, dS = torch.empty_like(mean), torch.empty_like(mean)
+    L.check(L.lib().abs_ensemble(nreal, nv, _ptr(X), _ptr(model), _ptr(mean), _ptr(sigma), _ptr(dB), _ptr(dS),
+                                 _stream(stream)), "abs_ensemble")
+    return mean, sigma, dB, dS
