@@ -221,18 +221,29 @@ def copy_probe(a):
           flush=True)
 
 
-def serve_specs(nreq, seed=4242):
-    """The serving stream: grid sizes uniform over {512, 1024, 2048, 4096}^2 with 16..32
-    log rings (46 <= l < 1320, radii scaled by n/1024); half the requests are realisations
-    sharing their channel's weights, half channels with their own."""
+def serve_specs(nreq, seed=4242, channels=16):
+    """The serving stream: `channels` channels, each a grid size uniform over
+    {512, 1024, 2048, 4096}^2 with 16..32 log rings (46 <= l < 1320, radii scaled by n/1024)
+    and its own baseline counts; half the requests are realisations of one of them (the
+    channel's plan and weights, so its triangle counts are computed once and batches can
+    form), half are channels of their own (grid size, rings and weights drawn afresh).
+    Returns [(n, edges, channel or None)] and the generator."""
     rng = np.random.default_rng(seed)
-    specs = []
-    for _ in range(nreq):
+
+    def draw():
         n = int(rng.choice([512, 1024, 2048, 4096]))
         nb = int(rng.integers(16, 33))
         s = n / 1024.0
-        edges = tuple((46.0 * s / (2 * np.pi)) * (1320.0 / 46.0) ** (np.arange(nb + 1) / nb))
-        specs.append((n, edges, bool(rng.random() < 0.5)))
+        return n, tuple((46.0 * s / (2 * np.pi)) * (1320.0 / 46.0) ** (np.arange(nb + 1) / nb))
+
+    chans = [draw() for _ in range(channels)]
+    specs = []
+    for _ in range(nreq):
+        if rng.random() < 0.5:
+            c = int(rng.integers(channels))
+            specs.append(chans[c] + (c,))
+        else:
+            specs.append(draw() + (None,))
     return specs, rng
 
 
@@ -263,27 +274,30 @@ def serve_run(precision, nreq, budget_gib, compiled=None, log=sys.stderr):
     ex = GpuExecutor(A.W_INV_COUNT, precision=prec, max_batch=max_batch, slots=slots)
     for k, p in zip(keys, plans):
         ex.plans[k] = p.bind(0)
-    # device-resident inputs: 4 grids per size, one shared (channel) mask per size and 4
-    # per-request masks per size
+    # device-resident inputs: 4 grids and 4 per-request count masks per size, one count
+    # mask per channel
     gen = torch.Generator(device=dev)
     gen.manual_seed(4242)
-    pool, chan, own = {}, {}, {}
+    pool, own, lams = {}, {}, {}
     for n in (512, 1024, 2048, 4096):
         g = torch.arange(n, device=dev)
         g = torch.where(g < n // 2, g, g - n).double()
         r = torch.sqrt(g[:, None] ** 2 + g[None, :] ** 2)
-        lam = 4.0 * torch.exp(-r / (n / 8.0))
+        lams[n] = 4.0 * torch.exp(-r / (n / 8.0))
         pool[n] = [torch.randn((n, n), dtype=torch.complex64, device=dev, generator=gen) for _ in range(4)]
-        chan[n] = torch.poisson(lam, generator=gen).float()
-        own[n] = [torch.poisson(lam, generator=gen).float() for _ in range(4)]
+        own[n] = [torch.poisson(lams[n], generator=gen).float() for _ in range(4)]
+    chan = {}
+    for n, e, c in specs:
+        if c is not None and c not in chan:
+            chan[c] = torch.poisson(lams[n], generator=gen).float()
     torch.cuda.synchronize()
 
     def requests(arrivals):
         out = []
-        for k, ((n, e, shared), t) in enumerate(zip(specs, arrivals)):
+        for k, ((n, e, c), t) in enumerate(zip(specs, arrivals)):
             grid = pool[n][k % 4]
-            if shared:
-                out.append(Request(k, n, e, grid, chan[n], ("chan", n), t))
+            if c is not None:
+                out.append(Request(k, n, e, grid, chan[c], ("chan", c), t))
             else:
                 out.append(Request(k, n, e, grid, own[n][k % 4], None, t))
         return out
@@ -339,9 +353,9 @@ def serve_bench(a):
         "ms_per_step": 1e3 / mu, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16x3": "bf16x3 (f32 acc)", "fp16x3": "fp16x3 (f32 acc)"}[a.precision],
         "data": "synthetic",
-        "config": {"workload": "serving: %d requests, n in {512,1024,2048,4096}, 16-32 log rings, "
-                               "50%% shared-mask realisations / 50%% channels, budget %.0f GiB"
-                               % (a.requests, a.budget_gib), **out},
+        "config": {"workload": "serving: %d requests, n in {512,1024,2048,4096}, 16-32 log rings; 50%% "
+                               "realisations of 16 channels (their plan and counts), 50%% channels of their "
+                               "own; budget %.0f GiB" % (a.requests, a.budget_gib), **out},
     }
     print(json.dumps(line), flush=True)
 
