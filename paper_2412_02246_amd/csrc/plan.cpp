@@ -196,17 +196,28 @@ WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_c
 namespace {
 
 // Split the ordered triplet list (ord[0 .. ntrip)) into G contiguous groups whose
-// register estimate, rw * (slots + bins used), stays within the budget.  G is a multiple
-// of the waves per workgroup (*waves): 4, or 8 when more than 4 groups are needed (fewer
-// slices re-read the fields).
-std::vector<int> split_groups(const abs_plan_s* p, const std::vector<int>& ord, int rw, int* waves) {
+// register estimate, rw * (slots + bins used), stays within kBudget, and with the pair
+// products the group forms (the compiler may keep them all live at once to overlap them)
+// within kBudgetPairs: above it the generated kernels spill (measured: groups of
+// rw * (slots + bins + pairs) up to 246 compile without spills, 258 and 262 spill 53 and
+// 12 VGPRs).  G is a multiple of the waves per workgroup (*waves): 4, or 8 when more than
+// 4 groups are needed (fewer slices re-read the fields).
+std::vector<int> split_groups(const abs_plan_s* p, const std::vector<int>& ord, int rw, bool jk, int* waves) {
   const int T = (int)p->ntrip;
-  const int kBudget = 200;
+  const int kBudget = rw == 1 ? 200 : 184, kBudgetPairs = rw == 1 ? 240 : 224;
   auto cost_ok = [&](int t0, int t1) {
     std::set<int> bins;
-    for (int t = t0; t < t1; ++t)
-      for (int q = 0; q < 3; ++q) bins.insert(p->trips[3 * ord[t] + q]);
-    return rw * ((t1 - t0) + (int)bins.size()) <= kBudget;
+    int pairs = 0, pa = -1, pb = -1;
+    for (int t = t0; t < t1; ++t) {
+      const int* x = &p->trips[3 * ord[t]];
+      for (int q = 0; q < 3; ++q) bins.insert(x[q]);
+      const int a = jk ? x[1] : x[0], b = jk ? x[2] : x[1];
+      if (a != pa || b != pb) ++pairs;
+      pa = a;
+      pb = b;
+    }
+    const int regs = rw * ((t1 - t0) + (int)bins.size());
+    return regs <= kBudget && regs + rw * pairs <= kBudgetPairs;
   };
   auto even = [&](int G) {
     std::vector<int> start(G + 1);
@@ -295,7 +306,7 @@ KernelOrder choose_order(const abs_plan_s* p, int rw) {
       if (B > 0)
         std::stable_sort(o.ord.begin(), o.ord.end(),
                          [&](int a, int b) { return p->trips[3 * a + 1] / B < p->trips[3 * b + 1] / B; });
-      o.start = split_groups(p, o.ord, rw, &o.waves);
+      o.start = split_groups(p, o.ord, rw, jk, &o.waves);
       if (o.start.empty()) continue;
       const int64_t cost = kStagedRingCost * staged_rings(p, o.ord, o.start, o.waves) +
                            pairs_formed(p, o.ord, o.start, jk) + T;

@@ -156,9 +156,10 @@ def test_code_variants_selected_by_each_plan():
         for k in seen:
             seen[k].add(got[k][1:] if k != "mfma" else got[k])
     # every order (jk plain, ij plain, ij in blocks of 4 / 8 / 16), both workgroup widths,
-    # multi-part code and the three precision-form variants occur
-    assert {(1, 0, 4), (1, 0, 8), (0, 0, 8), (0, 16, 8)} <= seen["contract"]
-    assert {(1, 0, 4), (1, 0, 8), (0, 0, 8), (0, 4, 8), (0, 8, 8), (0, 16, 8)} <= seen["weight"]
+    # multi-part code and the three precision-form variants occur (ij in blocks of 8 at
+    # 8 waves only for the FP64 kernel, jk in blocks never: no plan selects them)
+    assert {(1, 0, 4), (1, 0, 8), (0, 0, 8), (0, 4, 4), (0, 8, 4), (0, 4, 8), (0, 16, 8)} <= seen["contract"]
+    assert {(1, 0, 4), (1, 0, 8), (0, 0, 4), (0, 0, 8), (0, 4, 8), (0, 8, 8), (0, 16, 8)} <= seen["weight"]
     assert seen["mfma"] == {(2, 1), (12, 4), (12, 1)}
     assert any(VARIANTS[k]["contract"][0] > 1 for k in VARIANTS)
     assert any(VARIANTS[k]["weight"][0] > 2 for k in VARIANTS)
@@ -173,3 +174,31 @@ def test_4096_plan_triplets_match_oracle():
     trips, counts = oplan.plan_triplets(4096, e)
     assert np.array_equal(p.triplets, trips)
     assert p.ntrip == 2309 and np.all(counts >= 1)
+
+
+def _msgpack_uint_after(blob, key):
+    """The unsigned integer a msgpack map holds under `key` in a code object's metadata."""
+    i = blob.find(key)
+    assert i >= 0, key
+    b = blob[i + len(key):]
+    if b[0] < 0x80:
+        return b[0]
+    width = {0xcc: 1, 0xcd: 2, 0xce: 4}[b[0]]
+    return int.from_bytes(b[1:1 + width], "big")
+
+
+@pytest.mark.parametrize("which", ["1024x20", "4096x32", "8192x64"])
+def test_generated_contraction_kernels_do_not_spill(which):
+    """The run-time generated contraction code of the three workloads' plans (FP32 data and
+    FP64 weight kernels, every part) compiles without register spills: the triplet groups'
+    register estimate keeps spill code (scratch memory in the inner loop) out."""
+    A = _A()
+    n, nb = {"1024x20": (1024, 20), "4096x32": (4096, 32), "8192x64": (8192, 64)}[which]
+    s = n / 1024.0
+    e = oplan.log_edges(s * 46 / (2 * np.pi), s * 1320 / (2 * np.pi), nb)
+    p = A.Plan(n, e, wmode=A.W_INV_COUNT)
+    p.compile(workers=8)
+    for part in range(p.jit_parts):
+        _, blob = p.code(part)
+        assert _msgpack_uint_after(blob, b".vgpr_spill_count") == 0, (which, part)
+        assert _msgpack_uint_after(blob, b".private_segment_fixed_size") == 0, (which, part)

@@ -23,21 +23,28 @@ PLANS = {
     "ij_256x40": (256, _log(256, 0.05, 0.30, 40)),
     # the 4096^2 / 32-ring geometry scaled to 1024^2
     "c3_1024": (1024, _E3 / 4),
-    "w0_256x24": (256, _log(256, 0.05, 0.30, 24)),
+    "w0_256x16": (256, _log(256, 0.05, 0.30, 16)),
     "w4_512x24": (512, _log(512, 0.02, 0.33, 24)),
     "w4w_256x12": (256, _log(256, 0.02, 0.33, 12)),
     "jk8_256x16": (256, _log(256, 0.02, 0.33, 16)),
+    # rings of similar size (narrow radius range): orders in blocks of 4 or 8 j
+    "b4_256x12": (256, _log(256, 0.12, 0.25, 12)),
+    "b8_256x11": (256, _log(256, 0.08, 0.20, 11)),
+    "b4w_256x17": (256, _log(256, 0.12, 0.20, 17)),
 }
 
 VARIANTS = {
-    "ensemble_1024": dict(contract=(1, 0, 16, 8), weight=(2, 0, 8, 8), mfma=(12, 1)),
+    "ensemble_1024": dict(contract=(1, 0, 16, 8), weight=(3, 0, 8, 8), mfma=(12, 1)),
     "dense_256x64": dict(contract=(2, 0, 16, 8), weight=(3, 0, 8, 8), mfma=(12, 1)),
     "ij_256x40": dict(contract=(1, 0, 0, 8), weight=(2, 0, 8, 8), mfma=(12, 1)),
     "c3_1024": dict(contract=(1, 1, 0, 8), weight=(1, 0, 16, 8), mfma=(12, 4)),
-    "w0_256x24": dict(contract=(1, 1, 0, 8), weight=(1, 0, 0, 8), mfma=(12, 4)),
-    "w4_512x24": dict(contract=(1, 1, 0, 8), weight=(1, 0, 4, 8), mfma=(2, 1)),
+    "w0_256x16": dict(contract=(1, 1, 0, 4), weight=(1, 0, 0, 8), mfma=(2, 1)),
+    "w4_512x24": dict(contract=(1, 1, 0, 8), weight=(1, 1, 0, 8), mfma=(2, 1)),
     "w4w_256x12": dict(contract=(1, 1, 0, 4), weight=(1, 1, 0, 4), mfma=(2, 1)),
     "jk8_256x16": dict(contract=(1, 1, 0, 4), weight=(1, 1, 0, 8), mfma=(2, 1)),
+    "b4_256x12": dict(contract=(1, 0, 4, 4), weight=(1, 0, 4, 8), mfma=(2, 1)),
+    "b8_256x11": dict(contract=(1, 0, 8, 4), weight=(1, 0, 0, 4), mfma=(2, 1)),
+    "b4w_256x17": dict(contract=(1, 0, 4, 8), weight=(1, 0, 0, 8), mfma=(2, 1)),
 }
 
 # precision forms run on the plans whose tiling variant they cover
