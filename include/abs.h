@@ -210,6 +210,23 @@ abs_status abs_estimate(abs_plan_t plan, int32_t batch, int32_t dtype, const voi
                         const float* w, int32_t w_batched, const double* n_given,
                         void* work, size_t work_bytes, double* B, double* N, void* stream);
 
+/* The estimator for general complex gridded visibilities (Eq. 10 taken literally: the ring
+ * fields D_m of W V are complex, with no Hermitian symmetrisation), giving a complex B_t
+ * = S_t / (A N_t) with S_t = (1/n^2) sum_theta D_i D_j D_k, i.e. the sum of X(g1) X(g2)
+ * X(g3) over closed triangles with X = W V.  For Hermitian input Im B_t = 0 and Re B_t
+ * equals abs_estimate's B_t.  Computed as four real passes of the same kernels: with
+ * W V = H + i G (H, G Hermitian), the triple sums of H, G, H + G and H - G combine into
+ * Re S and Im S.  Arguments as abs_estimate, except:
+ *   work   device workspace of abs_estimate_complex_workspace bytes (four data sets a grid)
+ *   B      device double [batch][ntrip][2]  (Re B_t, Im B_t), NaN for empty triplets
+ * The weights must be real, non-negative and symmetric as for abs_estimate.  Errors: as
+ * abs_estimate. */
+abs_status abs_estimate_complex_workspace(abs_plan_t plan, int32_t batch, int32_t w_batched, int32_t have_counts,
+                                          size_t* bytes);
+abs_status abs_estimate_complex(abs_plan_t plan, int32_t batch, int32_t dtype, const void* grids, const float* w,
+                                int32_t w_batched, const double* n_given, void* work, size_t work_bytes,
+                                double* B, double* N, void* stream);
+
 /* abs_estimate without a caller workspace and without any device allocation, for callers
  * that cannot allocate (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  The arguments are those of abs_estimate minus work / work_bytes; the

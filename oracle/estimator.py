@@ -147,6 +147,47 @@ def estimate(grid, w, edges, norm, wmode=UNIT, trips=None, with_scales=False, ch
     return out
 
 
+def estimate_complex(grid, w, edges, norm, wmode=UNIT, trips=None, chunk=1 << 16):
+    """Eq. (12) for general complex gridded visibilities, taking Eq. (10) literally: the
+    fields D_m of X = W V (no Hermitian symmetrisation) are complex, S_t = sum_theta
+    D_i D_j D_k / n^2 is complex and B_t = S_t / (A N_t) (NaN for empty triplets).  Same
+    keys as estimate(..., with_scales=True); rhoS = sqrt(sum_theta |D_i D_j D_k|^2) / n^2."""
+    from . import plan as _plan
+    import scipy.fft
+    grid = np.asarray(grid).astype(np.complex128)
+    n = grid.shape[0]
+    if trips is None:
+        trips, _ = _plan.plan_triplets(n, edges)
+    trips = np.asarray(trips, dtype=np.int64).reshape(-1, 3)
+    W = effective_weights(n, w, wmode)
+    masks = _plan.ring_masks(n, edges)
+    X = W * grid
+    Y = hermitian_part(W.astype(np.complex128))
+    D = np.stack([scipy.fft.fft2(np.where(m, X, 0), workers=-1) for m in masks])
+    I = ring_fields(Y, masks)
+    npix = float(n * n)
+    pairs, pidx = _pairs_of(trips)
+    pi = np.array([p[0] for p in pairs], dtype=np.int64)
+    pj = np.array([p[1] for p in pairs], dtype=np.int64)
+    Df = D.reshape(len(masks), -1)
+    acc = np.zeros((len(pairs), len(masks)), np.complex128)
+    acc2 = np.zeros((len(pairs), len(masks)), np.float64)
+    for s0 in range(0, Df.shape[1], chunk):
+        Fc = Df[:, s0:s0 + chunk]
+        P = Fc[pi] * Fc[pj]
+        acc += P @ Fc.T
+        acc2 += (np.abs(P) ** 2) @ (np.abs(Fc) ** 2).T
+    S = np.array([acc[pidx[(i, j)], k] for i, j, k in trips]) / npix
+    rhoS = np.sqrt(np.array([acc2[pidx[(i, j)], k] for i, j, k in trips])) / npix
+    N = triple_sums(I, trips, chunk)
+    rhoN = np.sqrt(np.maximum(triple_sums(I, trips, chunk, power=2), 0.0) / n ** 2)
+    wmin = min_weight(Y.real, masks)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        B = S / (norm * N)
+    B = np.where(N < 0.5 * wmin ** 3, np.nan + 1j * np.nan, B)
+    return dict(B=B, S=S, N=N, trips=trips, wmin=wmin, rhoS=rhoS, rhoN=rhoN)
+
+
 def estimate_subset(grid, w, edges, norm, trips, wmode=UNIT):
     """Eq. (12) and the error scales for a subset of triplets, computing only the ring
     fields those triplets use (for full-size grids where every field would not fit the

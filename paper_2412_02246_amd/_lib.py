@@ -71,6 +71,8 @@ def lib():
         "abs_grid": [_P, i64, i32, _P, _P, _P, i32, _P, sz, _P, _P, _P, _P],
         "abs_estimate": [_P, i32, i32, _P, _P, i32, _P, _P, sz, _P, _P, _P],
         "abs_estimate_noalloc": [_P, i32, i32, _P, _P, i32, _P, _P, _P, _P],
+        "abs_estimate_complex_workspace": [_P, i32, i32, i32, ctypes.POINTER(sz)],
+        "abs_estimate_complex": [_P, i32, i32, _P, _P, i32, _P, _P, sz, _P, _P, _P],
         "abs_counts": [_P, _P, _P, sz, _P, _P],
         "abs_rebin_table": [_P, i32, _P, i32, i32, _P],
         "abs_rebin": [_P, i32, _P, i32, _P, _P, _P, _P, _P],

@@ -57,7 +57,8 @@ struct JitPart {
 };
 
 struct WorkLayout {
-  int nsets;          // D sets (one per grid) followed by I sets
+  int nsets;          // D sets followed by I sets
+  int ndsets;         // D sets (spg per grid)
   int nisets;
   size_t zd, zi, fd, fi, part, part64, fmax, wmin, xc, total;
   int64_t zset;       // complex elements per set of column-pass output
@@ -136,7 +137,7 @@ struct WeightMod {
 bool build_jit_source(abs_plan_s* p);
 abs_status compile_jit(abs_plan_s* p, int part);
 uint64_t jit_key(const abs_plan_s* p, int part);
-WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_counts);
+WorkLayout work_layout(const abs_plan_s* p, int grids, int w_batched, int have_counts, int spg = 1);
 void build_mfma_tables(abs_plan_s* p);
 // estimate.hip
 abs_status ensure_device(abs_plan_s* p);

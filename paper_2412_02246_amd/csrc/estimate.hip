@@ -14,7 +14,7 @@
 namespace abs_impl {
 hipError_t launch_colpass_data(const abs_plan_s* p, const void* grids, int dtype, const float* w,
                                int w_batched, int batch, void* xc, float2* Z, long long zset,
-                               unsigned long long* wmin, hipStream_t st);
+                               unsigned long long* wmin, hipStream_t st, int spg);
 hipError_t launch_colpass_weight(const abs_plan_s* p, const float* w, int w_batched, int nsets,
                                  void* xc, double2* Z, long long zset, unsigned long long* wmin,
                                  hipStream_t st, const WeightMod* mod);
@@ -98,6 +98,41 @@ finalize_kernel(const double* __restrict__ part, long long partset, int nblk, co
   }
 }
 
+// Complex input: with W V = H + i G (H and G Hermitian, their ring fields F and E real),
+// S = sum (F + i E)(F + i E)(F + i E) has Re S = FFF - (FEE + EFE + EEF) and
+// Im S = (EFF + FEF + FFE) - EEE.  The four sets of grid b hold the triple sums of H, G,
+// H + G and H - G: T0 = FFF, T1 = EEE, T2 = FFF + sym(EFF) + sym(FEE) + EEE and
+// T3 = FFF - sym(EFF) + sym(FEE) - EEE, so Re S = 2 T0 - (T2 + T3) / 2 and
+// Im S = (T2 - T3) / 2 - 2 T1.  B[b][t] = (Re S, Im S) / (A N), NaN for empty triplets.
+__global__ void __launch_bounds__(kFinBlock)
+finalize_complex_kernel(const double* __restrict__ part, long long partset, int nblk, const int* __restrict__ pos,
+                        const double* __restrict__ part64, long long partset64, int nblk64,
+                        const int* __restrict__ pos64, int ntrip, int nisets, const double* __restrict__ n_given,
+                        const unsigned long long* __restrict__ wmin_bits, double inv_npix, double norm,
+                        double* __restrict__ B, double* __restrict__ N) {
+  const int t = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int b = blockIdx.y;
+  double T[4];
+  for (int v = 0; v < 4; ++v)
+    T[v] = sum_partials(part + (long long)(4 * b + v) * partset, nblk, ntrip, pos, t) * inv_npix;
+  double nn;
+  if (nisets == 0) {
+    nn = t < ntrip ? n_given[t] : 0.0;
+  } else {
+    const int is = nisets > 1 ? b : 0;
+    nn = sum_partials_half(part64 + (long long)is * partset64, nblk64, ntrip, pos64, t) * inv_npix;
+  }
+  if (threadIdx.x < 64 && t < ntrip) {
+    const double re = 2.0 * T[0] - 0.5 * (T[2] + T[3]);
+    const double im = 0.5 * (T[2] - T[3]) - 2.0 * T[1];
+    const double wm = __longlong_as_double((long long)wmin_bits[4 * b]);
+    const bool empty = nn < 0.5 * wm * wm * wm;
+    B[2 * ((long long)b * ntrip + t)] = empty ? __builtin_nan("") : re / (norm * nn);
+    B[2 * ((long long)b * ntrip + t) + 1] = empty ? __builtin_nan("") : im / (norm * nn);
+    if (N) N[(long long)b * ntrip + t] = nn;
+  }
+}
+
 // abs_counts: N_t alone from the weight-set partials.
 __global__ void __launch_bounds__(kFinBlock)
 counts_kernel(const double* __restrict__ part64, int nblk64, const int* __restrict__ pos64, int ntrip,
@@ -137,9 +172,10 @@ abs_status launch_contract(const abs_plan_s* p, int kind, int waves, const void*
 
 // Data sets (FP32) for `batch` grids, then `nisets` weight sets (FP64); partials of
 // the data sets first, weight sets after them.
+// batch: data sets (spg per grid: 1, or 4 for complex input).
 abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batch, int dtype,
                                    const void* grids, const float* w, int w_batched, char* work,
-                                   hipStream_t st, const WeightMod* mod) {
+                                   hipStream_t st, const WeightMod* mod, int spg = 1) {
   double* part = reinterpret_cast<double*>(work + wl.part);
   const long long npix = (long long)p->n * p->n;
   unsigned long long* wmin = reinterpret_cast<unsigned long long*>(work + wl.wmin);
@@ -151,7 +187,7 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
     float2* Z = reinterpret_cast<float2*>(work + wl.zd);
     float* F = reinterpret_cast<float*>(work + wl.fd);
     prof_begin(p, ABS_STAGE_COLPASS, st);
-    if (launch_colpass_data(p, grids, dtype, w, w_batched, batch, work + wl.xc, Z, wl.zset, wmin, st) !=
+    if (launch_colpass_data(p, grids, dtype, w, w_batched, batch, work + wl.xc, Z, wl.zset, wmin, st, spg) !=
         hipSuccess)
       return ABS_ERR_DEVICE;
     prof_end(p, ABS_STAGE_COLPASS, st);
@@ -339,6 +375,38 @@ abs_status abs_estimate(abs_plan_t p, int32_t batch, int32_t dtype, const void* 
   if (work_bytes < wl.total) return ABS_ERR_NOMEM;
   return estimate_on(p, wl, batch, dtype, grids, w, w_batched, n_given, static_cast<char*>(work), B, N,
                      static_cast<hipStream_t>(stream));
+}
+
+abs_status abs_estimate_complex_workspace(abs_plan_t p, int32_t batch, int32_t w_batched, int32_t have_counts,
+                                          size_t* bytes) {
+  if (!p || !bytes || batch < 0 || batch > p->max_batch) return ABS_ERR_INVALID;
+  *bytes = work_layout(p, batch, w_batched, have_counts, 4).total;
+  return ABS_OK;
+}
+
+abs_status abs_estimate_complex(abs_plan_t p, int32_t batch, int32_t dtype, const void* grids, const float* w,
+                                int32_t w_batched, const double* n_given, void* work, size_t work_bytes,
+                                double* B, double* N, void* stream) {
+  abs_status s = check_estimate_args(p, batch, dtype, grids, w, w_batched, n_given, B);
+  if (s != ABS_OK) return s;
+  if (!work || (reinterpret_cast<uintptr_t>(work) & 15)) return ABS_ERR_INVALID;
+  const WorkLayout wl = work_layout(p, batch, w_batched, n_given != nullptr, 4);
+  if (work_bytes < wl.total) return ABS_ERR_NOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* wk = static_cast<char*>(work);
+  (void)hipGetLastError();
+  s = run_fields_and_contract(p, wl, 4 * batch, dtype, grids, w, w_batched, wk, st, nullptr, 4);
+  if (s != ABS_OK) return s;
+  const char* base = static_cast<const char*>(p->dev);
+  const int* pos = p->precision == ABS_FP32 ? reinterpret_cast<const int*>(base + p->dl.pos32) : nullptr;
+  const int* pos64 = reinterpret_cast<const int*>(base + p->dl.pos64);
+  const dim3 g((unsigned)((p->ntrip + 63) / 64), (unsigned)batch);
+  finalize_complex_kernel<<<g, kFinBlock, 0, st>>>(
+      reinterpret_cast<const double*>(wk + wl.part), wl.partset, p->nblk, pos,
+      reinterpret_cast<const double*>(wk + wl.part64), wl.partset64, p->nblk64, pos64, (int)p->ntrip, wl.nisets,
+      n_given, reinterpret_cast<const unsigned long long*>(wk + wl.wmin), 1.0 / ((double)p->n * (double)p->n),
+      p->norm, B, N);
+  return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
 
 abs_status abs_estimate_noalloc(abs_plan_t p, int32_t batch, int32_t dtype, const void* grids,

@@ -414,19 +414,25 @@ template <> struct HermT<false> { using T = double; };
 // contiguous), as a running minimum of FP64 bit patterns in wmin[set] (non-negative
 // doubles order like their bits; the caller sets it to +inf first).  Y is even, so the
 // half plane gx >= 0 holds every value.
+//
+// Complex input (spg = 4 data sets per grid): set 4 b + v of grid b holds, for v = 0 .. 3,
+// H, G, H + G and H - G, where H is the Hermitian part above and G = (W V(g) - conj(W V(-g)))
+// / (2 i) the anti-Hermitian part divided by i (Hermitian as well), so W V = H + i G and
+// every set's field is real (abs_estimate_complex combines their triple sums).
 template <bool DATA, typename GT>
 __global__ void __launch_bounds__(kBlock)
-herm_kernel(const GT* __restrict__ grids, const float* __restrict__ w, int w_batched, int wmode,
+herm_kernel(const GT* __restrict__ grids, const float* __restrict__ w, int w_batched, int spg, int wmode,
             int n, int hm, int lc, double lo2, double hi2, typename HermT<DATA>::T* __restrict__ xc,
             unsigned long long* __restrict__ wmin, WeightMod mod) {
   using OT = typename HermT<DATA>::T;
   __shared__ OT tile[kHy][kHx + 1];
   __shared__ double wred[kBlock / 64];
   const int set = blockIdx.z;
+  const int gi = set / spg, part = set - gi * spg;   // grid and, for complex input, variant
   const int gx0 = blockIdx.x * kHx, gy0 = blockIdx.y * kHy - hm;
   const long long nn = (long long)n * n;
-  const GT* __restrict__ gs = DATA ? grids + (long long)set * nn : nullptr;
-  const float* __restrict__ ws = (w && w_batched) ? w + (long long)set * nn : w;
+  const GT* __restrict__ gs = DATA ? grids + (long long)gi * nn : nullptr;
+  const float* __restrict__ ws = (w && w_batched) ? w + (long long)gi * nn : w;
   const int tx = threadIdx.x & (kHx - 1), ty = threadIdx.x / kHx;
   double ymin = __builtin_inf();
   for (int yy = ty; yy < kHy; yy += kBlock / kHx) {
@@ -447,7 +453,13 @@ herm_kernel(const GT* __restrict__ grids, const float* __restrict__ w, int w_bat
       if constexpr (DATA) {
         const float w0 = weight_of<float>(ws, wmode, i0), w1 = weight_of<float>(ws, wmode, i1);
         const float2 a = load_vis(gs, i0), b = load_vis(gs, i1);
-        v = make_float2(0.5f * (w0 * a.x + w1 * b.x), 0.5f * (w0 * a.y - w1 * b.y));
+        const float2 h = make_float2(0.5f * (w0 * a.x + w1 * b.x), 0.5f * (w0 * a.y - w1 * b.y));
+        if (spg == 1 || part == 0) {
+          v = h;
+        } else {
+          const float2 q = make_float2(0.5f * (w0 * a.y + w1 * b.y), -0.5f * (w0 * a.x - w1 * b.x));
+          v = part == 1 ? q : part == 2 ? make_float2(h.x + q.x, h.y + q.y) : make_float2(h.x - q.x, h.y - q.y);
+        }
       } else {
         v = y;
       }
@@ -576,10 +588,10 @@ constexpr int col_tiles_per_block(int log2n) { return log2n <= 10 ? 1 : 2; }
 template <bool DATA, typename GT>
 hipError_t launch_herm(const abs_plan_s* p, const GT* grids, const float* w, int w_batched, int nsets,
                        typename HermT<DATA>::T* xc, unsigned long long* wmin, hipStream_t st,
-                       const WeightMod* mod = nullptr) {
+                       const WeightMod* mod = nullptr, int spg = 1) {
   const int hm = p->hmax, lc = 2 * p->hmax + 1;
   const dim3 grid((unsigned)((hm + kHx) / kHx), (unsigned)((lc + kHy - 1) / kHy), (unsigned)nsets);
-  herm_kernel<DATA, GT><<<grid, kBlock, 0, st>>>(grids, w, w_batched, p->wmode, p->n, hm, lc, p->lo2[0],
+  herm_kernel<DATA, GT><<<grid, kBlock, 0, st>>>(grids, w, w_batched, spg, p->wmode, p->n, hm, lc, p->lo2[0],
                                                  p->hi2[p->nb - 1], xc, wmin, mod ? *mod : WeightMod{});
   return hipGetLastError();
 }
@@ -628,15 +640,15 @@ hipError_t launch_colpass(const abs_plan_s* p, int nsets, const typename HermT<s
 
 hipError_t launch_colpass_data(const abs_plan_s* p, const void* grids, int dtype, const float* w,
                                int w_batched, int batch, void* xc, float2* Z, long long zset,
-                               unsigned long long* wmin, hipStream_t st) {
+                               unsigned long long* wmin, hipStream_t st, int spg) {
   const char* base = static_cast<const char*>(p->dev);
   const float2* tw = reinterpret_cast<const float2*>(base + p->dl.tw);
   float2* x = static_cast<float2*>(xc);
   hipError_t e = dtype == ABS_C128
                      ? launch_herm<true, double2>(p, static_cast<const double2*>(grids), w, w_batched, batch, x,
-                                                  wmin, st)
+                                                  wmin, st, nullptr, spg)
                      : launch_herm<true, float2>(p, static_cast<const float2*>(grids), w, w_batched, batch, x,
-                                                 wmin, st);
+                                                 wmin, st, nullptr, spg);
   if (e != hipSuccess) return e;
   return launch_colpass<float>(p, batch, x, Z, zset, tw, st);
 }

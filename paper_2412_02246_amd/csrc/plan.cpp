@@ -145,9 +145,13 @@ int ilog2(int v) {
 
 namespace abs_impl {
 
-WorkLayout work_layout(const abs_plan_s* p, int batch, int w_batched, int have_counts) {
+WorkLayout work_layout(const abs_plan_s* p, int grids, int w_batched, int have_counts, int spg) {
   WorkLayout w{};
-  w.nisets = have_counts ? 0 : ((w_batched && p->wmode != ABS_W_UNIT) ? batch : 1);
+  // spg data sets per grid (4 for complex input: see abs_estimate_complex), one weight set
+  // per grid with batched weights, else one (none with cached counts)
+  w.nisets = have_counts ? 0 : ((w_batched && p->wmode != ABS_W_UNIT) ? grids : 1);
+  const int batch = grids * spg;
+  w.ndsets = batch;
   w.nsets = batch + w.nisets;
   const int64_t n = p->n;
   w.zset = n * p->ncols;

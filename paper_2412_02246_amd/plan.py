@@ -189,6 +189,30 @@ class Plan:
                 "abs_estimate")
         return B, N
 
+    def estimate_complex(self, grids, w=None, w_batched=False, n_given=None, stream=None):
+        """Complex B (and N) for general complex grids, without Hermitian symmetrisation:
+        (B complex128 [batch][ntrip], N float64 [batch][ntrip])."""
+        import torch
+        if grids.dim() == 2:
+            grids = grids.unsqueeze(0)
+        dtype = {torch.complex64: L.C64, torch.complex128: L.C128}.get(grids.dtype)
+        if dtype is None or not grids.is_contiguous() or tuple(grids.shape[1:]) != (self.n, self.n):
+            raise ValueError("grids must be contiguous complex64 / complex128 [batch][%d][%d]" % (self.n, self.n))
+        batch = grids.shape[0]
+        if w is not None and (w.dtype != torch.float32 or not w.is_contiguous()):
+            raise TypeError("w must be a contiguous float32 tensor")
+        b = ctypes.c_size_t()
+        L.check(L.lib().abs_estimate_complex_workspace(self.handle, batch, int(bool(w_batched)),
+                                                       int(n_given is not None), ctypes.byref(b)),
+                "abs_estimate_complex_workspace")
+        work = self._workspace(b.value)
+        B = torch.empty((batch, self.ntrip, 2), dtype=torch.float64, device=grids.device)
+        N = torch.empty((batch, self.ntrip), dtype=torch.float64, device=grids.device)
+        L.check(L.lib().abs_estimate_complex(self.handle, batch, dtype, _ptr(grids), _ptr(w), int(bool(w_batched)),
+                                             _ptr(n_given), _ptr(work), work.numel(), _ptr(B), _ptr(N),
+                                             _stream(stream)), "abs_estimate_complex")
+        return torch.view_as_complex(B), N
+
     def counts(self, w=None, stream=None, work=None):
         import torch
         if work is None:

@@ -156,3 +156,49 @@ def test_subset_estimate_matches_full():
     part = estimator.estimate_subset(V, W, edges, 2.0, sub, wmode=GIVEN)
     for key in ("S", "N", "B", "rhoS", "rhoN"):
         assert np.allclose(part[key], full[key][::3], rtol=1e-10, atol=1e-12), key
+
+
+@pytest.mark.parametrize("n,edges", CASES)
+def test_complex_input_equals_brute_force(n, edges):
+    """General complex input (no Hermitian symmetrisation): the complex triangle sum of
+    X = W V by direct enumeration, for the FFT route of estimate_complex."""
+    V, W = _random_case(n, 300 + n)
+    trips = plan.prefilter_triplets(edges)
+    out = estimator.estimate_complex(V, W, edges, 1.0, wmode=GIVEN, trips=trips)
+    X = W * V
+    S_b = brute.triangle_sums(X, n, edges, trips, cyclic=False)
+    scale = np.abs(X).max() ** 3 * max(1, len(trips))
+    assert np.allclose(out["S"], S_b, rtol=1e-10, atol=1e-12 * scale)
+    assert np.any(np.abs(S_b.imag) > 1e-3 * np.abs(S_b.real).max())   # genuinely complex
+
+
+def test_complex_input_reduces_to_the_hermitian_estimator():
+    n, edges = 32, [1.5, 2.7, 4.1, 6.0, 8.2, 10.6]
+    V, W = _random_case(n, 77, hermitian=True)
+    trips = plan.prefilter_triplets(edges)
+    c = estimator.estimate_complex(V, W, edges, 0.3, wmode=GIVEN, trips=trips)
+    r = estimator.estimate(V, W, edges, 0.3, wmode=GIVEN, trips=trips)
+    ok = ~np.isnan(r["B"])
+    assert np.allclose(c["B"].real[ok], r["B"][ok], rtol=1e-9, atol=1e-12 * np.abs(r["B"][ok]).max())
+    assert np.all(np.abs(c["B"].imag[ok]) <= 1e-9 * np.abs(r["B"][ok]).max())
+    # scaling by a complex constant multiplies B by its cube
+    z = 0.7 - 1.3j
+    c2 = estimator.estimate_complex(z * V, W, edges, 0.3, wmode=GIVEN, trips=trips)
+    assert np.allclose(c2["B"][ok], z ** 3 * c["B"][ok], rtol=1e-9)
+
+
+def test_half_plane_input_gives_the_full_plane_estimate():
+    """Grids and weights supplied on a half plane only (one cell of every (g, -g) pair, the
+    other zero): their Hermitian parts are half the full ones on every ring cell, S_t and N_t
+    scale by 1/8 and B_t is unchanged."""
+    n, edges = 32, [1.5, 2.7, 4.1, 6.0, 8.2, 10.6]
+    V, W = _random_case(n, 5, hermitian=True)
+    g = plan.signed_index(n)
+    gx, gy = np.meshgrid(g, g)
+    half = (gy > 0) | ((gy == 0) & (gx > 0))
+    trips = plan.prefilter_triplets(edges)
+    full = estimator.estimate(V, W, edges, 1.0, wmode=GIVEN, trips=trips)
+    hp = estimator.estimate(np.where(half, V, 0), np.where(half, W, 0), edges, 1.0, wmode=GIVEN, trips=trips)
+    ok = ~np.isnan(full["B"])
+    assert np.allclose(hp["N"], full["N"] / 8, rtol=1e-10, atol=1e-12 * np.abs(full["N"]).max())
+    assert np.allclose(hp["B"][ok], full["B"][ok], rtol=1e-9, atol=1e-12 * np.abs(full["B"][ok]).max())
