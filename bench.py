@@ -86,7 +86,7 @@ PEAK_HBM = 8.0e12
 # WRITE_SIZE passes scaled by a 1 GiB copy (2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE), for the
 # kernel as it stands in this tree and the workload's default batch (profiles/counters_mwa8192_batch8_fp32.md); keyed by
 # (workload, precision).  A workload or precision without an entry reports null.
-MEASURED_TRAFFIC = {("mwa8192", "fp32"): 417.4e9}
+MEASURED_TRAFFIC = {}
 
 
 def edges_of(W):
@@ -395,36 +395,44 @@ def measure(name, precision, plan, uv_d, vis_d, steps, warmup, log=sys.stderr):
     grids_s = batch * steps / dt
     print("bench: %s %s %.3f ms/step, %.2f grids/s, contraction %.3f ms" % (name, precision, ms, grids_s, con_ms),
           file=log, flush=True)
-    nsets = batch   # the contraction launch timed is the data-set one (the weight set runs in FP64)
+    nsets = batch   # the contraction launches timed are the data-set ones (the weight set runs in FP64)
     # algorithmic flops per pixel: two per triplet (product with the pair, add) plus the
     # pair products, counted for the orientation with the fewest distinct pairs ((i, j) or
-    # (j, k) of i <= j <= k)
-    ijk = np.asarray(plan.triplets).reshape(-1, 3)
-    pairs = min(len({(int(x[0]), int(x[1])) for x in ijk}), len({(int(x[1]), int(x[2])) for x in ijk}))
-    flops = float(nsets) * n * n * (pairs + 2 * plan.ntrip)
+    # (j, k) of i <= j <= k); each resolution level sums its triplets over its own m^2
+    # pixels (the least work that level's sum needs), so the launch's flops are the sum
+    # over levels; "flops_per_launch_at_n" counts every triplet over n^2 pixels instead
+    def level_flops(ijk, npix):
+        pairs = min(len({(int(x[0]), int(x[1])) for x in ijk}), len({(int(x[1]), int(x[2])) for x in ijk}))
+        return float(nsets) * npix * (pairs + 2 * len(ijk))
+    ijk_all = np.asarray(plan.triplets).reshape(-1, 3)
+    flops = sum(level_flops(ijk_all[lv["tmap"]], lv["m"] ** 2) for lv in plan.levels)
+    flops_n = level_flops(ijk_all, n * n)
     achieved = flops / (con_ms * 1e-3)
     traffic = MEASURED_TRAFFIC.get((name, precision)) if batch == W["batch"] else None
     if precision == "fp32":
         roof = {"kernel": "abs_contract (plan-specialised FP32 triplet contraction)", "bound": "alu",
                 "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic, "avg_ms": con_ms,
-                "flops_per_launch": flops,
+                "flops_per_launch": flops, "flops_per_launch_at_n": flops_n,
+                "levels": [[lv["m"], lv["ntrip"]] for lv in plan.levels],
                 "peak_nonpacked_valu": PEAK_VALU_NONPACKED / 1e12,
                 "frac_nonpacked_valu": achieved / PEAK_VALU_NONPACKED}
     else:
-        issued = float(nsets) * n * n * plan.mfma_tiles * 3 * 512   # 3 split MFMAs per tile
+        # 3 split MFMAs per 16 x 16 tile and pixel, each level's tiles over its m^2 pixels
+        issued = float(nsets) * sum(lv["mfma_tiles"] * lv["m"] ** 2 for lv in plan.levels) * 3 * 512
         roof = {"kernel": "mfma_contract_kernel (%s triplet contraction)" % precision, "bound": "mfma",
                 "achieved": achieved / 1e12, "peak": PEAK_MFMA_16BIT / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_MFMA_16BIT, "traffic": traffic, "avg_ms": con_ms,
-                "flops_per_launch": flops,
+                "flops_per_launch": flops, "flops_per_launch_at_n": flops_n,
+                "levels": [[lv["m"], lv["ntrip"]] for lv in plan.levels],
                 "mfma_issued_tflops": issued / (con_ms * 1e-3) / 1e12,
                 "mfma_issued_frac": issued / (con_ms * 1e-3) / PEAK_MFMA_16BIT}
     # HBM fraction of the gridding and FFT stages, from HIP events the library records
     # around each stage on a few extra (untimed) steps; algorithmic bytes per step:
     #   gridding: uv read once (16 B a visibility), values read (8 B a visibility and
     #             realisation), grids written (8 B a cell and realisation), counts (4 B a cell)
-    #   column pass: the pruned intermediate written (8 B x n x ncols a set)
-    #   row pass: that intermediate read and the FP32 fields written (4 B x nbins x n^2 a set)
+    #   column pass: the pruned intermediate written (8 B x m x ncols a set and level)
+    #   row pass: that intermediate read and the FP32 fields written (4 B x nbins x m^2 a set and level)
     stages = {}
     nprof = 3
     evs = {st: HipEvents(nprof) for st in (L.STAGE_GRID, L.STAGE_COLPASS, L.STAGE_ROWPASS)}
@@ -433,10 +441,12 @@ def measure(name, precision, plan, uv_d, vis_d, steps, warmup, log=sys.stderr):
             L.lib().abs_profile(plan.handle, st, *e.pair(k))
         step()
     torch.cuda.synchronize()
-    zbytes = 8.0 * n * plan.ncols * batch
+    # column pass and row pass of every resolution level (m, its rings and columns)
+    zbytes = sum(8.0 * lv["m"] * lv["ncols"] for lv in plan.levels) * batch
+    fbytes = sum(4.0 * lv["nbins"] * lv["m"] ** 2 for lv in plan.levels) * batch
     alg = {L.STAGE_GRID: 16.0 * nvis + batch * (8.0 * nvis + 8.0 * n * n) + 4.0 * n * n,
            L.STAGE_COLPASS: zbytes,
-           L.STAGE_ROWPASS: zbytes + 4.0 * nb * n * n * batch}
+           L.STAGE_ROWPASS: zbytes + fbytes}
     tot_b = tot_ms = 0.0
     for st, sname in ((L.STAGE_GRID, "gridding"), (L.STAGE_COLPASS, "column_pass"), (L.STAGE_ROWPASS, "row_pass")):
         L.lib().abs_profile(plan.handle, st, None, None)

@@ -71,6 +71,8 @@ enum { ABS_NEAREST = 0, ABS_GAUSS7 = 1 };
 /* plan flags */
 #define ABS_ALLOW_WRAP 1u /* accept rings beyond n/3: triangles then close modulo n */
 #define ABS_ALLOW_DC 2u   /* accept edges[0] == 0, i.e. a ring holding g = 0 (tests) */
+#define ABS_EVERY_LEVEL 4u /* run every resolution level n/2 .. n/levels that holds a    */
+                           /* triplet, instead of the set the cost model picks (tests) */
 
 typedef struct abs_plan_s* abs_plan_t;
 
@@ -87,7 +89,15 @@ typedef struct abs_plan_desc {
   int32_t precision;    /* ABS_FP32, ABS_BF16X3 or ABS_FP16X3                          */
   int32_t wmode;        /* ABS_W_UNIT, ABS_W_INV_COUNT or ABS_W_GIVEN                  */
   int32_t max_batch;    /* largest batch abs_estimate / abs_grid will be given (>= 1) */
-  uint32_t flags;       /* ABS_ALLOW_WRAP | ABS_ALLOW_DC                               */
+  uint32_t flags;       /* ABS_ALLOW_WRAP | ABS_ALLOW_DC | ABS_EVERY_LEVEL             */
+  int32_t levels;       /* largest n / m of a resolution level: a power of two; 1 runs */
+                        /* every triplet at n; 0 selects 4 (2 for ABS_BF16X3).  A     */
+                        /* triplet whose rings all lie within |g_x|, |g_y| < m/3       */
+                        /* closes exactly the same triangles on an m x m grid (Eqs.    */
+                        /* 10-12 summed over m^2 pixels), so it may be evaluated       */
+                        /* there; the plan picks its levels by a cost model.  Larger   */
+                        /* ratios save more work but average rounding errors over      */
+                        /* fewer pixels (a level's error grows about as n / m)         */
 } abs_plan_desc;
 
 typedef struct abs_plan_info {
@@ -107,6 +117,9 @@ typedef struct abs_plan_info {
   int32_t weight_parts, weight_jk, weight_block, weight_waves;  /* same, FP64 kernel  */
   int32_t mfma_tiles_per_wave;  /* precision form: output tiles a wave owns (2 or 12)  */
   int32_t mfma_depth;           /* precision form: chunks of loads in flight (1 or 4)  */
+  int32_t nlevels;              /* resolution levels the plan runs (1: none below n);  */
+                                /* with several, the variants above are the first     */
+                                /* (largest) level's and the counts are summed        */
 } abs_plan_info;
 
 /* Build a plan on the host: rings (Sec. 2), the triplet list with an exact lattice
@@ -114,12 +127,20 @@ typedef struct abs_plan_info {
  * triangle), per-triplet labels and the device tables.  No HIP call is made.
  * Errors: ABS_ERR_INVALID (n not a power of two in [16, 8192], nbins out of range,
  * edges not strictly increasing or negative, edges[0] == 0 without ABS_ALLOW_DC,
- * bad mode, max_batch < 1), ABS_ERR_ALIAS (edges[nbins] > n/3 without ABS_ALLOW_WRAP,
+ * bad mode, max_batch < 1, levels not 0 or a power of two <= n), ABS_ERR_ALIAS (edges[nbins] > n/3 without ABS_ALLOW_WRAP,
  * or any ring reaching |g| >= n/2), ABS_ERR_EMPTY, ABS_ERR_NOMEM. */
 abs_status abs_plan(const abs_plan_desc* desc, abs_plan_t* out);
 
 /* Sizes and counts of a plan (host only). */
 abs_status abs_plan_info_get(abs_plan_t plan, abs_plan_info* out);
+
+/* One resolution level of a plan (host only), 0 <= level < nlevels, largest first: its
+ * grid side m (info->n), rings 0 .. nbins-1 it transforms, its triplets (ntrip, npairs)
+ * and code variants; plan_bytes is 0 (the tables live in the parent's memory).  tmap:
+ * host int32 [info->ntrip], the index in the plan's triplet list of each of the level's
+ * triplets (ascending), or NULL.  A plan without levels reports itself as level 0.
+ * Errors: ABS_ERR_INVALID. */
+abs_status abs_plan_level_info(abs_plan_t plan, int32_t level, abs_plan_info* info, int32_t* tmap);
 
 /* Host copies of the triplet list, labels and ring radii; any pointer may be NULL.
  *   ijk      int32  [ntrip][3]  ring indices i <= j <= k

@@ -13,7 +13,7 @@ W_UNIT, W_INV_COUNT, W_GIVEN = 0, 1, 2
 C64, C128 = 0, 1
 NEAREST, GAUSS7 = 0, 1
 STAGE_CONTRACT, STAGE_COLPASS, STAGE_ROWPASS, STAGE_GRID = 0, 1, 2, 3
-ALLOW_WRAP, ALLOW_DC = 1, 2
+ALLOW_WRAP, ALLOW_DC, EVERY_LEVEL = 1, 2, 4
 
 
 class PlanDesc(ctypes.Structure):
@@ -21,7 +21,7 @@ class PlanDesc(ctypes.Structure):
                 ("edges", ctypes.POINTER(ctypes.c_double)), ("du", ctypes.c_double),
                 ("norm", ctypes.c_double), ("theta0", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("wmode", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("max_batch", ctypes.c_int32), ("flags", ctypes.c_uint32), ("levels", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -33,7 +33,8 @@ class PlanInfo(ctypes.Structure):
                 ("contract_block", ctypes.c_int32), ("contract_waves", ctypes.c_int32),
                 ("weight_parts", ctypes.c_int32), ("weight_jk", ctypes.c_int32),
                 ("weight_block", ctypes.c_int32), ("weight_waves", ctypes.c_int32),
-                ("mfma_tiles_per_wave", ctypes.c_int32), ("mfma_depth", ctypes.c_int32)]
+                ("mfma_tiles_per_wave", ctypes.c_int32), ("mfma_depth", ctypes.c_int32),
+                ("nlevels", ctypes.c_int32)]
 
 
 class AbsError(RuntimeError):
@@ -60,6 +61,7 @@ def lib():
     sig = {
         "abs_plan": [ctypes.POINTER(PlanDesc), ctypes.POINTER(_P)],
         "abs_plan_info_get": [_P, ctypes.POINTER(PlanInfo)],
+        "abs_plan_level_info": [_P, i32, ctypes.POINTER(PlanInfo), _P],
         "abs_plan_triplets": [_P, _P, _P, _P],
         "abs_plan_compile": [_P],
         "abs_plan_compile_part": [_P, i32],

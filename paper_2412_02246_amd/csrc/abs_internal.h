@@ -41,6 +41,7 @@ struct DevLayout {
   size_t tw, tw64, bins, tiles;
   size_t pt_pairs, mt_ptile, mt_bins, mt_trip, wave_tiles;   // precision-form tables
   size_t pos32, pos64;   // position of each triplet in the FP32 / FP64 kernel's partials
+  size_t tmap;           // level plans: index of each of their triplets in the parent's list
   size_t total;
 };
 
@@ -66,6 +67,10 @@ struct WorkLayout {
   int64_t fset64;     // values per set of weight fields (nbins * npix64)
   int64_t partset;    // doubles per data set of contraction partials (nblk * ntrip)
   int64_t partset64;  // doubles per weight set (nblk64 * ntrip)
+  // plans with resolution levels: each level's own layout (its xc and wmin unused) and
+  // its offset in the workspace; xc and wmin above are the parent's
+  std::vector<WorkLayout> lv;
+  std::vector<size_t> lvbase;
 };
 
 }  // namespace abs_impl
@@ -116,6 +121,20 @@ struct abs_plan_s {
   // all pixels is block 0 plus twice the others.
   int64_t npix64 = 0;
   std::vector<abs_impl::JitPart> parts;   // contraction code, compiled per part
+  // Resolution levels.  A triplet whose rings all hold |g_x|, |g_y| < m/3 closes exactly
+  // the same triangles on an m x m periodic grid as on the n x n one (a sum of three
+  // such cells is zero modulo m only if it is zero), and its ring fields on the m grid
+  // are those on the n grid sampled every n/m pixels.  Such a plan runs its triplets in
+  // level plans (`lv`, largest m first), each over m^2
+  // pixels with the rings 0 .. K-1 its triplets use; the parent forms the Hermitian part once
+  // (its hmax covers every level) and the smallest ring weight over all rings (for the
+  // empty-triplet rule), and owns no kernel code of its own.
+  int max_ratio = 1;                     // largest n / m allowed for a level
+  bool is_level = false;                 // a level plan of some parent
+  std::vector<abs_plan_s*> lv;           // level plans (empty: the plan runs at n itself)
+  std::vector<int32_t> tmap;             // level plan: parent index of each of its triplets
+  int xc_hm = 0;                         // half extent of the Hermitian part its column pass reads
+  size_t dev_off = 0;                    // level plan: offset of its tables in the parent's memory
   // device binding
   abs_impl::DevLayout dl{};
   void* dev = nullptr;
@@ -137,6 +156,18 @@ struct WeightMod {
 bool build_jit_source(abs_plan_s* p);
 abs_status compile_jit(abs_plan_s* p, int part);
 uint64_t jit_key(const abs_plan_s* p, int part);
+// The plans that run kernels: the level plans, or the plan itself.
+inline std::vector<abs_plan_s*> run_plans(abs_plan_s* p) {
+  return p->lv.empty() ? std::vector<abs_plan_s*>{p} : p->lv;
+}
+inline std::vector<const abs_plan_s*> run_plans(const abs_plan_s* p) {
+  if (p->lv.empty()) return {p};
+  return std::vector<const abs_plan_s*>(p->lv.begin(), p->lv.end());
+}
+// Part `k` of the plan's code counted over its run plans: the owning plan and the index
+// there (nullptr when out of range).
+abs_plan_s* part_owner(abs_plan_s* p, int k, int* local);
+void destroy_plan(abs_plan_s* p);
 WorkLayout work_layout(const abs_plan_s* p, int grids, int w_batched, int have_counts, int spg = 1);
 void build_mfma_tables(abs_plan_s* p);
 // estimate.hip

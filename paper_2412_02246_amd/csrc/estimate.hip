@@ -12,12 +12,14 @@
 #include "abs_internal.h"
 
 namespace abs_impl {
-hipError_t launch_colpass_data(const abs_plan_s* p, const void* grids, int dtype, const float* w,
-                               int w_batched, int batch, void* xc, float2* Z, long long zset,
-                               unsigned long long* wmin, hipStream_t st, int spg);
-hipError_t launch_colpass_weight(const abs_plan_s* p, const float* w, int w_batched, int nsets,
-                                 void* xc, double2* Z, long long zset, unsigned long long* wmin,
-                                 hipStream_t st, const WeightMod* mod);
+hipError_t launch_herm_data(const abs_plan_s* p, const void* grids, int dtype, const float* w, int w_batched,
+                            int batch, void* xc, unsigned long long* wmin, hipStream_t st, int spg);
+hipError_t launch_herm_weight(const abs_plan_s* p, const float* w, int w_batched, int nsets, void* xc,
+                              unsigned long long* wmin, hipStream_t st, const WeightMod* mod);
+hipError_t launch_colpass_f32(const abs_plan_s* p, int nsets, const void* xc, float2* Z, long long zset,
+                              hipStream_t st);
+hipError_t launch_colpass_f64(const abs_plan_s* p, int nsets, const void* xc, double2* Z, long long zset,
+                              hipStream_t st);
 hipError_t launch_rowpass_f32(const abs_plan_s* p, int nsets, const float2* Z, long long zset,
                               float* F, long long fset, unsigned* fmax_bits, hipStream_t st);
 hipError_t launch_mfma_contract(const abs_plan_s* p, const float* F, long long fset, int nsets,
@@ -70,7 +72,9 @@ __device__ __forceinline__ double sum_partials_half(const double* __restrict__ p
 
 // B[b][t] = S / (A N), S and N the per-triangle sums: workgroup partials are added
 // in FP64 in a fixed order and divided by n^2 (the sum over pixels of a product of
-// three DFTs counts every closed triangle n^2 times).  Block: 64 triplets of grid b.
+// three DFTs counts every closed triangle n^2 times; m^2 for a level of size m).
+// Block: 64 triplets of grid b.  A level plan's triplet t is the parent's tmap[t]: its
+// cached count, B and N are at that index of rows of ntrip_out values.
 // Empty triplets: with non-negative weights each closed triangle whose three cells carry
 // weight adds at least w_min^3 to N_t (w_min: the smallest non-zero ring-cell weight of
 // grid b, recorded by the Hermitian-part pass), so N_t < w_min^3 / 2 means no weighted
@@ -80,21 +84,23 @@ finalize_kernel(const double* __restrict__ part, long long partset, int nblk, co
                 const double* __restrict__ part64, long long partset64, int nblk64,
                 const int* __restrict__ pos64, int ntrip, int batch, int nisets,
                 const double* __restrict__ n_given, const unsigned long long* __restrict__ wmin_bits,
-                double inv_npix, double norm, double* __restrict__ B, double* __restrict__ N) {
+                double inv_npix, double norm, const int* __restrict__ tmap, int ntrip_out,
+                double* __restrict__ B, double* __restrict__ N) {
   const int t = blockIdx.x * 64 + (threadIdx.x & 63);
   const int b = blockIdx.y;
+  const int to = t < ntrip && tmap ? tmap[t] : t;
   const double s = sum_partials(part + (long long)b * partset, nblk, ntrip, pos, t) * inv_npix;
   double nn;
   if (nisets == 0) {
-    nn = t < ntrip ? n_given[t] : 0.0;
+    nn = t < ntrip ? n_given[to] : 0.0;
   } else {
     const int is = nisets > 1 ? b : 0;
     nn = sum_partials_half(part64 + (long long)is * partset64, nblk64, ntrip, pos64, t) * inv_npix;
   }
   if (threadIdx.x < 64 && t < ntrip) {
     const double wm = __longlong_as_double((long long)wmin_bits[b]);
-    B[(long long)b * ntrip + t] = nn < 0.5 * wm * wm * wm ? __builtin_nan("") : s / (norm * nn);
-    if (N) N[(long long)b * ntrip + t] = nn;
+    B[(long long)b * ntrip_out + to] = nn < 0.5 * wm * wm * wm ? __builtin_nan("") : s / (norm * nn);
+    if (N) N[(long long)b * ntrip_out + to] = nn;
   }
 }
 
@@ -109,15 +115,17 @@ finalize_complex_kernel(const double* __restrict__ part, long long partset, int 
                         const double* __restrict__ part64, long long partset64, int nblk64,
                         const int* __restrict__ pos64, int ntrip, int nisets, const double* __restrict__ n_given,
                         const unsigned long long* __restrict__ wmin_bits, double inv_npix, double norm,
-                        double* __restrict__ B, double* __restrict__ N) {
+                        const int* __restrict__ tmap, int ntrip_out, double* __restrict__ B,
+                        double* __restrict__ N) {
   const int t = blockIdx.x * 64 + (threadIdx.x & 63);
   const int b = blockIdx.y;
+  const int to = t < ntrip && tmap ? tmap[t] : t;
   double T[4];
   for (int v = 0; v < 4; ++v)
     T[v] = sum_partials(part + (long long)(4 * b + v) * partset, nblk, ntrip, pos, t) * inv_npix;
   double nn;
   if (nisets == 0) {
-    nn = t < ntrip ? n_given[t] : 0.0;
+    nn = t < ntrip ? n_given[to] : 0.0;
   } else {
     const int is = nisets > 1 ? b : 0;
     nn = sum_partials_half(part64 + (long long)is * partset64, nblk64, ntrip, pos64, t) * inv_npix;
@@ -127,19 +135,19 @@ finalize_complex_kernel(const double* __restrict__ part, long long partset, int 
     const double im = 0.5 * (T[2] - T[3]) - 2.0 * T[1];
     const double wm = __longlong_as_double((long long)wmin_bits[4 * b]);
     const bool empty = nn < 0.5 * wm * wm * wm;
-    B[2 * ((long long)b * ntrip + t)] = empty ? __builtin_nan("") : re / (norm * nn);
-    B[2 * ((long long)b * ntrip + t) + 1] = empty ? __builtin_nan("") : im / (norm * nn);
-    if (N) N[(long long)b * ntrip + t] = nn;
+    B[2 * ((long long)b * ntrip_out + to)] = empty ? __builtin_nan("") : re / (norm * nn);
+    B[2 * ((long long)b * ntrip_out + to) + 1] = empty ? __builtin_nan("") : im / (norm * nn);
+    if (N) N[(long long)b * ntrip_out + to] = nn;
   }
 }
 
 // abs_counts: N_t alone from the weight-set partials.
 __global__ void __launch_bounds__(kFinBlock)
 counts_kernel(const double* __restrict__ part64, int nblk64, const int* __restrict__ pos64, int ntrip,
-              double inv_npix, double* __restrict__ N) {
+              double inv_npix, const int* __restrict__ tmap, double* __restrict__ N) {
   const int t = blockIdx.x * 64 + (threadIdx.x & 63);
   const double nn = sum_partials_half(part64, nblk64, ntrip, pos64, t) * inv_npix;
-  if (threadIdx.x < 64 && t < ntrip) N[t] = nn;
+  if (threadIdx.x < 64 && t < ntrip) N[tmap ? tmap[t] : t] = nn;
 }
 
 abs_status ensure_device(abs_plan_s* p) {
@@ -170,81 +178,126 @@ abs_status launch_contract(const abs_plan_s* p, int kind, int waves, const void*
   return ABS_OK;
 }
 
+// The plans that run kernels with their workspace layouts and bases: the level plans and
+// their parts of the workspace, or the plan itself and the whole workspace.
+struct RunLevel {
+  const abs_plan_s* q;
+  const WorkLayout* wl;
+  char* base;
+};
+std::vector<RunLevel> run_levels(const abs_plan_s* p, const WorkLayout& wl, char* work) {
+  std::vector<RunLevel> r;
+  if (p->lv.empty()) {
+    r.push_back({p, &wl, work});
+  } else {
+    for (size_t L = 0; L < p->lv.size(); ++L) r.push_back({p->lv[L], &wl.lv[L], work + wl.lvbase[L]});
+  }
+  return r;
+}
+
 // Data sets (FP32) for `batch` grids, then `nisets` weight sets (FP64); partials of
-// the data sets first, weight sets after them.
+// the data sets first, weight sets after them.  The Hermitian part (and each set's
+// smallest ring-cell weight) is formed once for the plan; every level plan transforms its
+// own rings from it at its own size and contracts its own triplets.  Stages run one after
+// the other over all levels, so that the timing hooks bracket whole stages.
 // batch: data sets (spg per grid: 1, or 4 for complex input).
 abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batch, int dtype,
                                    const void* grids, const float* w, int w_batched, char* work,
                                    hipStream_t st, const WeightMod* mod, int spg = 1) {
-  double* part = reinterpret_cast<double*>(work + wl.part);
-  const long long npix = (long long)p->n * p->n;
+  const std::vector<RunLevel> lv = run_levels(p, wl, work);
   unsigned long long* wmin = reinterpret_cast<unsigned long long*>(work + wl.wmin);
+  void* xc = work + wl.xc;
   {
     const int cnt = batch + wl.nisets;
     fill_u64_kernel<<<(cnt + kBlock - 1) / kBlock, kBlock, 0, st>>>(wmin, cnt, kInfBits);
   }
   if (batch > 0) {
-    float2* Z = reinterpret_cast<float2*>(work + wl.zd);
-    float* F = reinterpret_cast<float*>(work + wl.fd);
     prof_begin(p, ABS_STAGE_COLPASS, st);
-    if (launch_colpass_data(p, grids, dtype, w, w_batched, batch, work + wl.xc, Z, wl.zset, wmin, st, spg) !=
-        hipSuccess)
+    if (launch_herm_data(p, grids, dtype, w, w_batched, batch, xc, wmin, st, spg) != hipSuccess)
       return ABS_ERR_DEVICE;
+    for (const RunLevel& r : lv)
+      if (launch_colpass_f32(r.q, batch, xc, reinterpret_cast<float2*>(r.base + r.wl->zd), r.wl->zset, st) !=
+          hipSuccess)
+        return ABS_ERR_DEVICE;
     prof_end(p, ABS_STAGE_COLPASS, st);
     // FP16 splits need a power-of-two scale per (grid, ring): the row pass records max |F|
-    unsigned* fmax = nullptr;
-    if (p->precision == ABS_FP16X3) {
-      fmax = reinterpret_cast<unsigned*>(work + wl.fmax);
-      const int cnt = batch * p->nb;
-      fill_u32_kernel<<<(cnt + kBlock - 1) / kBlock, kBlock, 0, st>>>(fmax, cnt, 0u);
-    }
+    if (p->precision == ABS_FP16X3)
+      for (const RunLevel& r : lv) {
+        const int cnt = batch * r.q->nb;
+        fill_u32_kernel<<<(cnt + kBlock - 1) / kBlock, kBlock, 0, st>>>(
+            reinterpret_cast<unsigned*>(r.base + r.wl->fmax), cnt, 0u);
+      }
     prof_begin(p, ABS_STAGE_ROWPASS, st);
-    if (launch_rowpass_f32(p, batch, Z, wl.zset, F, wl.fset, fmax, st) != hipSuccess)
-      return ABS_ERR_DEVICE;
+    for (const RunLevel& r : lv) {
+      unsigned* fmax = p->precision == ABS_FP16X3 ? reinterpret_cast<unsigned*>(r.base + r.wl->fmax) : nullptr;
+      if (launch_rowpass_f32(r.q, batch, reinterpret_cast<const float2*>(r.base + r.wl->zd), r.wl->zset,
+                             reinterpret_cast<float*>(r.base + r.wl->fd), r.wl->fset, fmax, st) != hipSuccess)
+        return ABS_ERR_DEVICE;
+    }
     prof_end(p, ABS_STAGE_ROWPASS, st);
     prof_begin(p, ABS_STAGE_CONTRACT, st);
-    abs_status s;
-    if (p->precision == ABS_FP32)
-      s = launch_contract(p, 0, p->waves, F, wl.fset, npix, p->pix_per_block, p->nblk,
-                          (int)p->ntrip, batch, part, st);
-    else
-      s = launch_mfma_contract(p, F, wl.fset, batch, part, fmax, st) == hipSuccess ? ABS_OK
-                                                                                  : ABS_ERR_DEVICE;
+    for (const RunLevel& r : lv) {
+      const abs_plan_s* q = r.q;
+      const float* F = reinterpret_cast<const float*>(r.base + r.wl->fd);
+      double* part = reinterpret_cast<double*>(r.base + r.wl->part);
+      abs_status s;
+      if (p->precision == ABS_FP32) {
+        s = launch_contract(q, 0, q->waves, F, r.wl->fset, (long long)q->n * q->n, q->pix_per_block, q->nblk,
+                            (int)q->ntrip, batch, part, st);
+      } else {
+        const unsigned* fmax =
+            p->precision == ABS_FP16X3 ? reinterpret_cast<const unsigned*>(r.base + r.wl->fmax) : nullptr;
+        s = launch_mfma_contract(q, F, r.wl->fset, batch, part, fmax, st) == hipSuccess ? ABS_OK
+                                                                                       : ABS_ERR_DEVICE;
+      }
+      if (s != ABS_OK) return s;
+    }
     prof_end(p, ABS_STAGE_CONTRACT, st);
-    if (s != ABS_OK) return s;
   }
   if (wl.nisets > 0) {
-    double2* Z = reinterpret_cast<double2*>(work + wl.zi);
-    double* F = reinterpret_cast<double*>(work + wl.fi);
-    if (launch_colpass_weight(p, w, w_batched, wl.nisets, work + wl.xc, Z, wl.zset, wmin + batch, st, mod) !=
-        hipSuccess)
+    if (launch_herm_weight(p, w, w_batched, wl.nisets, xc, wmin + batch, st, mod) != hipSuccess)
       return ABS_ERR_DEVICE;
-    if (launch_rowpass_f64(p, wl.nisets, Z, wl.zset, F, wl.fset64, st) != hipSuccess)
-      return ABS_ERR_DEVICE;
-    return launch_contract(p, 1, p->waves64, F, wl.fset64, p->npix64, p->pix_per_block64,
-                           p->nblk64, (int)p->ntrip, wl.nisets,
-                           reinterpret_cast<double*>(work + wl.part64), st);
+    for (const RunLevel& r : lv)
+      if (launch_colpass_f64(r.q, wl.nisets, xc, reinterpret_cast<double2*>(r.base + r.wl->zi), r.wl->zset, st) !=
+          hipSuccess)
+        return ABS_ERR_DEVICE;
+    for (const RunLevel& r : lv)
+      if (launch_rowpass_f64(r.q, wl.nisets, reinterpret_cast<const double2*>(r.base + r.wl->zi), r.wl->zset,
+                             reinterpret_cast<double*>(r.base + r.wl->fi), r.wl->fset64, st) != hipSuccess)
+        return ABS_ERR_DEVICE;
+    for (const RunLevel& r : lv) {
+      const abs_plan_s* q = r.q;
+      const abs_status s = launch_contract(q, 1, q->waves64, r.base + r.wl->fi, r.wl->fset64, q->npix64,
+                                           q->pix_per_block64, q->nblk64, (int)q->ntrip, wl.nisets,
+                                           reinterpret_cast<double*>(r.base + r.wl->part64), st);
+      if (s != ABS_OK) return s;
+    }
   }
   return ABS_OK;
+}
+
+// Device tables of a run plan: partial positions and, for a level plan, its triplet map.
+const int* dev_pos32(const abs_plan_s* q) {
+  return q->precision == ABS_FP32 ? reinterpret_cast<const int*>(static_cast<const char*>(q->dev) + q->dl.pos32)
+                                  : nullptr;   // the precision form writes partials by triplet index
+}
+const int* dev_pos64(const abs_plan_s* q) {
+  return reinterpret_cast<const int*>(static_cast<const char*>(q->dev) + q->dl.pos64);
+}
+const int* dev_tmap(const abs_plan_s* q) {
+  return q->is_level ? reinterpret_cast<const int*>(static_cast<const char*>(q->dev) + q->dl.tmap) : nullptr;
 }
 
 }  // namespace abs_impl
 
 using namespace abs_impl;
 
-extern "C" {
+namespace abs_impl {
 
-abs_status abs_plan_bind(abs_plan_t p, void* mem, size_t bytes, void* stream) {
-  if (!p || !mem) return ABS_ERR_INVALID;
-  if (reinterpret_cast<uintptr_t>(mem) & 255) return ABS_ERR_INVALID;
-  if (bytes < p->dl.total) return ABS_ERR_NOMEM;
-  for (int k = 0; k < (int)p->parts.size(); ++k) {
-    const abs_status s = compile_jit(p, k);
-    if (s != ABS_OK) return s;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess) return ABS_ERR_DEVICE;
+// Load a run plan's compiled code and upload its tables to mem (its part of the plan
+// memory): twiddles, rings, column tiles, the precision form's tables, partial positions
+// and a level's triplet map.
+abs_status bind_tables(abs_plan_s* p, void* mem, hipStream_t st) {
   for (JitPart& q : p->parts) {
     if (q.module) {
       (void)hipModuleUnload(q.module);
@@ -285,10 +338,36 @@ abs_status abs_plan_bind(abs_plan_t p, void* mem, size_t bytes, void* stream) {
   put(p->dl.wave_tiles, p->wave_tiles);
   put(p->dl.pos32, p->pos32);
   put(p->dl.pos64, p->pos64);
+  put(p->dl.tmap, p->tmap);
   if (hipMemcpyAsync(mem, img.data(), img.size(), hipMemcpyHostToDevice, st) != hipSuccess)
     return ABS_ERR_DEVICE;
   // the host image is a local: wait for the copy before it goes out of scope
   if (hipStreamSynchronize(st) != hipSuccess) return ABS_ERR_DEVICE;
+  p->dev = mem;
+  return ABS_OK;
+}
+
+}  // namespace abs_impl
+
+extern "C" {
+
+abs_status abs_plan_bind(abs_plan_t p, void* mem, size_t bytes, void* stream) {
+  if (!p || !mem) return ABS_ERR_INVALID;
+  if (reinterpret_cast<uintptr_t>(mem) & 255) return ABS_ERR_INVALID;
+  if (bytes < p->dl.total) return ABS_ERR_NOMEM;
+  for (abs_plan_s* q : run_plans(p))
+    for (int k = 0; k < (int)q->parts.size(); ++k) {
+      const abs_status s = compile_jit(q, k);
+      if (s != ABS_OK) return s;
+    }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return ABS_ERR_DEVICE;
+  for (abs_plan_s* q : run_plans(p)) {
+    const abs_status s = bind_tables(q, static_cast<char*>(mem) + q->dev_off, st);
+    if (s != ABS_OK) return s;
+    q->device = dev;
+  }
   p->dev = mem;
   p->device = dev;
   return ABS_OK;
@@ -321,19 +400,17 @@ abs_status estimate_on(abs_plan_t p, const WorkLayout& wl, int32_t batch, int32_
   (void)hipGetLastError();
   abs_status s = run_fields_and_contract(p, wl, batch, dtype, grids, w, w_batched, wk, st, nullptr);
   if (s != ABS_OK) return s;
-  const double* part = reinterpret_cast<const double*>(wk + wl.part);
-  const double* part64 = reinterpret_cast<const double*>(wk + wl.part64);
-  const double inv = 1.0 / ((double)p->n * (double)p->n);
-  const dim3 g((unsigned)((p->ntrip + 63) / 64), (unsigned)batch);
-  const char* base = static_cast<const char*>(p->dev);
-  // the FP32 contraction writes partials in its own triplet order, the precision form
-  // by triplet index
-  const int* pos = p->precision == ABS_FP32 ? reinterpret_cast<const int*>(base + p->dl.pos32) : nullptr;
-  const int* pos64 = reinterpret_cast<const int*>(base + p->dl.pos64);
   const unsigned long long* wmin = reinterpret_cast<const unsigned long long*>(wk + wl.wmin);
-  finalize_kernel<<<g, kFinBlock, 0, st>>>(part, wl.partset, p->nblk, pos, part64, wl.partset64, p->nblk64,
-                                        pos64, (int)p->ntrip, batch, wl.nisets, n_given, wmin, inv, p->norm,
-                                        B, N);
+  for (const RunLevel& r : run_levels(p, wl, wk)) {
+    const abs_plan_s* q = r.q;
+    const double inv = 1.0 / ((double)q->n * (double)q->n);
+    const dim3 g((unsigned)((q->ntrip + 63) / 64), (unsigned)batch);
+    finalize_kernel<<<g, kFinBlock, 0, st>>>(reinterpret_cast<const double*>(r.base + r.wl->part), r.wl->partset,
+                                          q->nblk, dev_pos32(q), reinterpret_cast<const double*>(r.base + r.wl->part64),
+                                          r.wl->partset64, q->nblk64, dev_pos64(q), (int)q->ntrip, batch,
+                                          wl.nisets, n_given, wmin, inv, p->norm, dev_tmap(q), (int)p->ntrip,
+                                          B, N);
+  }
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
 
@@ -397,15 +474,16 @@ abs_status abs_estimate_complex(abs_plan_t p, int32_t batch, int32_t dtype, cons
   (void)hipGetLastError();
   s = run_fields_and_contract(p, wl, 4 * batch, dtype, grids, w, w_batched, wk, st, nullptr, 4);
   if (s != ABS_OK) return s;
-  const char* base = static_cast<const char*>(p->dev);
-  const int* pos = p->precision == ABS_FP32 ? reinterpret_cast<const int*>(base + p->dl.pos32) : nullptr;
-  const int* pos64 = reinterpret_cast<const int*>(base + p->dl.pos64);
-  const dim3 g((unsigned)((p->ntrip + 63) / 64), (unsigned)batch);
-  finalize_complex_kernel<<<g, kFinBlock, 0, st>>>(
-      reinterpret_cast<const double*>(wk + wl.part), wl.partset, p->nblk, pos,
-      reinterpret_cast<const double*>(wk + wl.part64), wl.partset64, p->nblk64, pos64, (int)p->ntrip, wl.nisets,
-      n_given, reinterpret_cast<const unsigned long long*>(wk + wl.wmin), 1.0 / ((double)p->n * (double)p->n),
-      p->norm, B, N);
+  const unsigned long long* wmin = reinterpret_cast<const unsigned long long*>(wk + wl.wmin);
+  for (const RunLevel& r : run_levels(p, wl, wk)) {
+    const abs_plan_s* q = r.q;
+    const dim3 g((unsigned)((q->ntrip + 63) / 64), (unsigned)batch);
+    finalize_complex_kernel<<<g, kFinBlock, 0, st>>>(
+        reinterpret_cast<const double*>(r.base + r.wl->part), r.wl->partset, q->nblk, dev_pos32(q),
+        reinterpret_cast<const double*>(r.base + r.wl->part64), r.wl->partset64, q->nblk64, dev_pos64(q),
+        (int)q->ntrip, wl.nisets, n_given, wmin, 1.0 / ((double)q->n * (double)q->n), p->norm, dev_tmap(q),
+        (int)p->ntrip, B, N);
+  }
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
 
@@ -436,10 +514,12 @@ abs_status counts_into(abs_plan_s* p, const float* w, char* wk, const WeightMod*
   // batch 0: the single set is the weight set
   abs_status s = run_fields_and_contract(p, wl, 0, ABS_C64, nullptr, w, 0, wk, st, mod);
   if (s != ABS_OK) return s;
-  const double inv = 1.0 / ((double)p->n * (double)p->n);
-  const int* pos64 = reinterpret_cast<const int*>(static_cast<const char*>(p->dev) + p->dl.pos64);
-  counts_kernel<<<(unsigned)((p->ntrip + 63) / 64), kFinBlock, 0, st>>>(
-      reinterpret_cast<const double*>(wk + wl.part64), p->nblk64, pos64, (int)p->ntrip, inv, N);
+  for (const RunLevel& r : run_levels(p, wl, wk)) {
+    const abs_plan_s* q = r.q;
+    counts_kernel<<<(unsigned)((q->ntrip + 63) / 64), kFinBlock, 0, st>>>(
+        reinterpret_cast<const double*>(r.base + r.wl->part64), q->nblk64, dev_pos64(q), (int)q->ntrip,
+        1.0 / ((double)q->n * (double)q->n), dev_tmap(q), N);
+  }
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
 

@@ -619,7 +619,9 @@ hipError_t launch_colpass_n(const abs_plan_s* p, int nsets, const typename HermT
   auto k = colpass_fixed_kernel<R, LOG2N>;
   hipError_t e = allow_lds(k, lds);
   if (e != hipSuccess) return e;
-  k<<<grid, CB, lds, st>>>(xc, p->hmax, 2 * p->hmax + 1, tiles, ntiles, tpb, bins, tw,
+  // the Hermitian part read is the one formed for the plan, or for its parent (level
+  // plans), whose half extent xc_hm covers the plan's rings
+  k<<<grid, CB, lds, st>>>(xc, p->xc_hm, 2 * p->xc_hm + 1, tiles, ntiles, tpb, bins, tw,
                            Z, zset);
   return hipGetLastError();
 }
@@ -638,30 +640,34 @@ hipError_t launch_colpass(const abs_plan_s* p, int nsets, const typename HermT<s
   }
 }
 
-hipError_t launch_colpass_data(const abs_plan_s* p, const void* grids, int dtype, const float* w,
-                               int w_batched, int batch, void* xc, float2* Z, long long zset,
-                               unsigned long long* wmin, hipStream_t st, int spg) {
-  const char* base = static_cast<const char*>(p->dev);
-  const float2* tw = reinterpret_cast<const float2*>(base + p->dl.tw);
+// Hermitian part of a batch of grids (FP32 complex) or of the weights (FP64 real) for the
+// plan's rings, and the smallest non-zero ring-cell weight of each set.
+hipError_t launch_herm_data(const abs_plan_s* p, const void* grids, int dtype, const float* w, int w_batched,
+                            int batch, void* xc, unsigned long long* wmin, hipStream_t st, int spg) {
   float2* x = static_cast<float2*>(xc);
-  hipError_t e = dtype == ABS_C128
-                     ? launch_herm<true, double2>(p, static_cast<const double2*>(grids), w, w_batched, batch, x,
-                                                  wmin, st, nullptr, spg)
-                     : launch_herm<true, float2>(p, static_cast<const float2*>(grids), w, w_batched, batch, x,
-                                                 wmin, st, nullptr, spg);
-  if (e != hipSuccess) return e;
-  return launch_colpass<float>(p, batch, x, Z, zset, tw, st);
+  return dtype == ABS_C128
+             ? launch_herm<true, double2>(p, static_cast<const double2*>(grids), w, w_batched, batch, x, wmin, st,
+                                          nullptr, spg)
+             : launch_herm<true, float2>(p, static_cast<const float2*>(grids), w, w_batched, batch, x, wmin, st,
+                                         nullptr, spg);
 }
 
-hipError_t launch_colpass_weight(const abs_plan_s* p, const float* w, int w_batched, int nsets,
-                                 void* xc, double2* Z, long long zset, unsigned long long* wmin,
-                                 hipStream_t st, const WeightMod* mod) {
-  const char* base = static_cast<const char*>(p->dev);
-  const double2* tw = reinterpret_cast<const double2*>(base + p->dl.tw64);
-  double* x = static_cast<double*>(xc);
-  hipError_t e = launch_herm<false, float2>(p, nullptr, w, w_batched, nsets, x, wmin, st, mod);
-  if (e != hipSuccess) return e;
-  return launch_colpass<double>(p, nsets, x, Z, zset, tw, st);
+hipError_t launch_herm_weight(const abs_plan_s* p, const float* w, int w_batched, int nsets, void* xc,
+                              unsigned long long* wmin, hipStream_t st, const WeightMod* mod) {
+  return launch_herm<false, float2>(p, nullptr, w, w_batched, nsets, static_cast<double*>(xc), wmin, st, mod);
+}
+
+// Ring-masked column FFTs of plan p (a plan, or one of its levels) from a Hermitian part.
+hipError_t launch_colpass_f32(const abs_plan_s* p, int nsets, const void* xc, float2* Z, long long zset,
+                              hipStream_t st) {
+  const float2* tw = reinterpret_cast<const float2*>(static_cast<const char*>(p->dev) + p->dl.tw);
+  return launch_colpass<float>(p, nsets, static_cast<const float2*>(xc), Z, zset, tw, st);
+}
+
+hipError_t launch_colpass_f64(const abs_plan_s* p, int nsets, const void* xc, double2* Z, long long zset,
+                              hipStream_t st) {
+  const double2* tw = reinterpret_cast<const double2*>(static_cast<const char*>(p->dev) + p->dl.tw64);
+  return launch_colpass<double>(p, nsets, static_cast<const double*>(xc), Z, zset, tw, st);
 }
 
 template <typename R, int LOG2N>

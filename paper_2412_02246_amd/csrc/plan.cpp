@@ -146,6 +146,27 @@ int ilog2(int v) {
 namespace abs_impl {
 
 WorkLayout work_layout(const abs_plan_s* p, int grids, int w_batched, int have_counts, int spg) {
+  if (!p->lv.empty()) {
+    // the parent's Hermitian part and wmin slots, then each level's buffers
+    WorkLayout w{};
+    w.nisets = have_counts ? 0 : ((w_batched && p->wmode != ABS_W_UNIT) ? grids : 1);
+    const int batch = grids * spg;
+    w.ndsets = batch;
+    w.nsets = batch + w.nisets;
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t off = 0;
+    w.wmin = off;
+    off = al(off + (size_t)(batch + w.nisets) * 8);
+    w.xc = off;
+    off = al(off + (size_t)std::max(batch, w.nisets) * (size_t)(p->hmax + 1) * (size_t)(2 * p->hmax + 1) * 8);
+    for (const abs_plan_s* q : p->lv) {
+      w.lv.push_back(work_layout(q, grids, w_batched, have_counts, spg));
+      w.lvbase.push_back(off);
+      off = al(off + w.lv.back().total);
+    }
+    w.total = off;
+    return w;
+  }
   WorkLayout w{};
   // spg data sets per grid (4 for complex input: see abs_estimate_complex), one weight set
   // per grid with batched weights, else one (none with cached counts)
@@ -176,12 +197,15 @@ WorkLayout work_layout(const abs_plan_s* p, int grids, int w_batched, int have_c
   w.fmax = off;
   off = al(off + (size_t)batch * p->nb * 4);
   // smallest non-zero ring-cell weight per data set, then per weight set (FP64 bits)
+  // (a level plan uses its parent's wmin and Hermitian part)
+  const bool level = p->is_level;
   w.wmin = off;
-  off = al(off + (size_t)(batch + w.nisets) * 8);
+  if (!level) off = al(off + (size_t)(batch + w.nisets) * 8);
   // column-major Hermitian part for the column pass: 8 bytes per cell (FP32 complex for
   // the data sets, FP64 real for the weight sets), reused by both in turn
   w.xc = off;
-  off = al(off + (size_t)std::max(batch, w.nisets) * (size_t)(p->hmax + 1) * (size_t)(2 * p->hmax + 1) * 8);
+  if (!level)
+    off = al(off + (size_t)std::max(batch, w.nisets) * (size_t)(p->hmax + 1) * (size_t)(2 * p->hmax + 1) * 8);
   w.total = off;
   return w;
 }
@@ -208,7 +232,7 @@ namespace {
 // 4 groups are needed (fewer slices re-read the fields).
 std::vector<int> split_groups(const abs_plan_s* p, const std::vector<int>& ord, int rw, bool jk, int* waves) {
   const int T = (int)p->ntrip;
-  const int kBudget = rw == 1 ? 200 : 184, kBudgetPairs = rw == 1 ? 240 : 224;
+  const int kBudget = rw == 1 ? 200 : 184, kBudgetPairs = rw == 1 ? 232 : 224;
   auto cost_ok = [&](int t0, int t1) {
     std::set<int> bins;
     int pairs = 0, pa = -1, pb = -1;
@@ -493,6 +517,11 @@ void emit_kernel(const abs_plan_s* p, const std::vector<int>& ord, const std::ve
 // slices, 140 ms in parts of 12; FP64 123 and 109 ms) and take longer to compile (a
 // 12-slice part about 8 s).
 constexpr int kSlicesPerPart = 12;
+// Default bound of n / m for resolution levels (abs_plan_desc.levels = 0): 4, and 2 for the
+// BF16 split form, whose per-product error (about 2^-16) is the largest; with ratio 4 its
+// worst triplet error against the FP64 oracle reached 8.8e-5 on a 512^2 / 24-ring plan
+// (FP16 split 4.4e-6, FP32 3.9e-6).
+constexpr int kDefaultLevelRatio = 4, kDefaultLevelRatioBf16 = 2;
 
 bool build_jit_source(abs_plan_s* p) {
   const KernelOrder o32 = choose_order(p, 1), o64 = choose_order(p, 2);
@@ -752,74 +781,23 @@ void build_mfma_tables(abs_plan_s* p) {
   }
 }
 
-}  // namespace abs_impl
 
-extern "C" {
-
-const char* abs_status_str(abs_status s) {
-  switch (s) {
-    case ABS_OK: return "ok";
-    case ABS_ERR_INVALID: return "invalid argument";
-    case ABS_ERR_ALIAS: return "rings reach beyond n/3 (triangles would wrap); set ABS_ALLOW_WRAP";
-    case ABS_ERR_UNBOUND: return "plan is not bound to device memory";
-    case ABS_ERR_DEVICE: return "HIP runtime or kernel error";
-    case ABS_ERR_JIT: return "run-time compilation of the contraction kernel failed";
-    case ABS_ERR_NOMEM: return "out of host memory or caller buffer too small";
-    case ABS_ERR_EMPTY: return "no ring triplet contains a closed lattice triangle";
-    case ABS_ERR_SCRATCH:
-      return "the estimate needs more workspace than the 256 MiB static scratch of abs_estimate_noalloc";
-  }
-  return "unknown status";
-}
-
-abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
-  if (!d || !out) return ABS_ERR_INVALID;
-  *out = nullptr;
-  const int n = d->n, nb = d->nbins;
-  if (n < 16 || n > kMaxN || (n & (n - 1))) return ABS_ERR_INVALID;
-  if (nb < 1 || nb > kMaxBins || !d->edges) return ABS_ERR_INVALID;
-  if (d->max_batch < 1 || d->max_batch > 65535) return ABS_ERR_INVALID;
-  if (d->wmode < ABS_W_UNIT || d->wmode > ABS_W_GIVEN) return ABS_ERR_INVALID;
-  if (d->precision < ABS_FP32 || d->precision > ABS_FP16X3) return ABS_ERR_INVALID;
-  if (!(d->du > 0.0) || !std::isfinite(d->du)) return ABS_ERR_INVALID;
-  for (int m = 0; m <= nb; ++m)
-    if (!std::isfinite(d->edges[m]) || d->edges[m] < 0.0) return ABS_ERR_INVALID;
-  for (int m = 0; m < nb; ++m)
-    if (!(d->edges[m + 1] > d->edges[m])) return ABS_ERR_INVALID;
-  if (d->edges[0] == 0.0 && !(d->flags & ABS_ALLOW_DC)) return ABS_ERR_INVALID;
-  if (d->edges[nb] > 0.5 * n) return ABS_ERR_ALIAS;
-  if (d->edges[nb] > n / 3.0 && !(d->flags & ABS_ALLOW_WRAP)) return ABS_ERR_ALIAS;
-
-  abs_plan_s* p = new (std::nothrow) abs_plan_s;
-  if (!p) return ABS_ERR_NOMEM;
-  p->n = n;
-  p->nb = nb;
-  p->log2n = ilog2(n);
-  p->du = d->du;
-  p->theta0 = d->theta0 > 0 ? d->theta0 : 0.6 * 24.68 * kPi / 180.0;
-  p->norm = d->norm > 0 ? d->norm : kPi * p->theta0 * p->theta0 / 3.0;
-  p->precision = d->precision;
-  p->wmode = d->wmode;
-  p->max_batch = d->max_batch;
-  p->flags = d->flags;
-  p->edges.assign(d->edges, d->edges + nb + 1);
-  for (int m = 0; m < nb; ++m) {
-    p->lo2.push_back(p->edges[m] * p->edges[m]);
-    p->hi2.push_back(p->edges[m + 1] * p->edges[m + 1]);
-  }
-
-  // rings: columns used by the FFT and mean radii for the labels
+// Rings of a plan: per ring the largest |g_x| (h), the half-plane columns 0 .. h its
+// column pass transforms, their offset in a set of column-pass output (n per column), the
+// mean radius; also hmax and the total column count.  Returns each ring's rows of cells.
+std::vector<RingRows> setup_rings(abs_plan_s* p) {
+  const int nb = p->nb;
   std::vector<RingRows> rows(nb);
-  p->h.resize(nb);
-  p->cols.resize(nb);
-  p->zoff.resize(nb);
-  p->radius.resize(nb);
+  p->h.assign(nb, 0);
+  p->cols.assign(nb, 0);
+  p->zoff.assign(nb, 0);
+  p->radius.assign(nb, 0.0);
   int64_t acc = 0;
   for (int m = 0; m < nb; ++m) {
     rows[m] = ring_rows(p->lo2[m], p->hi2[m]);
     p->h[m] = (int)rows[m].H;
     p->cols[m] = rows[m].H >= 0 ? (int)rows[m].H + 1 : 0;
-    p->zoff[m] = acc * n;
+    p->zoff[m] = acc * p->n;
     acc += p->cols[m];
     double sr = 0.0;
     long long cnt = 0;
@@ -836,58 +814,26 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
   p->ncols = acc;
   p->hmax = 0;
   for (int m = 0; m < nb; ++m) p->hmax = std::max(p->hmax, p->h[m]);
+  return rows;
+}
 
-  // triplets i <= j <= k with at least one closed lattice triangle
-  const bool wrap = (p->flags & ABS_ALLOW_WRAP) && p->edges[nb] > n / 3.0;
-  std::vector<std::vector<std::pair<int, int>>> cells;
-  if (wrap) {
-    cells.resize(nb);
-    for (int m = 0; m < nb; ++m) cells[m] = cells_of(rows[m]);
-  }
-  for (int i = 0; i < nb; ++i)
-    for (int j = i; j < nb; ++j)
-      for (int k = j; k < nb; ++k) {
-        bool ok;
-        if (wrap) {
-          ok = has_cyclic_triangle(n, cells[i], cells[j], p->lo2[k], p->hi2[k]);
-        } else {
-          if (!(p->edges[k] < p->edges[i + 1] + p->edges[j + 1])) continue;  // triangle inequality
-          ok = has_planar_triangle(rows[i], rows[j], rows[k], p->edges[k], p->edges[j + 1]);
-        }
-        if (!ok) continue;
-        p->trips.push_back(i);
-        p->trips.push_back(j);
-        p->trips.push_back(k);
-      }
-  p->ntrip = (int64_t)p->trips.size() / 3;
-  if (p->ntrip == 0) {
-    delete p;
-    return ABS_ERR_EMPTY;
-  }
-  {
-    std::set<std::pair<int, int>> pairs;
-    for (int64_t t = 0; t < p->ntrip; ++t) pairs.insert({p->trips[3 * t], p->trips[3 * t + 1]});
-    p->npairs = (int64_t)pairs.size();
-  }
-  p->labels.resize(5 * p->ntrip);
-  for (int64_t t = 0; t < p->ntrip; ++t) {
-    const double l3 = 2 * kPi * p->du * p->radius[p->trips[3 * t]];
-    const double l2 = 2 * kPi * p->du * p->radius[p->trips[3 * t + 1]];
-    const double l1 = 2 * kPi * p->du * p->radius[p->trips[3 * t + 2]];
-    double* L = &p->labels[5 * t];
-    L[0] = l1;
-    L[1] = l2;
-    L[2] = l3;
-    L[3] = (l1 * l1 + l2 * l2 - l3 * l3) / (2.0 * l1 * l2);
-    L[4] = l2 / l1;
-  }
+int64_t count_pairs(const std::vector<int32_t>& trips) {
+  std::set<std::pair<int, int>> pairs;
+  for (size_t t = 0; t + 2 < trips.size(); t += 3) pairs.insert({trips[t], trips[t + 1]});
+  return (int64_t)pairs.size();
+}
 
+// FFT tiling, contraction pixel blocks, the device layout of the tables, the precision
+// form's tables and the contraction code of a plan whose rings and triplets are set.
+bool setup_kernels(abs_plan_s* p) {
+  const int n = p->n, nb = p->nb;
   // FFT tiling: a column-pass workgroup of col_block(log2 n) threads transforms ct columns
   // of one ring at once, one transform per n/16 threads (at most the whole workgroup)
   {
     const int cb = col_block(p->log2n);
     p->ct = cb / std::min(cb, std::max(1, n / 16));
   }
+  p->tiles.clear();
   for (int m = 0; m < nb; ++m)
     for (int g0 = 0; g0 < p->cols[m]; g0 += p->ct)
       p->tiles.push_back({m, g0, std::min(p->ct, p->cols[m] - g0), 0});
@@ -935,9 +881,271 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
   off = al(off + (size_t)p->ntrip * 4);
   p->dl.pos64 = off;
   off = al(off + (size_t)p->ntrip * 4);
+  p->dl.tmap = off;
+  off = al(off + p->tmap.size() * 4);
   p->dl.total = off;
+  return build_jit_source(p);
+}
 
-  if (!build_jit_source(p)) {
+// Resolution levels of a plan.  A triplet fits a level of size m when 3 h < m for each
+// of its rings (h: the ring's largest |g_x|, which is also its largest |g_y|): the sum of
+// three of its cells then has components in (-m, m), so it vanishes modulo m only where it
+// vanishes.  It runs in the smallest chosen level that fits it (the level at n, always
+// available, takes the rest, wrapped plans' cyclic triplets included; a level left without
+// triplets is dropped).  The sets of levels
+// drawn from n/2, n/4, ..., n / max_ratio (at least 16) are compared by a cost per call,
+// in units of one contraction flop on one set: per level, its FFT passes (each of its
+// rings over m^2 pixels, about kFftCost flops a pixel and ring), its contraction (pair
+// products and two flops per triplet, per pixel), both over max_batch data sets and one
+// weight set, and a fixed cost for its launches (kLevelCost, about 40 us).  The ratio is
+// bounded because the sum over m^2 pixels averages the fields' rounding errors over fewer
+// terms (the FP32 error of a level's sums grows about as n / m against the FP64
+// random-error scale of the full-grid sum).  ABS_EVERY_LEVEL takes every candidate level.
+void choose_levels(const abs_plan_s* p, std::vector<int>& sizes, std::vector<int>& level_of) {
+  constexpr double kFftCost = 72.0, kLevelCost = 2.4e9;
+  const int T = (int)p->ntrip, n = p->n;
+  std::vector<int> need(T);
+  for (int t = 0; t < T; ++t) {
+    const int* x = &p->trips[3 * t];
+    const int hm = std::max(p->h[x[0]], std::max(p->h[x[1]], p->h[x[2]]));
+    int m = 16;
+    while (3 * hm >= m && m <= n) m *= 2;
+    need[t] = m;
+  }
+  std::vector<int> cand;
+  for (int m = n / 2; m >= 16 && (int64_t)m * p->max_ratio >= n; m /= 2) cand.push_back(m);
+  const double sets = (double)p->max_batch + 1.0;
+  double best = -1.0;
+  const int all = (1 << cand.size()) - 1;
+  for (int mask = (p->flags & ABS_EVERY_LEVEL) ? all : 0; mask <= all; ++mask) {
+    std::vector<int> lv = {n};
+    for (int c = 0; c < (int)cand.size(); ++c)
+      if (mask >> c & 1) lv.push_back(cand[c]);
+    std::vector<int> lof(T);
+    for (int t = 0; t < T; ++t) {
+      int L = 0;
+      for (int q = 1; q < (int)lv.size(); ++q)
+        if (lv[q] >= need[t]) L = q;   // lv is descending: the last that fits is the smallest
+      lof[t] = L;
+    }
+    double cost = 0.0;
+    std::vector<int> keep, remap(lv.size(), -1);
+    for (int L = 0; L < (int)lv.size(); ++L) {
+      int64_t cnt = 0;
+      int K = 0;
+      std::set<std::pair<int, int>> ij, jk;
+      for (int t = 0; t < T; ++t) {
+        if (lof[t] != L) continue;
+        const int* x = &p->trips[3 * t];
+        ++cnt;
+        K = std::max(K, x[2] + 1);
+        ij.insert({x[0], x[1]});
+        jk.insert({x[1], x[2]});
+      }
+      if (cnt == 0) continue;   // a level without triplets is left out
+      remap[L] = (int)keep.size();
+      keep.push_back(lv[L]);
+      const double m2 = (double)lv[L] * lv[L];
+      cost += sets * m2 * (kFftCost * K + (double)std::min(ij.size(), jk.size()) + 2.0 * cnt) + kLevelCost;
+    }
+    if (best < 0.0 || cost < best) {
+      best = cost;
+      sizes = keep;
+      level_of.resize(T);
+      for (int t = 0; t < T; ++t) level_of[t] = remap[lof[t]];
+    }
+  }
+}
+
+// A level plan of size m: rings 0 .. K-1 (K one past the largest ring its triplets use),
+// the given triplets of the parent (tidx, ascending) and its own FFT tiling, tables and
+// contraction code; its column pass reads the parent's Hermitian part.
+abs_plan_s* make_level(const abs_plan_s* p, int m, const std::vector<int32_t>& tidx) {
+  abs_plan_s* q = new (std::nothrow) abs_plan_s;
+  if (!q) return nullptr;
+  q->is_level = true;
+  int K = 0;
+  for (int32_t t : tidx) K = std::max(K, p->trips[3 * t + 2] + 1);
+  q->n = m;
+  q->nb = K;
+  q->log2n = ilog2(m);
+  q->du = p->du;
+  q->theta0 = p->theta0;
+  q->norm = p->norm;
+  q->precision = p->precision;
+  q->wmode = p->wmode;
+  q->max_batch = p->max_batch;
+  q->flags = p->flags;
+  q->edges.assign(p->edges.begin(), p->edges.begin() + K + 1);
+  q->lo2.assign(p->lo2.begin(), p->lo2.begin() + K);
+  q->hi2.assign(p->hi2.begin(), p->hi2.begin() + K);
+  setup_rings(q);
+  q->xc_hm = p->hmax;
+  q->tmap = tidx;
+  for (int32_t t : tidx)
+    for (int c = 0; c < 3; ++c) q->trips.push_back(p->trips[3 * t + c]);
+  q->ntrip = (int64_t)tidx.size();
+  q->npairs = count_pairs(q->trips);
+  if (!setup_kernels(q)) {
+    delete q;
+    return nullptr;
+  }
+  return q;
+}
+
+abs_plan_s* part_owner(abs_plan_s* p, int k, int* local) {
+  if (k < 0) return nullptr;
+  for (abs_plan_s* q : run_plans(p)) {
+    if (k < (int)q->parts.size()) {
+      *local = k;
+      return q;
+    }
+    k -= (int)q->parts.size();
+  }
+  return nullptr;
+}
+
+void destroy_plan(abs_plan_s* p) {
+  if (!p) return;
+  bool loaded = false;
+  for (abs_plan_s* q : run_plans(p))
+    for (const JitPart& c : q->parts) loaded = loaded || c.module;
+  if (loaded) {
+    int cur = -1;
+    const bool other = hipGetDevice(&cur) == hipSuccess && p->device >= 0 && cur != p->device;
+    if (other) (void)hipSetDevice(p->device);
+    for (abs_plan_s* q : run_plans(p))
+      for (JitPart& c : q->parts)
+        if (c.module) (void)hipModuleUnload(c.module);
+    if (other) (void)hipSetDevice(cur);
+  }
+  for (abs_plan_s* q : p->lv) delete q;
+  delete p;
+}
+
+}  // namespace abs_impl
+
+extern "C" {
+
+const char* abs_status_str(abs_status s) {
+  switch (s) {
+    case ABS_OK: return "ok";
+    case ABS_ERR_INVALID: return "invalid argument";
+    case ABS_ERR_ALIAS: return "rings reach beyond n/3 (triangles would wrap); set ABS_ALLOW_WRAP";
+    case ABS_ERR_UNBOUND: return "plan is not bound to device memory";
+    case ABS_ERR_DEVICE: return "HIP runtime or kernel error";
+    case ABS_ERR_JIT: return "run-time compilation of the contraction kernel failed";
+    case ABS_ERR_NOMEM: return "out of host memory or caller buffer too small";
+    case ABS_ERR_EMPTY: return "no ring triplet contains a closed lattice triangle";
+    case ABS_ERR_SCRATCH:
+      return "the estimate needs more workspace than the 256 MiB static scratch of abs_estimate_noalloc";
+  }
+  return "unknown status";
+}
+
+abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
+  if (!d || !out) return ABS_ERR_INVALID;
+  *out = nullptr;
+  const int n = d->n, nb = d->nbins;
+  if (n < 16 || n > kMaxN || (n & (n - 1))) return ABS_ERR_INVALID;
+  if (nb < 1 || nb > kMaxBins || !d->edges) return ABS_ERR_INVALID;
+  if (d->max_batch < 1 || d->max_batch > 65535) return ABS_ERR_INVALID;
+  if (d->wmode < ABS_W_UNIT || d->wmode > ABS_W_GIVEN) return ABS_ERR_INVALID;
+  if (d->precision < ABS_FP32 || d->precision > ABS_FP16X3) return ABS_ERR_INVALID;
+  if (!(d->du > 0.0) || !std::isfinite(d->du)) return ABS_ERR_INVALID;
+  if (d->levels < 0 || d->levels > n || (d->levels & (d->levels - 1))) return ABS_ERR_INVALID;
+  for (int m = 0; m <= nb; ++m)
+    if (!std::isfinite(d->edges[m]) || d->edges[m] < 0.0) return ABS_ERR_INVALID;
+  for (int m = 0; m < nb; ++m)
+    if (!(d->edges[m + 1] > d->edges[m])) return ABS_ERR_INVALID;
+  if (d->edges[0] == 0.0 && !(d->flags & ABS_ALLOW_DC)) return ABS_ERR_INVALID;
+  if (d->edges[nb] > 0.5 * n) return ABS_ERR_ALIAS;
+  if (d->edges[nb] > n / 3.0 && !(d->flags & ABS_ALLOW_WRAP)) return ABS_ERR_ALIAS;
+
+  abs_plan_s* p = new (std::nothrow) abs_plan_s;
+  if (!p) return ABS_ERR_NOMEM;
+  p->n = n;
+  p->nb = nb;
+  p->log2n = ilog2(n);
+  p->du = d->du;
+  p->theta0 = d->theta0 > 0 ? d->theta0 : 0.6 * 24.68 * kPi / 180.0;
+  p->norm = d->norm > 0 ? d->norm : kPi * p->theta0 * p->theta0 / 3.0;
+  p->precision = d->precision;
+  p->wmode = d->wmode;
+  p->max_batch = d->max_batch;
+  p->flags = d->flags;
+  p->max_ratio = d->levels != 0 ? d->levels
+                 : d->precision == ABS_BF16X3 ? kDefaultLevelRatioBf16 : kDefaultLevelRatio;
+  p->edges.assign(d->edges, d->edges + nb + 1);
+  for (int m = 0; m < nb; ++m) {
+    p->lo2.push_back(p->edges[m] * p->edges[m]);
+    p->hi2.push_back(p->edges[m + 1] * p->edges[m + 1]);
+  }
+  const std::vector<RingRows> rows = setup_rings(p);
+  p->xc_hm = p->hmax;
+
+  // triplets i <= j <= k with at least one closed lattice triangle
+  const bool wrap = (p->flags & ABS_ALLOW_WRAP) && p->edges[nb] > n / 3.0;
+  std::vector<std::vector<std::pair<int, int>>> cells;
+  if (wrap) {
+    cells.resize(nb);
+    for (int m = 0; m < nb; ++m) cells[m] = cells_of(rows[m]);
+  }
+  for (int i = 0; i < nb; ++i)
+    for (int j = i; j < nb; ++j)
+      for (int k = j; k < nb; ++k) {
+        bool ok;
+        if (wrap) {
+          ok = has_cyclic_triangle(n, cells[i], cells[j], p->lo2[k], p->hi2[k]);
+        } else {
+          if (!(p->edges[k] < p->edges[i + 1] + p->edges[j + 1])) continue;  // triangle inequality
+          ok = has_planar_triangle(rows[i], rows[j], rows[k], p->edges[k], p->edges[j + 1]);
+        }
+        if (!ok) continue;
+        p->trips.push_back(i);
+        p->trips.push_back(j);
+        p->trips.push_back(k);
+      }
+  p->ntrip = (int64_t)p->trips.size() / 3;
+  if (p->ntrip == 0) {
+    delete p;
+    return ABS_ERR_EMPTY;
+  }
+  p->npairs = count_pairs(p->trips);
+  p->labels.resize(5 * p->ntrip);
+  for (int64_t t = 0; t < p->ntrip; ++t) {
+    const double l3 = 2 * kPi * p->du * p->radius[p->trips[3 * t]];
+    const double l2 = 2 * kPi * p->du * p->radius[p->trips[3 * t + 1]];
+    const double l1 = 2 * kPi * p->du * p->radius[p->trips[3 * t + 2]];
+    double* L = &p->labels[5 * t];
+    L[0] = l1;
+    L[1] = l2;
+    L[2] = l3;
+    L[3] = (l1 * l1 + l2 * l2 - l3 * l3) / (2.0 * l1 * l2);
+    L[4] = l2 / l1;
+  }
+
+  // resolution levels, when the cost model finds more than one worth running
+  std::vector<int> sizes, level_of;
+  choose_levels(p, sizes, level_of);
+  if (sizes.size() > 1 || sizes[0] != n) {
+    size_t off = 0;
+    for (int L = 0; L < (int)sizes.size(); ++L) {
+      std::vector<int32_t> tidx;
+      for (int64_t t = 0; t < p->ntrip; ++t)
+        if (level_of[t] == L) tidx.push_back((int32_t)t);
+      abs_plan_s* q = make_level(p, sizes[L], tidx);
+      if (!q) {
+        destroy_plan(p);
+        return ABS_ERR_JIT;
+      }
+      q->dev_off = off;
+      off = (off + q->dl.total + 255) & ~(size_t)255;
+      p->lv.push_back(q);
+    }
+    p->dl = DevLayout{};
+    p->dl.total = off;
+  } else if (!setup_kernels(p)) {
     delete p;
     return ABS_ERR_JIT;
   }
@@ -945,8 +1153,8 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
   return ABS_OK;
 }
 
-abs_status abs_plan_info_get(abs_plan_t p, abs_plan_info* o) {
-  if (!p || !o) return ABS_ERR_INVALID;
+namespace {
+void fill_info(const abs_plan_s* p, abs_plan_info* o) {
   o->n = p->n;
   o->nbins = p->nb;
   o->ntrip = p->ntrip;
@@ -966,6 +1174,51 @@ abs_status abs_plan_info_get(abs_plan_t p, abs_plan_info* o) {
   o->weight_waves = p->waves64;
   o->mfma_tiles_per_wave = p->mfma_tpw;
   o->mfma_depth = p->mfma_depth;
+  o->nlevels = 1;
+}
+}  // namespace
+
+abs_status abs_plan_info_get(abs_plan_t p, abs_plan_info* o) {
+  if (!p || !o) return ABS_ERR_INVALID;
+  if (p->lv.empty()) {
+    fill_info(p, o);
+    return ABS_OK;
+  }
+  // the code variants reported are the top level's; counts are summed over the levels
+  fill_info(p->lv[0], o);
+  o->n = p->n;
+  o->nbins = p->nb;
+  o->ntrip = p->ntrip;
+  o->npairs = p->npairs;
+  o->ncols = p->ncols;
+  o->plan_bytes = (int64_t)p->dl.total;
+  o->mfma_tiles = o->jit_parts = o->contract_parts = o->weight_parts = 0;
+  for (const abs_plan_s* q : p->lv) {
+    abs_plan_info qi;
+    fill_info(q, &qi);
+    o->mfma_tiles += qi.mfma_tiles;
+    o->jit_parts += qi.jit_parts;
+    o->contract_parts += qi.contract_parts;
+    o->weight_parts += qi.weight_parts;
+  }
+  o->nlevels = (int32_t)p->lv.size();
+  return ABS_OK;
+}
+
+abs_status abs_plan_level_info(abs_plan_t p, int32_t level, abs_plan_info* o, int32_t* tmap) {
+  if (!p || !o || level < 0) return ABS_ERR_INVALID;
+  if (p->lv.empty()) {
+    if (level != 0) return ABS_ERR_INVALID;
+    fill_info(p, o);
+    if (tmap)
+      for (int64_t t = 0; t < p->ntrip; ++t) tmap[t] = (int32_t)t;
+    return ABS_OK;
+  }
+  if (level >= (int)p->lv.size()) return ABS_ERR_INVALID;
+  const abs_plan_s* q = p->lv[level];
+  fill_info(q, o);
+  o->plan_bytes = 0;   // part of the parent's
+  if (tmap) std::memcpy(tmap, q->tmap.data(), q->tmap.size() * sizeof(int32_t));
   return ABS_OK;
 }
 
@@ -979,43 +1232,50 @@ abs_status abs_plan_triplets(abs_plan_t p, int32_t* ijk, double* labels, double*
 
 abs_status abs_plan_compile(abs_plan_t p) {
   if (!p) return ABS_ERR_INVALID;
-  for (int k = 0; k < (int)p->parts.size(); ++k) {
-    const abs_status s = compile_jit(p, k);
-    if (s != ABS_OK) return s;
-  }
+  for (abs_plan_s* q : run_plans(p))
+    for (int k = 0; k < (int)q->parts.size(); ++k) {
+      const abs_status s = compile_jit(q, k);
+      if (s != ABS_OK) return s;
+    }
   return ABS_OK;
 }
 
 abs_status abs_plan_compile_part(abs_plan_t p, int32_t part) {
-  if (!p || part < 0 || part >= (int)p->parts.size()) return ABS_ERR_INVALID;
-  return compile_jit(p, part);
+  int k = 0;
+  abs_plan_s* q = p ? part_owner(p, part, &k) : nullptr;
+  if (!q) return ABS_ERR_INVALID;
+  return compile_jit(q, k);
 }
 
 abs_status abs_plan_code(abs_plan_t p, int32_t part, uint64_t* key, void* dst, size_t* bytes) {
-  if (!p || !bytes || part < 0 || part >= (int)p->parts.size()) return ABS_ERR_INVALID;
-  JitPart& q = p->parts[part];
-  if (key) *key = jit_key(p, part);
+  int k = 0;
+  abs_plan_s* q = p ? part_owner(p, part, &k) : nullptr;
+  if (!q || !bytes) return ABS_ERR_INVALID;
+  JitPart& c = q->parts[k];
+  if (key) *key = jit_key(q, k);
   if (!dst) {
-    if (!q.compiled) {
-      const abs_status s = compile_jit(p, part);
+    if (!c.compiled) {
+      const abs_status s = compile_jit(q, k);
       if (s != ABS_OK) return s;
     }
-    *bytes = q.code.size();
+    *bytes = c.code.size();
     return ABS_OK;
   }
-  if (!q.compiled) return ABS_ERR_INVALID;
-  if (*bytes < q.code.size()) return ABS_ERR_NOMEM;
-  std::memcpy(dst, q.code.data(), q.code.size());
-  *bytes = q.code.size();
+  if (!c.compiled) return ABS_ERR_INVALID;
+  if (*bytes < c.code.size()) return ABS_ERR_NOMEM;
+  std::memcpy(dst, c.code.data(), c.code.size());
+  *bytes = c.code.size();
   return ABS_OK;
 }
 
 abs_status abs_plan_set_code(abs_plan_t p, int32_t part, uint64_t key, const void* src, size_t bytes) {
-  if (!p || !src || bytes == 0 || part < 0 || part >= (int)p->parts.size()) return ABS_ERR_INVALID;
-  if (key != jit_key(p, part)) return ABS_ERR_INVALID;   // compiled for another triplet list
-  JitPart& q = p->parts[part];
-  q.code.assign(static_cast<const char*>(src), static_cast<const char*>(src) + bytes);
-  q.compiled = true;
+  int k = 0;
+  abs_plan_s* q = p ? part_owner(p, part, &k) : nullptr;
+  if (!q || !src || bytes == 0) return ABS_ERR_INVALID;
+  if (key != jit_key(q, k)) return ABS_ERR_INVALID;   // compiled for another triplet list
+  JitPart& c = q->parts[k];
+  c.code.assign(static_cast<const char*>(src), static_cast<const char*>(src) + bytes);
+  c.compiled = true;
   return ABS_OK;
 }
 
@@ -1027,18 +1287,7 @@ abs_status abs_estimate_workspace(abs_plan_t p, int32_t batch, int32_t w_batched
 }
 
 abs_status abs_destroy(abs_plan_t p) {
-  if (!p) return ABS_OK;
-  bool loaded = false;
-  for (const JitPart& q : p->parts) loaded = loaded || q.module;
-  if (loaded) {
-    int cur = -1;
-    const bool other = hipGetDevice(&cur) == hipSuccess && p->device >= 0 && cur != p->device;
-    if (other) (void)hipSetDevice(p->device);
-    for (JitPart& q : p->parts)
-      if (q.module) (void)hipModuleUnload(q.module);
-    if (other) (void)hipSetDevice(cur);
-  }
-  delete p;
+  destroy_plan(p);
   return ABS_OK;
 }
 

@@ -27,22 +27,24 @@ class Plan:
     wmode       W_UNIT, W_INV_COUNT or W_GIVEN
     max_batch   largest batch of grids per call
     flags       ALLOW_WRAP | ALLOW_DC
+    levels      largest n / m of a resolution level (1: evaluate every triplet at n;
+                0: the library's default)
     """
 
     def __init__(self, n, edges, du=1.0, norm=0.0, theta0=0.0, precision=L.FP32,
-                 wmode=L.W_UNIT, max_batch=1, flags=0):
+                 wmode=L.W_UNIT, max_batch=1, flags=0, levels=0):
         lib = L.lib()
         e = np.ascontiguousarray(edges, dtype=np.float64)
         self._edges = e
         self._spec = (int(n), tuple(float(x) for x in e),
                       dict(du=float(du), norm=float(norm), theta0=float(theta0),
                            precision=int(precision), wmode=int(wmode), max_batch=int(max_batch),
-                           flags=int(flags)))
+                           flags=int(flags), levels=int(levels)))
         d = L.PlanDesc(n=int(n), nbins=len(e) - 1,
                        edges=e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                        du=float(du), norm=float(norm), theta0=float(theta0),
                        precision=int(precision), wmode=int(wmode), max_batch=int(max_batch),
-                       flags=int(flags))
+                       flags=int(flags), levels=int(levels))
         h = ctypes.c_void_p()
         L.check(lib.abs_plan(ctypes.byref(d), ctypes.byref(h)), "abs_plan")
         self.handle = h
@@ -59,6 +61,20 @@ class Plan:
             "contract": (info.contract_parts, info.contract_jk, info.contract_block, info.contract_waves),
             "weight": (info.weight_parts, info.weight_jk, info.weight_block, info.weight_waves),
             "mfma": (info.mfma_tiles_per_wave, info.mfma_depth)}
+        # resolution levels, largest first: dicts with the level's grid side m, rings,
+        # triplets (their indices in self.triplets: "tmap"), pairs and code variants
+        self.levels = []
+        for lv in range(info.nlevels):
+            li = L.PlanInfo()
+            tm = np.zeros(max(1, self.ntrip), np.int32)
+            L.check(lib.abs_plan_level_info(h, lv, ctypes.byref(li), tm.ctypes.data_as(ctypes.c_void_p)),
+                    "abs_plan_level_info")
+            self.levels.append(dict(m=li.n, nbins=li.nbins, ntrip=li.ntrip, npairs=li.npairs, ncols=li.ncols,
+                                    tmap=tm[:li.ntrip].copy(), mfma_tiles=li.mfma_tiles,
+                                    contract=(li.contract_parts, li.contract_jk, li.contract_block,
+                                              li.contract_waves),
+                                    weight=(li.weight_parts, li.weight_jk, li.weight_block, li.weight_waves),
+                                    mfma=(li.mfma_tiles_per_wave, li.mfma_depth)))
         self.precision = int(precision)
         self.wmode, self.max_batch = int(wmode), int(max_batch)
         ijk = np.zeros((self.ntrip, 3), np.int32)

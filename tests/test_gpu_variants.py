@@ -8,7 +8,7 @@ import pytest
 
 import synth
 from oracle import estimator as oest
-from variant_plans import PLANS, PRECISION_CASES, VARIANTS
+from variant_plans import LEVELS, PLANS, PRECISION_CASES, VARIANTS
 
 pytestmark = pytest.mark.gpu
 TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "fp16x3": 1e-4}
@@ -35,7 +35,7 @@ def _run(name, prec):
     import paper_2412_02246_amd as A
     n, e = PLANS[name]
     P = {"fp32": A.FP32, "bf16x3": A.BF16X3, "fp16x3": A.FP16X3}[prec]
-    p = A.Plan(n, e, wmode=A.W_INV_COUNT, precision=P)
+    p = A.Plan(n, e, wmode=A.W_INV_COUNT, precision=P, levels=LEVELS)
     want = VARIANTS[name]
     if prec == "fp32":
         assert p.variants["contract"] == want["contract"]

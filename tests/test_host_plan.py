@@ -143,12 +143,12 @@ def test_jit_parts_code_roundtrip_and_parallel_compile():
 def test_code_variants_selected_by_each_plan():
     """Pins which contraction variant every test plan selects (the GPU variant tests compare
     each of them with the oracle on every triplet)."""
-    from variant_plans import PLANS, VARIANTS
+    from variant_plans import LEVELS, PLANS, VARIANTS
     A = _A()
     seen = {"contract": set(), "weight": set(), "mfma": set()}
     for name, (n, e) in PLANS.items():
-        p = A.Plan(n, e)
-        q = A.Plan(n, e, precision=A.BF16X3)
+        p = A.Plan(n, e, levels=LEVELS)
+        q = A.Plan(n, e, precision=A.BF16X3, levels=LEVELS)
         got = dict(contract=p.variants["contract"], weight=p.variants["weight"], mfma=q.variants["mfma"])
         assert got == VARIANTS[name], (name, got)
         assert q.variants["contract"][0] == 0           # the precision form has no FP32 kernel
@@ -202,3 +202,69 @@ def test_generated_contraction_kernels_do_not_spill(which):
         _, blob = p.code(part)
         assert _msgpack_uint_after(blob, b".vgpr_spill_count") == 0, (which, part)
         assert _msgpack_uint_after(blob, b".private_segment_fixed_size") == 0, (which, part)
+
+
+def _ring_h(n, edges):
+    """Largest |g_x| of each ring's lattice cells (brute force over the grid)."""
+    g = np.arange(-(n // 2), n // 2)
+    r2 = g[:, None] ** 2 + g[None, :] ** 2
+    gx = np.abs(np.broadcast_to(g[None, :], r2.shape))
+    e2 = np.asarray(edges, np.float64) ** 2
+    return np.array([gx[(r2 >= e2[m]) & (r2 < e2[m + 1])].max(initial=-1) for m in range(len(edges) - 1)])
+
+
+LEVEL_CASES = {
+    # (n, edges, max_batch, levels, flags, the levels the plan picks: (m, rings, triplets))
+    "mwa1024_b16": (1024, oplan.log_edges(46 / (2 * np.pi), 1320 / (2 * np.pi), 20), 16, 0, 0,
+                    [(1024, 20, 330), (256, 14, 360)]),
+    "mwa4096_b16": (4096, oplan.log_edges(4 * 46 / (2 * np.pi), 4 * 1320 / (2 * np.pi), 32), 16, 0, 0,
+                    [(4096, 32, 240), (2048, 30, 777), (1024, 23, 1292)]),
+    "mwa8192_b8": (8192, oplan.log_edges(8 * 46 / (2 * np.pi), 8 * 1320 / (2 * np.pi), 64), 8, 0, 0,
+                   [(8192, 64, 1528), (4096, 60, 5030), (2048, 46, 8671)]),
+    "every_256": (256, oplan.log_edges(3.0, 85.0, 16), 2, 8, 4, None),
+    "wrap_128": (128, oplan.log_edges(2.0, 60.0, 12), 2, 8, 5, None),
+}
+
+
+@pytest.mark.parametrize("name", sorted(LEVEL_CASES))
+def test_resolution_levels(name):
+    """Levels partition the triplets; every level's triplets close their triangles exactly
+    on its m x m grid (3 h < m for each of their rings, h the ring's largest |g_x|) and sit
+    in the smallest of the plan's levels that allows this; a level transforms the rings up
+    to its largest k; sizes are n / 2^j within the ratio.  The three workloads' choices are
+    pinned."""
+    A = _A()
+    n, e, mb, ratio, flags, want = LEVEL_CASES[name]
+    p = A.Plan(n, e, max_batch=mb, levels=ratio, flags=flags)
+    got = [(lv["m"], lv["nbins"], lv["ntrip"]) for lv in p.levels]
+    if want is not None:
+        assert got == want, got
+    h = _ring_h(n, e)
+    T = p.triplets
+    need = np.array([16 * 2 ** int(max(0, np.ceil(np.log2((3 * h[t].max() + 1) / 16.0)))) for t in T])
+    sizes = sorted(lv["m"] for lv in p.levels)
+    seen = np.zeros(p.ntrip, int)
+    for lv in p.levels:
+        m, tm = lv["m"], lv["tmap"]
+        assert n % m == 0 and (n // m) & (n // m - 1) == 0 and n // m <= (ratio or 4)
+        assert np.all(np.diff(tm) > 0)
+        seen[tm] += 1
+        assert lv["nbins"] == T[tm, 2].max() + 1
+        fits = need[tm] <= m
+        if m < n:
+            assert fits.all(), name
+        # the smallest level of the plan that fits each triplet
+        smallest = np.array([min([s for s in sizes if s >= need[t]] or [n]) for t in tm])
+        assert np.array_equal(smallest, np.full(len(tm), m)), name
+    assert np.all(seen == 1)
+    one = A.Plan(n, e, max_batch=mb, levels=1, flags=flags & ~A.EVERY_LEVEL)
+    assert [lv["m"] for lv in one.levels] == [n]
+    assert np.array_equal(one.triplets, p.triplets)
+
+
+def test_levels_argument_checks():
+    A = _A()
+    e = oplan.log_edges(3.0, 40.0, 8)
+    for bad in (-1, 3, 12, 512):
+        with pytest.raises(A.AbsError):
+            A.Plan(256, e, levels=bad)

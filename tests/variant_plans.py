@@ -3,10 +3,14 @@ FP32 data kernel's triplet order ((D_j D_k) D_i or (D_i D_j) D_k, blocks of j), 
 workgroup and code parts; the same for the FP64 weight kernel; and the precision form's
 tiles per wave and loads in flight.  All are small enough for the oracle to evaluate every
 triplet.  VARIANTS pins what each plan selects: (parts, jk, block, waves) for the FP32 and
-FP64 kernels, (tiles per wave, depth) for the precision form."""
+FP64 kernels, (tiles per wave, depth) for the precision form.  The plans are built with
+LEVELS = 1 (every triplet at the plan's own n), so that each variant runs at the size
+pinned here; resolution levels have tests of their own."""
 import numpy as np
 
 from oracle import plan as oplan
+
+LEVELS = 1
 
 _E5 = oplan.log_edges(8 * 46 / (2 * np.pi), 8 * 1320 / (2 * np.pi), 64)    # 8192^2 ring radii
 _E3 = oplan.log_edges(4 * 46 / (2 * np.pi), 4 * 1320 / (2 * np.pi), 32)    # 4096^2 ring radii
@@ -34,7 +38,7 @@ PLANS = {
 }
 
 VARIANTS = {
-    "ensemble_1024": dict(contract=(1, 0, 16, 8), weight=(3, 0, 8, 8), mfma=(12, 1)),
+    "ensemble_1024": dict(contract=(2, 0, 16, 8), weight=(3, 0, 8, 8), mfma=(12, 1)),
     "dense_256x64": dict(contract=(2, 0, 16, 8), weight=(3, 0, 8, 8), mfma=(12, 1)),
     "ij_256x40": dict(contract=(1, 0, 0, 8), weight=(2, 0, 8, 8), mfma=(12, 1)),
     "c3_1024": dict(contract=(1, 1, 0, 8), weight=(1, 0, 16, 8), mfma=(12, 4)),
