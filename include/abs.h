@@ -92,12 +92,13 @@ typedef struct abs_plan_desc {
   uint32_t flags;       /* ABS_ALLOW_WRAP | ABS_ALLOW_DC | ABS_EVERY_LEVEL             */
   int32_t levels;       /* largest n / m of a resolution level: a power of two; 1 runs */
                         /* every triplet at n; 0 selects 4 (2 for ABS_BF16X3).  A     */
-                        /* triplet whose rings all lie within |g_x|, |g_y| < m/3       */
-                        /* closes exactly the same triangles on an m x m grid (Eqs.    */
-                        /* 10-12 summed over m^2 pixels), so it may be evaluated       */
-                        /* there; the plan picks its levels by a cost model.  Larger   */
-                        /* ratios save more work but average rounding errors over      */
-                        /* fewer pixels (a level's error grows about as n / m)         */
+                        /* triplet i <= j <= k with h_i + h_j + h_k < m and 2 h_k < m  */
+                        /* (h: a ring's largest |g_x|) closes exactly the same         */
+                        /* triangles on an m x m grid (Eqs. 10-12 summed over m^2      */
+                        /* pixels), so it may be evaluated there; the plan picks its   */
+                        /* levels by a cost model.  Larger ratios save more work but   */
+                        /* average rounding errors over fewer pixels (a level's error  */
+                        /* grows about as n / m)                                       */
 } abs_plan_desc;
 
 typedef struct abs_plan_info {
@@ -120,6 +121,8 @@ typedef struct abs_plan_info {
   int32_t nlevels;              /* resolution levels the plan runs (1: none below n);  */
                                 /* with several, the variants above are the first     */
                                 /* (largest) level's and the counts are summed        */
+  int32_t ring0;                /* abs_plan_level_info: the level's first ring (its   */
+                                /* nbins rings are ring0 .. ring0 + nbins - 1); 0 here */
 } abs_plan_info;
 
 /* Build a plan on the host: rings (Sec. 2), the triplet list with an exact lattice
@@ -135,8 +138,9 @@ abs_status abs_plan(const abs_plan_desc* desc, abs_plan_t* out);
 abs_status abs_plan_info_get(abs_plan_t plan, abs_plan_info* out);
 
 /* One resolution level of a plan (host only), 0 <= level < nlevels, largest first: its
- * grid side m (info->n), rings 0 .. nbins-1 it transforms, its triplets (ntrip, npairs)
- * and code variants; plan_bytes is 0 (the tables live in the parent's memory).  tmap:
+ * grid side m (info->n), the rings ring0 .. ring0 + nbins - 1 it transforms, its
+ * triplets (ntrip, npairs) and code variants; plan_bytes is 0 (the tables live in the
+ * parent's memory).  tmap:
  * host int32 [info->ntrip], the index in the plan's triplet list of each of the level's
  * triplets (ascending), or NULL.  A plan without levels reports itself as level 0.
  * Errors: ABS_ERR_INVALID. */

@@ -34,7 +34,7 @@ class PlanInfo(ctypes.Structure):
                 ("weight_parts", ctypes.c_int32), ("weight_jk", ctypes.c_int32),
                 ("weight_block", ctypes.c_int32), ("weight_waves", ctypes.c_int32),
                 ("mfma_tiles_per_wave", ctypes.c_int32), ("mfma_depth", ctypes.c_int32),
-                ("nlevels", ctypes.c_int32)]
+                ("nlevels", ctypes.c_int32), ("ring0", ctypes.c_int32)]
 
 
 class AbsError(RuntimeError):

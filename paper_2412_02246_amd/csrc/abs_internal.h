@@ -121,16 +121,18 @@ struct abs_plan_s {
   // all pixels is block 0 plus twice the others.
   int64_t npix64 = 0;
   std::vector<abs_impl::JitPart> parts;   // contraction code, compiled per part
-  // Resolution levels.  A triplet whose rings all hold |g_x|, |g_y| < m/3 closes exactly
-  // the same triangles on an m x m periodic grid as on the n x n one (a sum of three
-  // such cells is zero modulo m only if it is zero), and its ring fields on the m grid
-  // are those on the n grid sampled every n/m pixels.  Such a plan runs its triplets in
-  // level plans (`lv`, largest m first), each over m^2
-  // pixels with the rings 0 .. K-1 its triplets use; the parent forms the Hermitian part once
-  // (its hmax covers every level) and the smallest ring weight over all rings (for the
-  // empty-triplet rule), and owns no kernel code of its own.
+  // Resolution levels.  A triplet i <= j <= k with h_i + h_j + h_k < m and 2 h_k < m (h:
+  // a ring's largest |g_x|) closes exactly the same triangles on an m x m periodic grid
+  // as on the n x n one (a sum of three of its cells is zero modulo m only if it is zero),
+  // and its ring fields on the m grid are those on the n grid sampled every n/m pixels.
+  // Such a plan runs its triplets in level plans (`lv`, largest m first), each over m^2
+  // pixels with the rings ring0 .. ring0 + nb - 1 its triplets use (renumbered from 0);
+  // the parent forms the Hermitian part once (its hmax covers every level) and the
+  // smallest ring weight over all rings (for the empty-triplet rule), and owns no kernel
+  // code of its own.
   int max_ratio = 1;                     // largest n / m allowed for a level
   bool is_level = false;                 // a level plan of some parent
+  int ring0 = 0;                         // level plan: the parent's index of its ring 0
   std::vector<abs_plan_s*> lv;           // level plans (empty: the plan runs at n itself)
   std::vector<int32_t> tmap;             // level plan: parent index of each of its triplets
   int xc_hm = 0;                         // half extent of the Hermitian part its column pass reads

@@ -232,7 +232,7 @@ namespace {
 // 4 groups are needed (fewer slices re-read the fields).
 std::vector<int> split_groups(const abs_plan_s* p, const std::vector<int>& ord, int rw, bool jk, int* waves) {
   const int T = (int)p->ntrip;
-  const int kBudget = rw == 1 ? 200 : 184, kBudgetPairs = rw == 1 ? 232 : 224;
+  const int kBudget = rw == 1 ? 200 : 184, kBudgetPairs = rw == 1 ? 232 : 208;
   auto cost_ok = [&](int t0, int t1) {
     std::set<int> bins;
     int pairs = 0, pa = -1, pb = -1;
@@ -887,29 +887,32 @@ bool setup_kernels(abs_plan_s* p) {
   return build_jit_source(p);
 }
 
-// Resolution levels of a plan.  A triplet fits a level of size m when 3 h < m for each
-// of its rings (h: the ring's largest |g_x|, which is also its largest |g_y|): the sum of
-// three of its cells then has components in (-m, m), so it vanishes modulo m only where it
-// vanishes.  It runs in the smallest chosen level that fits it (the level at n, always
-// available, takes the rest, wrapped plans' cyclic triplets included; a level left without
-// triplets is dropped).  The sets of levels
-// drawn from n/2, n/4, ..., n / max_ratio (at least 16) are compared by a cost per call,
-// in units of one contraction flop on one set: per level, its FFT passes (each of its
-// rings over m^2 pixels, about kFftCost flops a pixel and ring), its contraction (pair
-// products and two flops per triplet, per pixel), both over max_batch data sets and one
-// weight set, and a fixed cost for its launches (kLevelCost, about 40 us).  The ratio is
-// bounded because the sum over m^2 pixels averages the fields' rounding errors over fewer
-// terms (the FP32 error of a level's sums grows about as n / m against the FP64
-// random-error scale of the full-grid sum).  ABS_EVERY_LEVEL takes every candidate level.
+// Resolution levels of a plan.  A triplet i <= j <= k fits a level of size m when
+// h_i + h_j + h_k < m and 2 h_k < m (h: a ring's largest |g_x|, which is also its largest
+// |g_y|): the x and y components of the sum of three of its cells then lie in (-m, m), so
+// the sum vanishes modulo m only where it vanishes, and no two cells of a ring share a
+// column or row of the m x m transform.  It runs in the smallest chosen level that fits it
+// (the level at n, always available, takes the rest, wrapped plans' cyclic triplets
+// included; a level left without triplets is dropped), and a level transforms only the
+// rings from its smallest i to its largest k.  The sets of levels drawn from n/2, n/4, ...,
+// n / max_ratio (at least 16) are compared by a cost per call, in units of one
+// contraction flop on one set: per level, its FFT passes (each of its rings over m^2
+// pixels, about kFftCost flops a pixel and ring), its contraction (pair products and two
+// flops per triplet, per pixel), both over max_batch data sets and one weight set, and a
+// fixed cost for its launches (kLevelCost, about 40 us).  The ratio is bounded because the
+// sum over m^2 pixels averages the fields' rounding errors over fewer terms (the FP32
+// error of a level's sums grows about as n / m against the FP64 random-error scale of the
+// full-grid sum).  ABS_EVERY_LEVEL takes every candidate level.
 void choose_levels(const abs_plan_s* p, std::vector<int>& sizes, std::vector<int>& level_of) {
   constexpr double kFftCost = 72.0, kLevelCost = 2.4e9;
   const int T = (int)p->ntrip, n = p->n;
   std::vector<int> need(T);
   for (int t = 0; t < T; ++t) {
     const int* x = &p->trips[3 * t];
+    const int hs = p->h[x[0]] + p->h[x[1]] + p->h[x[2]];
     const int hm = std::max(p->h[x[0]], std::max(p->h[x[1]], p->h[x[2]]));
     int m = 16;
-    while (3 * hm >= m && m <= n) m *= 2;
+    while ((hs >= m || 2 * hm >= m) && m <= n) m *= 2;
     need[t] = m;
   }
   std::vector<int> cand;
@@ -932,13 +935,14 @@ void choose_levels(const abs_plan_s* p, std::vector<int>& sizes, std::vector<int
     std::vector<int> keep, remap(lv.size(), -1);
     for (int L = 0; L < (int)lv.size(); ++L) {
       int64_t cnt = 0;
-      int K = 0;
+      int K0 = p->nb, K1 = 0;
       std::set<std::pair<int, int>> ij, jk;
       for (int t = 0; t < T; ++t) {
         if (lof[t] != L) continue;
         const int* x = &p->trips[3 * t];
         ++cnt;
-        K = std::max(K, x[2] + 1);
+        K0 = std::min(K0, x[0]);
+        K1 = std::max(K1, x[2] + 1);
         ij.insert({x[0], x[1]});
         jk.insert({x[1], x[2]});
       }
@@ -946,7 +950,8 @@ void choose_levels(const abs_plan_s* p, std::vector<int>& sizes, std::vector<int
       remap[L] = (int)keep.size();
       keep.push_back(lv[L]);
       const double m2 = (double)lv[L] * lv[L];
-      cost += sets * m2 * (kFftCost * K + (double)std::min(ij.size(), jk.size()) + 2.0 * cnt) + kLevelCost;
+      cost += sets * m2 * (kFftCost * (K1 - K0) + (double)std::min(ij.size(), jk.size()) + 2.0 * cnt) +
+              kLevelCost;
     }
     if (best < 0.0 || cost < best) {
       best = cost;
@@ -957,17 +962,22 @@ void choose_levels(const abs_plan_s* p, std::vector<int>& sizes, std::vector<int
   }
 }
 
-// A level plan of size m: rings 0 .. K-1 (K one past the largest ring its triplets use),
-// the given triplets of the parent (tidx, ascending) and its own FFT tiling, tables and
-// contraction code; its column pass reads the parent's Hermitian part.
+// A level plan of size m: the parent's rings K0 .. K1-1 (from the smallest i to the
+// largest k of its triplets), renumbered from 0; the given triplets of the parent (tidx,
+// ascending) in that numbering; its own FFT tiling, tables and contraction code.  Its
+// column pass reads the parent's Hermitian part.
 abs_plan_s* make_level(const abs_plan_s* p, int m, const std::vector<int32_t>& tidx) {
   abs_plan_s* q = new (std::nothrow) abs_plan_s;
   if (!q) return nullptr;
   q->is_level = true;
-  int K = 0;
-  for (int32_t t : tidx) K = std::max(K, p->trips[3 * t + 2] + 1);
+  int K0 = p->nb, K1 = 0;
+  for (int32_t t : tidx) {
+    K0 = std::min(K0, p->trips[3 * t]);
+    K1 = std::max(K1, p->trips[3 * t + 2] + 1);
+  }
   q->n = m;
-  q->nb = K;
+  q->nb = K1 - K0;
+  q->ring0 = K0;
   q->log2n = ilog2(m);
   q->du = p->du;
   q->theta0 = p->theta0;
@@ -976,14 +986,14 @@ abs_plan_s* make_level(const abs_plan_s* p, int m, const std::vector<int32_t>& t
   q->wmode = p->wmode;
   q->max_batch = p->max_batch;
   q->flags = p->flags;
-  q->edges.assign(p->edges.begin(), p->edges.begin() + K + 1);
-  q->lo2.assign(p->lo2.begin(), p->lo2.begin() + K);
-  q->hi2.assign(p->hi2.begin(), p->hi2.begin() + K);
+  q->edges.assign(p->edges.begin() + K0, p->edges.begin() + K1 + 1);
+  q->lo2.assign(p->lo2.begin() + K0, p->lo2.begin() + K1);
+  q->hi2.assign(p->hi2.begin() + K0, p->hi2.begin() + K1);
   setup_rings(q);
   q->xc_hm = p->hmax;
   q->tmap = tidx;
   for (int32_t t : tidx)
-    for (int c = 0; c < 3; ++c) q->trips.push_back(p->trips[3 * t + c]);
+    for (int c = 0; c < 3; ++c) q->trips.push_back(p->trips[3 * t + c] - K0);
   q->ntrip = (int64_t)tidx.size();
   q->npairs = count_pairs(q->trips);
   if (!setup_kernels(q)) {
@@ -1175,6 +1185,7 @@ void fill_info(const abs_plan_s* p, abs_plan_info* o) {
   o->mfma_tiles_per_wave = p->mfma_tpw;
   o->mfma_depth = p->mfma_depth;
   o->nlevels = 1;
+  o->ring0 = p->ring0;
 }
 }  // namespace
 

@@ -61,15 +61,17 @@ class Plan:
             "contract": (info.contract_parts, info.contract_jk, info.contract_block, info.contract_waves),
             "weight": (info.weight_parts, info.weight_jk, info.weight_block, info.weight_waves),
             "mfma": (info.mfma_tiles_per_wave, info.mfma_depth)}
-        # resolution levels, largest first: dicts with the level's grid side m, rings,
-        # triplets (their indices in self.triplets: "tmap"), pairs and code variants
+        # resolution levels, largest first: dicts with the level's grid side m, its rings
+        # ring0 .. ring0 + nbins - 1, triplets (their indices in self.triplets: "tmap"),
+        # pairs and code variants
         self.levels = []
         for lv in range(info.nlevels):
             li = L.PlanInfo()
             tm = np.zeros(max(1, self.ntrip), np.int32)
             L.check(lib.abs_plan_level_info(h, lv, ctypes.byref(li), tm.ctypes.data_as(ctypes.c_void_p)),
                     "abs_plan_level_info")
-            self.levels.append(dict(m=li.n, nbins=li.nbins, ntrip=li.ntrip, npairs=li.npairs, ncols=li.ncols,
+            self.levels.append(dict(m=li.n, ring0=li.ring0, nbins=li.nbins, ntrip=li.ntrip, npairs=li.npairs,
+                                    ncols=li.ncols,
                                     tmap=tm[:li.ntrip].copy(), mfma_tiles=li.mfma_tiles,
                                     contract=(li.contract_parts, li.contract_jk, li.contract_block,
                                               li.contract_waves),

@@ -1,6 +1,7 @@
 """GPU parity of resolution levels: plans whose triplets run on m x m grids (m = n/2 down
-to n/8, each triplet on the smallest level whose size exceeds three times its rings'
-largest |g_x|) against the FP64 oracle on every triplet, in every weight mode and
+to n/8, each triplet i <= j <= k on the smallest level with h_i + h_j + h_k < m and
+2 h_k < m, h a ring's largest |g_x|) against the FP64 oracle on every triplet, in every
+weight mode and
 precision form, for wrapped (cyclic) plans, with cached counts and for the complex
 estimator; and against the same plan evaluated at n alone.  Gates as in the other parity
 tests: e_t <= 1e-5 for FP32, 1e-4 for the split-precision forms."""
@@ -49,7 +50,7 @@ def _weights(rng, n, wmode):
 
 
 def _levels_of(p):
-    return [(lv["m"], lv["nbins"], lv["ntrip"]) for lv in p.levels]
+    return [(lv["m"], lv["ring0"], lv["nbins"], lv["ntrip"]) for lv in p.levels]
 
 
 CASES = {
@@ -140,8 +141,9 @@ def test_levels_cached_counts_and_complex_input():
 
 def test_mwa_1024_levels_against_single_level_and_oracle():
     """The 1024^2 / 20-ring MWA-shaped channel with the levels the cost model picks for
-    batches of 16 (1024 and 256), on two realisations with per-grid counts: every triplet
-    against the oracle, and against the same plan with every triplet at 1024."""
+    batches of 16 (1024 for rings 15-19, 512 for the rest), on two realisations with
+    per-grid counts: every triplet against the oracle, and against the same plan with every
+    triplet at 1024."""
     A = _A()
     torch = _torch()
     n = 1024
@@ -150,7 +152,7 @@ def test_mwa_1024_levels_against_single_level_and_oracle():
     g = torch.from_numpy(np.stack(grids)).to(torch.complex64).cuda()
     wt = torch.from_numpy(np.stack(ws).astype(np.float32)).cuda()
     p = A.Plan(n, e, wmode=A.W_INV_COUNT, max_batch=16)
-    assert _levels_of(p) == [(1024, 20, 330), (256, 14, 360)], _levels_of(p)
+    assert _levels_of(p) == [(1024, 15, 5, 9), (512, 0, 20, 681)], _levels_of(p)
     q = A.Plan(n, e, wmode=A.W_INV_COUNT, max_batch=16, levels=1)
     assert len(q.levels) == 1
     p.bind()
@@ -163,7 +165,7 @@ def test_mwa_1024_levels_against_single_level_and_oracle():
         ref = oest.estimate(grids[b], ws[b], e, p.norm, wmode=oest.INV_COUNT, trips=p.triplets, with_scales=True)
         e_lv = _check(B[b], N[b], ref, p.norm, label="mwa1024 levels [%d]" % b)
         e_one = _check(B1[b], N1[b], ref, p.norm, label="mwa1024 single [%d]" % b)
-        # the level at 256 sums over 1/16 of the pixels: its rounding error is larger but
-        # within the same gate
-        lv256 = np.isin(np.arange(p.ntrip), p.levels[1]["tmap"])[~np.isnan(ref["B"])]
-        print("  level 256 max e_t %.3g (single level %.3g)" % (e_lv[lv256].max(), e_one[lv256].max()), flush=True)
+        # the level at 512 sums over a quarter of the pixels: its rounding error is larger
+        # but within the same gate
+        lv = np.isin(np.arange(p.ntrip), p.levels[1]["tmap"])[~np.isnan(ref["B"])]
+        print("  level 512 max e_t %.3g (single level %.3g)" % (e_lv[lv].max(), e_one[lv].max()), flush=True)

@@ -95,7 +95,7 @@ def test_runtime_compilation_without_device():
 def test_workspace_sizes():
     A = _A()
     n, e = CASES["c2_1024_20log"]
-    p = A.Plan(n, e, max_batch=4, wmode=A.W_INV_COUNT)
+    p = A.Plan(n, e, max_batch=4, wmode=A.W_INV_COUNT, levels=1)   # one level: the layout below
     shared = p.estimate_workspace(4, False)
     per = p.estimate_workspace(4, True)
     cached = p.estimate_workspace(4, False, True)
@@ -193,10 +193,11 @@ def test_generated_contraction_kernels_do_not_spill(which):
     FP64 weight kernels, every part) compiles without register spills: the triplet groups'
     register estimate keeps spill code (scratch memory in the inner loop) out."""
     A = _A()
-    n, nb = {"1024x20": (1024, 20), "4096x32": (4096, 32), "8192x64": (8192, 64)}[which]
+    n, nb, mb = {"1024x20": (1024, 20, 16), "4096x32": (4096, 32, 16), "8192x64": (8192, 64, 8)}[which]
     s = n / 1024.0
     e = oplan.log_edges(s * 46 / (2 * np.pi), s * 1320 / (2 * np.pi), nb)
-    p = A.Plan(n, e, wmode=A.W_INV_COUNT)
+    # the benchmark's batch sizes, which set the resolution levels
+    p = A.Plan(n, e, wmode=A.W_INV_COUNT, max_batch=mb)
     p.compile(workers=8)
     for part in range(p.jit_parts):
         _, blob = p.code(part)
@@ -214,13 +215,14 @@ def _ring_h(n, edges):
 
 
 LEVEL_CASES = {
-    # (n, edges, max_batch, levels, flags, the levels the plan picks: (m, rings, triplets))
+    # (n, edges, max_batch, levels, flags, the levels the plan picks: (m, ring0, rings,
+    # triplets))
     "mwa1024_b16": (1024, oplan.log_edges(46 / (2 * np.pi), 1320 / (2 * np.pi), 20), 16, 0, 0,
-                    [(1024, 20, 330), (256, 14, 360)]),
+                    [(1024, 15, 5, 9), (512, 0, 20, 681)]),
     "mwa4096_b16": (4096, oplan.log_edges(4 * 46 / (2 * np.pi), 4 * 1320 / (2 * np.pi), 32), 16, 0, 0,
-                    [(4096, 32, 240), (2048, 30, 777), (1024, 23, 1292)]),
+                    [(4096, 24, 8, 23), (2048, 0, 32, 679), (1024, 0, 27, 1607)]),
     "mwa8192_b8": (8192, oplan.log_edges(8 * 46 / (2 * np.pi), 8 * 1320 / (2 * np.pi), 64), 8, 0, 0,
-                   [(8192, 64, 1528), (4096, 60, 5030), (2048, 46, 8671)]),
+                   [(8192, 48, 16, 109), (4096, 0, 64, 4285), (2048, 0, 54, 10835)]),
     "every_256": (256, oplan.log_edges(3.0, 85.0, 16), 2, 8, 4, None),
     "wrap_128": (128, oplan.log_edges(2.0, 60.0, 12), 2, 8, 5, None),
 }
@@ -229,19 +231,26 @@ LEVEL_CASES = {
 @pytest.mark.parametrize("name", sorted(LEVEL_CASES))
 def test_resolution_levels(name):
     """Levels partition the triplets; every level's triplets close their triangles exactly
-    on its m x m grid (3 h < m for each of their rings, h the ring's largest |g_x|) and sit
-    in the smallest of the plan's levels that allows this; a level transforms the rings up
-    to its largest k; sizes are n / 2^j within the ratio.  The three workloads' choices are
-    pinned."""
+    on its m x m grid (h_i + h_j + h_k < m and 2 h_k < m, h a ring's largest |g_x|) and sit
+    in the smallest of the plan's levels that allows this; a level transforms the rings
+    from its smallest i to its largest k; sizes are n / 2^j within the ratio.  The three
+    workloads' choices are pinned."""
     A = _A()
     n, e, mb, ratio, flags, want = LEVEL_CASES[name]
     p = A.Plan(n, e, max_batch=mb, levels=ratio, flags=flags)
-    got = [(lv["m"], lv["nbins"], lv["ntrip"]) for lv in p.levels]
+    got = [(lv["m"], lv["ring0"], lv["nbins"], lv["ntrip"]) for lv in p.levels]
     if want is not None:
         assert got == want, got
     h = _ring_h(n, e)
     T = p.triplets
-    need = np.array([16 * 2 ** int(max(0, np.ceil(np.log2((3 * h[t].max() + 1) / 16.0)))) for t in T])
+
+    def need(t):
+        m = 16
+        while h[t].sum() >= m or 2 * h[t].max() >= m:
+            m *= 2
+        return m
+
+    need = np.array([need(t) for t in T])
     sizes = sorted(lv["m"] for lv in p.levels)
     seen = np.zeros(p.ntrip, int)
     for lv in p.levels:
@@ -249,10 +258,9 @@ def test_resolution_levels(name):
         assert n % m == 0 and (n // m) & (n // m - 1) == 0 and n // m <= (ratio or 4)
         assert np.all(np.diff(tm) > 0)
         seen[tm] += 1
-        assert lv["nbins"] == T[tm, 2].max() + 1
-        fits = need[tm] <= m
+        assert lv["ring0"] == T[tm, 0].min() and lv["ring0"] + lv["nbins"] == T[tm, 2].max() + 1
         if m < n:
-            assert fits.all(), name
+            assert np.all(need[tm] <= m), name
         # the smallest level of the plan that fits each triplet
         smallest = np.array([min([s for s in sizes if s >= need[t]] or [n]) for t in tm])
         assert np.array_equal(smallest, np.full(len(tm), m)), name
