@@ -19,7 +19,9 @@ estimator for radio-interferometric data":
                    discretely-sampled average, plus the paper's constants.
 * ``analysis``  -- the (ell1, mu, t) re-binning of the triplet estimates, ensemble mean
                    and sigma, and the deviation metrics of Secs. 3-4.
+* ``simulate``  -- visibilities of a flat-sky field through the primary beam, Eq. (4)
+                   with Eqs. (5)/(6), by direct summation.
 
 Parity status per function is stated in each module header.
 """
-from . import plan, estimator, brute, gridding, theory, analysis  # noqa: F401
+from . import plan, estimator, brute, gridding, theory, analysis, simulate  # noqa: F401

@@ -14,6 +14,7 @@ C64, C128 = 0, 1
 NEAREST, GAUSS7 = 0, 1
 STAGE_CONTRACT, STAGE_COLPASS, STAGE_ROWPASS, STAGE_GRID = 0, 1, 2, 3
 ALLOW_WRAP, ALLOW_DC, EVERY_LEVEL = 1, 2, 4
+BEAM_NONE, BEAM_MWA, BEAM_GAUSS = 0, 1, 2
 
 
 class PlanDesc(ctypes.Structure):
@@ -81,6 +82,8 @@ def lib():
         "abs_ensemble": [i32, i32, _P, _P, _P, _P, _P, _P, _P],
         "abs_model_workspace": [_P, ctypes.POINTER(sz)],
         "abs_model_discrete": [_P, _P, _P, dbl, _P, sz, _P, _P],
+        "abs_simulate_workspace": [i32, ctypes.POINTER(sz)],
+        "abs_simulate": [i32, dbl, i32, dbl, dbl, i32, _P, i64, _P, _P, _P, sz, _P],
         "abs_sync": [_P, _P],
         "abs_profile": [_P, i32, _P, _P],
         "abs_destroy": [_P],

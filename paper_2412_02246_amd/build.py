@@ -13,7 +13,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code of this library.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["plan.cpp", "fft.hip", "grid.hip", "estimate.hip", "mfma.hip", "analysis.hip"]
+SOURCES = ["plan.cpp", "fft.hip", "grid.hip", "estimate.hip", "mfma.hip", "analysis.hip", "simulate.hip"]
 
 
 def _run(cmd):

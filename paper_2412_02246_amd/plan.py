@@ -327,3 +327,32 @@ def ensemble(X, model=None, stream=None):
     L.check(L.lib().abs_ensemble(nreal, nv, _ptr(X), _ptr(model), _ptr(mean), _ptr(sigma), _ptr(dB), _ptr(dS),
                                  _stream(stream)), "abs_ensemble")
     return mean, sigma, dB, dS
+
+
+def simulate(sky, dtheta, uv, beam=L.BEAM_NONE, beam_param=0.0, q=1.0, stream=None, work=None):
+    """Visibilities of flat-sky brightness fields at baselines (Eq. 4), on the device.
+
+    sky   torch float32 [batch][N][N] or [N][N] (row = theta_y index, column = theta_x),
+          pixel (a, b) at ((a - N/2), (b - N/2)) dtheta, N a power of two in [16, 4096]
+    uv    torch float64 [nvis][2] baselines in wavelengths
+    beam  BEAM_NONE, BEAM_MWA (Eq. 5, beam_param = tile side / wavelength) or BEAM_GAUSS
+          (Eq. 6, beam_param = theta0 in radians)
+    Returns torch complex64 [batch][nvis]."""
+    import torch
+    if sky.dim() == 2:
+        sky = sky.unsqueeze(0)
+    if sky.dtype != torch.float32 or not sky.is_contiguous() or sky.shape[1] != sky.shape[2]:
+        raise ValueError("sky must be a contiguous float32 [batch][N][N] tensor")
+    if uv.dtype != torch.float64 or not uv.is_contiguous() or uv.dim() != 2 or uv.shape[1] != 2:
+        raise ValueError("uv must be a contiguous float64 [nvis][2] tensor")
+    batch, nsky, nvis = sky.shape[0], sky.shape[1], uv.shape[0]
+    b = ctypes.c_size_t()
+    L.check(L.lib().abs_simulate_workspace(nsky, ctypes.byref(b)), "abs_simulate_workspace")
+    if work is None or work.numel() < b.value:
+        work = torch.empty(b.value + 256, dtype=torch.uint8, device=sky.device)
+    off = (-work.data_ptr()) % 256
+    vis = torch.empty((batch, nvis), dtype=torch.complex64, device=sky.device)
+    L.check(L.lib().abs_simulate(nsky, float(dtheta), int(beam), float(beam_param), float(q), batch, _ptr(sky),
+                                 nvis, _ptr(uv), _ptr(vis), ctypes.c_void_p(work.data_ptr() + off),
+                                 work.numel() - off, _stream(stream)), "abs_simulate")
+    return vis
