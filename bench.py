@@ -40,6 +40,12 @@ WORKLOADS = {
     "mwa8192": dict(n=8192, nbins=64, lmin=8 * 46.0, lmax=8 * 1320.0, batch=8, cfg=4,
                     desc="large ensemble: 8192x8192 c64 grids, 64 log rings 8x(46<=l<1320) (15229 triplets), "
                          "realisations of one channel, 8 a step, INV_COUNT weights from the gridded counts"),
+    # multi-frequency form: 4 channels of the 1024^2 channel's geometry, 16 log rings; each
+    # step grids and estimates 4 multi-frequency grids (16 channel grids), every channel
+    # triplet (ring triplet x channel combination)
+    "mf1024": dict(n=1024, nbins=16, lmin=46.0, lmax=1320.0, batch=4, cfg=1, nchan=4,
+                   desc="multi-frequency: 4 channels of 1024x1024 c64 grids, 16 log rings 46<=l<1320, every "
+                        "channel triplet, 4 multi-frequency grids (16 channel grids) a step, INV_COUNT weights"),
 }
 DEFAULT_WORKLOAD = "mwa8192"
 
@@ -84,9 +90,10 @@ PEAK_HBM = 8.0e12
 
 # HBM bytes per launch of the timed contraction kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by a 1 GiB copy (2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE), for the
-# kernel as it stands in this tree and the workload's default batch (profiles/counters_mwa8192_batch8_fp32.md); keyed by
+# kernels as they stand in this tree and the workload's default batch, summed over the level launches
+# (profiles/counters_mwa8192_batch8.md); keyed by
 # (workload, precision).  A workload or precision without an entry reports null.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {("mwa8192", "fp32"): 86.66e9}
 
 
 def edges_of(W):
@@ -99,7 +106,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + ["serve", "copy"])
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + ["serve", "copy", "sim4096"])
     ap.add_argument("--requests", type=int, default=512, help="serve: number of requests")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serve: admission budget")
     ap.add_argument("--batch", type=int, default=0)
@@ -195,6 +202,49 @@ def cpu_baseline_sampled(n, edges, trips, uv, vis0, norm):
                       "all %d triplets over %d of %d rows %.2f s, x %d x 2; scipy FFT on %d threads, BLAS on "
                       "%d threads" % (time.perf_counter() - T0, t_total, S, nvis, t_s, t_grid, t_herm, k,
                                       t_ring, 2 * nb, len(trips), R, n, t_sum, n // R, fft, blas)}
+
+
+def sim_bench(a):
+    """Visibility simulation (Eq. 4 through the Eq. 5 beam) at the paper's geometry: 4096^2
+    skies of 0.029 deg pixels, 2^20 baselines with density ~ exp(-U / 62.5) inside U = 250
+    wavelengths, 4 skies a step.  Reports visibilities/s, and the HBM fraction of the
+    transform (its algorithmic bytes: the row transforms write N x M complex values, the
+    transpose reads and writes them, the column transforms read them and write M^2; 8 bytes
+    a value) from HIP events around the whole call."""
+    import torch
+
+    import paper_2412_02246_amd as A
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    nsky, dth, nvis, batch = 4096, np.deg2rad(0.029), 1 << 20, a.batch or 4
+    d_lam = 4.0 * 154.25e6 / 299792458.0
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(20241202)
+    sky = torch.randn((batch, nsky, nsky), dtype=torch.float32, device=dev, generator=gen)
+    r = -62.5 * torch.log1p(-torch.rand(nvis, dtype=torch.float64, device=dev, generator=gen) *
+                            (1 - np.exp(-250.0 / 62.5)))
+    ph = 2 * np.pi * torch.rand(nvis, dtype=torch.float64, device=dev, generator=gen)
+    uv = torch.stack([r * torch.cos(ph), r * torch.sin(ph)], dim=1).contiguous()
+    for _ in range(a.warmup):
+        A.simulate(sky, dth, uv, beam=A.BEAM_MWA, beam_param=d_lam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        V = A.simulate(sky, dth, uv, beam=A.BEAM_MWA, beam_param=d_lam)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    m = 2 * nsky
+    fft_bytes = 8.0 * (nsky * m + 2 * nsky * m + nsky * m + m * m) * batch
+    out = {"metric": "simulated visibilities/s at 1 GPU (Eq. 4, MWA beam, non-uniform FFT)",
+           "value": nvis * batch / dt, "unit": "visibilities/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "4096^2 skies of 0.029 deg pixels, MWA tile beam, 2^20 baselines within U = 250, "
+                                  "%d skies a step" % batch, "skies_per_s": batch / dt,
+                      "transform_alg_bytes": fft_bytes,
+                      "transform_bytes_over_call_frac_hbm": fft_bytes / dt / 8.0e12}}
+    del V
+    print(json.dumps(out), flush=True)
 
 
 def copy_probe(a):
@@ -369,7 +419,8 @@ def measure(name, precision, plan, uv_d, vis_d, steps, warmup, log=sys.stderr):
     import paper_2412_02246_amd as A
     W = WORKLOADS[name]
     n, nb = W["n"], W["nbins"]
-    batch = vis_d.shape[0]
+    C = plan.nchan
+    batch = vis_d.shape[0] // C      # grids (multi-frequency grids of C channel grids each)
     nvis = uv_d.shape[0]
 
     def step():
@@ -442,9 +493,9 @@ def measure(name, precision, plan, uv_d, vis_d, steps, warmup, log=sys.stderr):
         step()
     torch.cuda.synchronize()
     # column pass and row pass of every resolution level (m, its rings and columns)
-    zbytes = sum(8.0 * lv["m"] * lv["ncols"] for lv in plan.levels) * batch
-    fbytes = sum(4.0 * lv["nbins"] * lv["m"] ** 2 for lv in plan.levels) * batch
-    alg = {L.STAGE_GRID: 16.0 * nvis + batch * (8.0 * nvis + 8.0 * n * n) + 4.0 * n * n,
+    zbytes = sum(8.0 * lv["m"] * lv["ncols"] for lv in plan.levels) * batch * C
+    fbytes = sum(4.0 * lv["nbins"] * lv["m"] ** 2 for lv in plan.levels) * batch * C
+    alg = {L.STAGE_GRID: 16.0 * nvis + batch * C * (8.0 * nvis + 8.0 * n * n) + 4.0 * n * n,
            L.STAGE_COLPASS: zbytes,
            L.STAGE_ROWPASS: zbytes + fbytes}
     tot_b = tot_ms = 0.0
@@ -476,6 +527,8 @@ def main():
         return serve_bench(a)
     if a.workload == "copy":
         return copy_probe(a)
+    if a.workload == "sim4096":
+        return sim_bench(a)
     import torch
 
     import paper_2412_02246_amd as A
@@ -500,7 +553,7 @@ def main():
     plans, specs = [], []
     for wname, prec, b in jobs:
         Wj = WORKLOADS[wname]
-        kw = dict(wmode=A.W_INV_COUNT, max_batch=b, precision=P[prec])
+        kw = dict(wmode=A.W_INV_COUNT, max_batch=b, precision=P[prec], nchan=Wj.get("nchan", 1))
         plans.append(A.Plan(Wj["n"], edges_of(Wj), **kw))
         specs.append((Wj["n"], tuple(edges_of(Wj)), kw))
     compile_parts(plans, specs, workers=16)
@@ -519,7 +572,7 @@ def main():
               file=sys.stderr, flush=True)
         return uv_d, vis_d
 
-    uv_d, vis_d = inputs(name, batch)
+    uv_d, vis_d = inputs(name, batch * W.get("nchan", 1))
     main_plan = plans[0].bind()
     res = measure(name, a.precision, main_plan, uv_d, vis_d, a.steps, a.warmup)
     ntrip = int(main_plan.ntrip)

@@ -99,6 +99,14 @@ typedef struct abs_plan_desc {
                         /* levels by a cost model.  Larger ratios save more work but   */
                         /* average rounding errors over fewer pixels (a level's error  */
                         /* grows about as n / m)                                       */
+  int32_t nchan;        /* channels of a multi-frequency plan (0 or 1: one channel).   */
+                        /* With nchan = C > 1 (C x nbins <= 64) the plan estimates the */
+                        /* multi-frequency angular bispectrum, Eq. (12) with the three  */
+                        /* fields taken at channels a, b, c (Sec. 1 names the multi-   */
+                        /* frequency and 3-D bispectrum as the next step): triplets run */
+                        /* over channel rings s = c nbins + r, every non-decreasing     */
+                        /* (s1, s2, s3) whose rings, sorted, form a plan triplet; each  */
+                        /* grid of a call is C consecutive channel grids               */
 } abs_plan_desc;
 
 typedef struct abs_plan_info {
@@ -123,6 +131,7 @@ typedef struct abs_plan_info {
                                 /* (largest) level's and the counts are summed        */
   int32_t ring0;                /* abs_plan_level_info: the level's first ring (its   */
                                 /* nbins rings are ring0 .. ring0 + nbins - 1); 0 here */
+  int32_t nchan;                /* channels (1 unless a multi-frequency plan)          */
 } abs_plan_info;
 
 /* Build a plan on the host: rings (Sec. 2), the triplet list with an exact lattice
@@ -147,7 +156,9 @@ abs_status abs_plan_info_get(abs_plan_t plan, abs_plan_info* out);
 abs_status abs_plan_level_info(abs_plan_t plan, int32_t level, abs_plan_info* info, int32_t* tmap);
 
 /* Host copies of the triplet list, labels and ring radii; any pointer may be NULL.
- *   ijk      int32  [ntrip][3]  ring indices i <= j <= k
+ *   ijk      int32  [ntrip][3]  ring indices i <= j <= k (multi-frequency plans: channel
+ *                               rings s = c nbins + r, s1 <= s2 <= s3; labels then come
+ *                               from the rings sorted by size)
  *   labels   double [ntrip][5]  (ell1, ell2, ell3, mu, t) from the rings' mean radii,
  *                               ell = 2 pi du <|g|>, mu = (l1^2 + l2^2 - l3^2) / (2 l1 l2),
  *                               t = l2 / l1 (Sec. 2, below Eq. 3 and after Eq. 12)
@@ -199,7 +210,8 @@ abs_status abs_grid_workspace(abs_plan_t plan, int64_t nvis, int32_t batch, size
  * even, FP64) and, because the sky is real (Eq. 4), its conjugate goes to -g.
  * Visibilities with any |g| component >= n/2 are dropped and counted.
  *   nvis     number of visibilities (baselines), >= 0
- *   batch    realisations sharing the baselines, 1 <= batch <= max_batch
+ *   batch    realisations sharing the baselines, 1 <= batch <= max_batch (max_batch x
+ *            nchan for a multi-frequency plan: one per channel grid)
  *   uv       device double [nvis][2]  (u, v) in wavelengths
  *   vis      device float  [batch][nvis][2]  (re, im)
  *   vis_w    device float  [nvis] per-visibility weights, or NULL for 1
@@ -220,7 +232,9 @@ abs_status abs_grid(abs_plan_t plan, int64_t nvis, int32_t batch, const double* 
 /* The estimator, Eqs. (10)-(12), for `batch` gridded-visibility arrays.
  *   batch      1 <= batch <= max_batch
  *   dtype      ABS_C64 (float pairs) or ABS_C128 (double pairs, rounded to FP32 on load)
- *   grids      device [batch][n][n] complex
+ *   grids      device [batch][n][n] complex ([batch][nchan][n][n] for a multi-frequency
+ *              plan: w, if batched, likewise; shared weights are one [n][n] array for every
+ *              channel)
  *   w          device float [n][n] (w_batched = 0) or [batch][n][n] (w_batched = 1),
  *              interpreted by the plan's wmode; may be NULL only for ABS_W_UNIT
  *   n_given    device double [ntrip] weighted triangle counts N_t previously returned
@@ -245,7 +259,7 @@ abs_status abs_estimate(abs_plan_t plan, int32_t batch, int32_t dtype, const voi
  *   work   device workspace of abs_estimate_complex_workspace bytes (four data sets a grid)
  *   B      device double [batch][ntrip][2]  (Re B_t, Im B_t), NaN for empty triplets
  * The weights must be real, non-negative and symmetric as for abs_estimate.  Errors: as
- * abs_estimate. */
+ * abs_estimate; ABS_ERR_INVALID for a multi-frequency plan. */
 abs_status abs_estimate_complex_workspace(abs_plan_t plan, int32_t batch, int32_t w_batched, int32_t have_counts,
                                           size_t* bytes);
 abs_status abs_estimate_complex(abs_plan_t plan, int32_t batch, int32_t dtype, const void* grids, const float* w,
@@ -328,8 +342,8 @@ abs_status abs_model_workspace(abs_plan_t plan, size_t* bytes);
  *   f      f_NG / sigma_T of Eq. (13)
  *   work   device, abs_model_workspace bytes, 256-byte aligned
  *   out    device double [ntrip]; NaN for empty triplets (as B_t)
- * Asynchronous on `stream`.  Errors: ABS_ERR_INVALID, ABS_ERR_UNBOUND, ABS_ERR_NOMEM,
- * ABS_ERR_DEVICE. */
+ * Asynchronous on `stream`.  Errors: ABS_ERR_INVALID (also for a multi-frequency plan),
+ * ABS_ERR_UNBOUND, ABS_ERR_NOMEM, ABS_ERR_DEVICE. */
 abs_status abs_model_discrete(abs_plan_t plan, const float* w, const float* c, double f, void* work,
                               size_t work_bytes, double* out, void* stream);
 

@@ -24,6 +24,9 @@ Readings of the paper where it is silent or ambiguous:
   N_t < w_min^3 / 2 therefore holds no weighted triangle (its N_t is rounding noise
   of an exact zero) and its B_t is NaN; N_t is still reported.
 
+``estimate_multifreq`` takes the three fields of a triplet at three channels (the
+multi-frequency form the paper names as its next step, Sec. 1).
+
 Pins: tests/test_oracle_estimator.py (brute force over closed triangles on
 n = 8, 16, 32 in cyclic and planar form, integer counts, invariants, the
 two-field Parseval special case, zero-mean Gaussian and the closed-form
@@ -217,6 +220,47 @@ def estimate_subset(grid, w, edges, norm, trips, wmode=UNIT):
     out["B"] = ratio(out["S"], out["N"], norm, wmin)
     out["trips"] = trips
     return out
+
+
+def estimate_multifreq(grids, w, edges, norm, wmode=UNIT, trips=None, chunk=1 << 16):
+    """Multi-frequency form of Eq. (12): the three fields of a triplet taken at channels
+    a, b, c (Sec. 1 names multi-frequency observations as the estimator's next step):
+    B = (1/A) sum_theta D_i(a) D_j(b) D_k(c) / sum_theta I_i(a) I_j(b) I_k(c).
+
+    grids : complex [C][n][n], one gridded-visibility array per channel
+    w     : [n][n] weights shared by every channel, or [C][n][n] (ignored for UNIT)
+    trips : (T, 3) channel rings s = c nb + r, s1 <= s2 <= s3 (default: every such triple
+            whose rings, sorted, form a plan triplet)
+    Returns the keys of estimate(..., with_scales=True); w_min is the smallest over the
+    channels (the empty-triplet rule of ``ratio``)."""
+    from . import plan as _plan
+    grids = np.asarray(grids).astype(np.complex128)
+    C, n = grids.shape[0], grids.shape[1]
+    nb = len(edges) - 1
+    if trips is None:
+        ring_trips, _ = _plan.plan_triplets(n, edges)
+        ok = {tuple(int(x) for x in t) for t in ring_trips}
+        trips = [(s1, s2, s3) for s1 in range(C * nb) for s2 in range(s1, C * nb) for s3 in range(s2, C * nb)
+                 if tuple(sorted((s1 % nb, s2 % nb, s3 % nb))) in ok]
+    trips = np.asarray(trips, dtype=np.int64).reshape(-1, 3)
+    masks = _plan.ring_masks(n, edges)
+    D, I, wmins = [], [], []
+    for c in range(C):
+        wc = None if wmode == UNIT else (w[c] if np.ndim(w) == 3 else w)
+        W = effective_weights(n, wc, wmode)
+        X = hermitian_part(W * grids[c])
+        Y = hermitian_part(W.astype(np.complex128))
+        D.append(ring_fields(X, masks))
+        I.append(ring_fields(Y, masks))
+        wmins.append(min_weight(Y.real, masks))
+    D = np.concatenate(D)           # channel ring s = c nb + r
+    I = np.concatenate(I)
+    S = triple_sums(D, trips, chunk)
+    N = triple_sums(I, trips, chunk)
+    wmin = min(wmins)
+    return dict(B=ratio(S, N, norm, wmin), S=S, N=N, trips=trips, wmin=wmin,
+                rhoS=np.sqrt(np.maximum(triple_sums(D, trips, chunk, power=2), 0.0) / n ** 2),
+                rhoN=np.sqrt(np.maximum(triple_sums(I, trips, chunk, power=2), 0.0) / n ** 2))
 
 
 def relative_error(B, ref, norm):

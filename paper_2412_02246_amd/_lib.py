@@ -22,7 +22,8 @@ class PlanDesc(ctypes.Structure):
                 ("edges", ctypes.POINTER(ctypes.c_double)), ("du", ctypes.c_double),
                 ("norm", ctypes.c_double), ("theta0", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("wmode", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32), ("flags", ctypes.c_uint32), ("levels", ctypes.c_int32)]
+                ("max_batch", ctypes.c_int32), ("flags", ctypes.c_uint32), ("levels", ctypes.c_int32),
+                ("nchan", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -35,7 +36,7 @@ class PlanInfo(ctypes.Structure):
                 ("weight_parts", ctypes.c_int32), ("weight_jk", ctypes.c_int32),
                 ("weight_block", ctypes.c_int32), ("weight_waves", ctypes.c_int32),
                 ("mfma_tiles_per_wave", ctypes.c_int32), ("mfma_depth", ctypes.c_int32),
-                ("nlevels", ctypes.c_int32), ("ring0", ctypes.c_int32)]
+                ("nlevels", ctypes.c_int32), ("ring0", ctypes.c_int32), ("nchan", ctypes.c_int32)]
 
 
 class AbsError(RuntimeError):

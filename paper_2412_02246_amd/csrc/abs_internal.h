@@ -61,6 +61,8 @@ struct WorkLayout {
   int nsets;          // D sets followed by I sets
   int ndsets;         // D sets (spg per grid)
   int nisets;
+  int npsets;         // contraction partial sets of the data (ndsets / nchan)
+  int nipsets;        // and of the weights (nisets / nchan)
   size_t zd, zi, fd, fi, part, part64, fmax, wmin, xc, total;
   int64_t zset;       // complex elements per set of column-pass output
   int64_t fset;       // values per set of data fields (nbins * n * n)
@@ -78,6 +80,12 @@ struct WorkLayout {
 struct abs_plan_s {
   // descriptor
   int n = 0, nb = 0, log2n = 0;
+  // Multi-frequency plans: nchan channels of the same rings; every data set of a call is
+  // one channel of one multi-frequency grid (channel-major), the FFT passes transform each
+  // channel's nb rings, and the contraction runs over nbc = nchan * nb "channel rings"
+  // s = c * nb + r (ring r of channel c), which are contiguous in memory because the
+  // channels' fields are consecutive sets.  Single-frequency plans have nchan = 1.
+  int nchan = 1, nbc = 0;
   double du = 1.0, norm = 0.0, theta0 = 0.0;
   int precision = 0, wmode = 0, max_batch = 1;
   uint32_t flags = 0;

@@ -194,6 +194,7 @@ abs_status abs_model_discrete(abs_plan_t p, const float* w, const float* c, doub
   if (s != ABS_OK) return s;
   if (!c || !work || !out || (!w && p->wmode != ABS_W_UNIT)) return ABS_ERR_INVALID;
   if (reinterpret_cast<uintptr_t>(work) & 255) return ABS_ERR_INVALID;
+  if (p->nchan > 1) return ABS_ERR_INVALID;   // the model of Eq. (14) is a single-frequency one
   const ModelWork ml = model_layout(p);
   if (work_bytes < ml.total) return ABS_ERR_NOMEM;
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -70,6 +70,14 @@ __device__ __forceinline__ double sum_partials_half(const double* __restrict__ p
   return b0 + 2.0 * rest;
 }
 
+// Smallest non-zero ring-cell weight over the spw data sets of grid b (its channels, or the
+// four sets of a complex grid), from the bit patterns the Hermitian-part pass recorded.
+__device__ __forceinline__ double min_weight(const unsigned long long* __restrict__ wmin_bits, int b, int spw) {
+  unsigned long long m = wmin_bits[(long long)b * spw];
+  for (int c = 1; c < spw; ++c) m = m < wmin_bits[(long long)b * spw + c] ? m : wmin_bits[(long long)b * spw + c];
+  return __longlong_as_double((long long)m);
+}
+
 // B[b][t] = S / (A N), S and N the per-triangle sums: workgroup partials are added
 // in FP64 in a fixed order and divided by n^2 (the sum over pixels of a product of
 // three DFTs counts every closed triangle n^2 times; m^2 for a level of size m).
@@ -83,7 +91,7 @@ __global__ void __launch_bounds__(kFinBlock)
 finalize_kernel(const double* __restrict__ part, long long partset, int nblk, const int* __restrict__ pos,
                 const double* __restrict__ part64, long long partset64, int nblk64,
                 const int* __restrict__ pos64, int ntrip, int batch, int nisets,
-                const double* __restrict__ n_given, const unsigned long long* __restrict__ wmin_bits,
+                const double* __restrict__ n_given, const unsigned long long* __restrict__ wmin_bits, int spw,
                 double inv_npix, double norm, const int* __restrict__ tmap, int ntrip_out,
                 double* __restrict__ B, double* __restrict__ N) {
   const int t = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -98,7 +106,7 @@ finalize_kernel(const double* __restrict__ part, long long partset, int nblk, co
     nn = sum_partials_half(part64 + (long long)is * partset64, nblk64, ntrip, pos64, t) * inv_npix;
   }
   if (threadIdx.x < 64 && t < ntrip) {
-    const double wm = __longlong_as_double((long long)wmin_bits[b]);
+    const double wm = min_weight(wmin_bits, b, spw);
     B[(long long)b * ntrip_out + to] = nn < 0.5 * wm * wm * wm ? __builtin_nan("") : s / (norm * nn);
     if (N) N[(long long)b * ntrip_out + to] = nn;
   }
@@ -114,7 +122,7 @@ __global__ void __launch_bounds__(kFinBlock)
 finalize_complex_kernel(const double* __restrict__ part, long long partset, int nblk, const int* __restrict__ pos,
                         const double* __restrict__ part64, long long partset64, int nblk64,
                         const int* __restrict__ pos64, int ntrip, int nisets, const double* __restrict__ n_given,
-                        const unsigned long long* __restrict__ wmin_bits, double inv_npix, double norm,
+                        const unsigned long long* __restrict__ wmin_bits, int spw, double inv_npix, double norm,
                         const int* __restrict__ tmap, int ntrip_out, double* __restrict__ B,
                         double* __restrict__ N) {
   const int t = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -133,7 +141,7 @@ finalize_complex_kernel(const double* __restrict__ part, long long partset, int 
   if (threadIdx.x < 64 && t < ntrip) {
     const double re = 2.0 * T[0] - 0.5 * (T[2] + T[3]);
     const double im = 0.5 * (T[2] - T[3]) - 2.0 * T[1];
-    const double wm = __longlong_as_double((long long)wmin_bits[4 * b]);
+    const double wm = min_weight(wmin_bits, b, spw);
     const bool empty = nn < 0.5 * wm * wm * wm;
     B[2 * ((long long)b * ntrip_out + to)] = empty ? __builtin_nan("") : re / (norm * nn);
     B[2 * ((long long)b * ntrip_out + to) + 1] = empty ? __builtin_nan("") : im / (norm * nn);
@@ -201,10 +209,13 @@ std::vector<RunLevel> run_levels(const abs_plan_s* p, const WorkLayout& wl, char
 // own rings from it at its own size and contracts its own triplets.  Stages run one after
 // the other over all levels, so that the timing hooks bracket whole stages.
 // batch: data sets (spg per grid: 1, or 4 for complex input).
-abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batch, int dtype,
-                                   const void* grids, const float* w, int w_batched, char* work,
-                                   hipStream_t st, const WeightMod* mod, int spg = 1) {
+abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int dtype, const void* grids,
+                                   const float* w, int w_batched, char* work, hipStream_t st,
+                                   const WeightMod* mod, int spg = 1) {
   const std::vector<RunLevel> lv = run_levels(p, wl, work);
+  // data sets (spg per grid and channel), and the sets the contraction sees: a
+  // multi-frequency grid's nchan channel sets are one set of nbc channel rings
+  const int batch = wl.ndsets, C = p->nchan;
   unsigned long long* wmin = reinterpret_cast<unsigned long long*>(work + wl.wmin);
   void* xc = work + wl.xc;
   {
@@ -242,13 +253,13 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
       double* part = reinterpret_cast<double*>(r.base + r.wl->part);
       abs_status s;
       if (p->precision == ABS_FP32) {
-        s = launch_contract(q, 0, q->waves, F, r.wl->fset, (long long)q->n * q->n, q->pix_per_block, q->nblk,
-                            (int)q->ntrip, batch, part, st);
+        s = launch_contract(q, 0, q->waves, F, C * r.wl->fset, (long long)q->n * q->n, q->pix_per_block,
+                            q->nblk, (int)q->ntrip, wl.npsets, part, st);
       } else {
         const unsigned* fmax =
             p->precision == ABS_FP16X3 ? reinterpret_cast<const unsigned*>(r.base + r.wl->fmax) : nullptr;
-        s = launch_mfma_contract(q, F, r.wl->fset, batch, part, fmax, st) == hipSuccess ? ABS_OK
-                                                                                       : ABS_ERR_DEVICE;
+        s = launch_mfma_contract(q, F, C * r.wl->fset, wl.npsets, part, fmax, st) == hipSuccess ? ABS_OK
+                                                                                               : ABS_ERR_DEVICE;
       }
       if (s != ABS_OK) return s;
     }
@@ -267,8 +278,8 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int batc
         return ABS_ERR_DEVICE;
     for (const RunLevel& r : lv) {
       const abs_plan_s* q = r.q;
-      const abs_status s = launch_contract(q, 1, q->waves64, r.base + r.wl->fi, r.wl->fset64, q->npix64,
-                                           q->pix_per_block64, q->nblk64, (int)q->ntrip, wl.nisets,
+      const abs_status s = launch_contract(q, 1, q->waves64, r.base + r.wl->fi, C * r.wl->fset64, q->npix64,
+                                           q->pix_per_block64, q->nblk64, (int)q->ntrip, wl.nipsets,
                                            reinterpret_cast<double*>(r.base + r.wl->part64), st);
       if (s != ABS_OK) return s;
     }
@@ -398,7 +409,7 @@ abs_status estimate_on(abs_plan_t p, const WorkLayout& wl, int32_t batch, int32_
                        const float* w, int32_t w_batched, const double* n_given, char* wk, double* B,
                        double* N, hipStream_t st) {
   (void)hipGetLastError();
-  abs_status s = run_fields_and_contract(p, wl, batch, dtype, grids, w, w_batched, wk, st, nullptr);
+  abs_status s = run_fields_and_contract(p, wl, dtype, grids, w, w_batched, wk, st, nullptr);
   if (s != ABS_OK) return s;
   const unsigned long long* wmin = reinterpret_cast<const unsigned long long*>(wk + wl.wmin);
   for (const RunLevel& r : run_levels(p, wl, wk)) {
@@ -408,8 +419,8 @@ abs_status estimate_on(abs_plan_t p, const WorkLayout& wl, int32_t batch, int32_
     finalize_kernel<<<g, kFinBlock, 0, st>>>(reinterpret_cast<const double*>(r.base + r.wl->part), r.wl->partset,
                                           q->nblk, dev_pos32(q), reinterpret_cast<const double*>(r.base + r.wl->part64),
                                           r.wl->partset64, q->nblk64, dev_pos64(q), (int)q->ntrip, batch,
-                                          wl.nisets, n_given, wmin, inv, p->norm, dev_tmap(q), (int)p->ntrip,
-                                          B, N);
+                                          wl.nipsets, n_given, wmin, p->nchan, inv, p->norm, dev_tmap(q),
+                                          (int)p->ntrip, B, N);
   }
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }
@@ -466,13 +477,14 @@ abs_status abs_estimate_complex(abs_plan_t p, int32_t batch, int32_t dtype, cons
                                 double* B, double* N, void* stream) {
   abs_status s = check_estimate_args(p, batch, dtype, grids, w, w_batched, n_given, B);
   if (s != ABS_OK) return s;
+  if (p->nchan > 1) return ABS_ERR_INVALID;   // single-frequency plans only
   if (!work || (reinterpret_cast<uintptr_t>(work) & 15)) return ABS_ERR_INVALID;
   const WorkLayout wl = work_layout(p, batch, w_batched, n_given != nullptr, 4);
   if (work_bytes < wl.total) return ABS_ERR_NOMEM;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* wk = static_cast<char*>(work);
   (void)hipGetLastError();
-  s = run_fields_and_contract(p, wl, 4 * batch, dtype, grids, w, w_batched, wk, st, nullptr, 4);
+  s = run_fields_and_contract(p, wl, dtype, grids, w, w_batched, wk, st, nullptr, 4);
   if (s != ABS_OK) return s;
   const unsigned long long* wmin = reinterpret_cast<const unsigned long long*>(wk + wl.wmin);
   for (const RunLevel& r : run_levels(p, wl, wk)) {
@@ -481,7 +493,7 @@ abs_status abs_estimate_complex(abs_plan_t p, int32_t batch, int32_t dtype, cons
     finalize_complex_kernel<<<g, kFinBlock, 0, st>>>(
         reinterpret_cast<const double*>(r.base + r.wl->part), r.wl->partset, q->nblk, dev_pos32(q),
         reinterpret_cast<const double*>(r.base + r.wl->part64), r.wl->partset64, q->nblk64, dev_pos64(q),
-        (int)q->ntrip, wl.nisets, n_given, wmin, 1.0 / ((double)q->n * (double)q->n), p->norm, dev_tmap(q),
+        (int)q->ntrip, wl.nipsets, n_given, wmin, 4, 1.0 / ((double)q->n * (double)q->n), p->norm, dev_tmap(q),
         (int)p->ntrip, B, N);
   }
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
@@ -512,7 +524,7 @@ abs_status counts_into(abs_plan_s* p, const float* w, char* wk, const WeightMod*
   const WorkLayout wl = work_layout(p, 0, 0, 0);
   (void)hipGetLastError();
   // batch 0: the single set is the weight set
-  abs_status s = run_fields_and_contract(p, wl, 0, ABS_C64, nullptr, w, 0, wk, st, mod);
+  abs_status s = run_fields_and_contract(p, wl, ABS_C64, nullptr, w, 0, wk, st, mod);
   if (s != ABS_OK) return s;
   for (const RunLevel& r : run_levels(p, wl, wk)) {
     const abs_plan_s* q = r.q;

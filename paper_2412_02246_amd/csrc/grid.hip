@@ -483,7 +483,7 @@ GridWork grid_layout(long long n, long long nvis, int batch) {
 using namespace abs_impl;
 
 extern "C" abs_status abs_grid_workspace(abs_plan_t p, int64_t nvis, int32_t batch, size_t* bytes) {
-  if (!p || !bytes || nvis < 0 || batch < 1 || batch > p->max_batch) return ABS_ERR_INVALID;
+  if (!p || !bytes || nvis < 0 || batch < 1 || batch > p->max_batch * p->nchan) return ABS_ERR_INVALID;
   if (nvis > 0x7fffffffLL) return ABS_ERR_INVALID;   // list entries are 32-bit indices
   *bytes = grid_layout(p->n, nvis, batch).total;
   return ABS_OK;
@@ -495,7 +495,7 @@ extern "C" abs_status abs_grid(abs_plan_t p, int64_t nvis, int32_t batch, const 
                                void* stream) {
   if (!p) return ABS_ERR_INVALID;
   if (!p->dev) return ABS_ERR_UNBOUND;
-  if (nvis < 0 || nvis > 0x7fffffffLL || batch < 1 || batch > p->max_batch) return ABS_ERR_INVALID;
+  if (nvis < 0 || nvis > 0x7fffffffLL || batch < 1 || batch > p->max_batch * p->nchan) return ABS_ERR_INVALID;
   if (kernel != ABS_NEAREST && kernel != ABS_GAUSS7) return ABS_ERR_INVALID;
   if (!work || !grid || (nvis > 0 && (!uv || !vis))) return ABS_ERR_INVALID;
   if ((reinterpret_cast<uintptr_t>(uv) | reinterpret_cast<uintptr_t>(vis) |

@@ -326,14 +326,14 @@ hipError_t launch_mfma_contract(const abs_plan_s* p, const float* F, long long f
   const int* mt_bins = reinterpret_cast<const int*>(base + p->dl.mt_bins);
   const int* mt_trip = reinterpret_cast<const int*>(base + p->dl.mt_trip);
   const int2* wave_tiles = reinterpret_cast<const int2*>(base + p->dl.wave_tiles);
-  const size_t lds = mfma_lds_bytes(p->nb);
+  const size_t lds = mfma_lds_bytes(p->nbc);   // every contraction bin of a set is staged
   const dim3 grid((unsigned)p->nblk, (unsigned)nsets, (unsigned)p->mfma_groups);
   const long long npix = (long long)p->n * p->n;
   // the variant the plan chose (mfma_tpw, mfma_depth): small plans two tiles a wave; up
   // to 32 rings four chunks in flight; larger plans one
   const bool f16 = p->precision == ABS_FP16X3;
   const bool small = p->mfma_tpw == kSmallTilesPerWave, deep = p->mfma_depth == 4;
-  if (!small && p->nb > 32 && deep) return hipErrorInvalidValue;
+  if (!small && p->nbc > 32 && deep) return hipErrorInvalidValue;
   auto k = f16 ? (small  ? mfma_contract_kernel<true, 32, 1, kSmallTilesPerWave>
                   : deep ? mfma_contract_kernel<true, 32, 4, kTilesPerWave>
                          : mfma_contract_kernel<true, kMaxBins, 1, kTilesPerWave>)
@@ -345,7 +345,7 @@ hipError_t launch_mfma_contract(const abs_plan_s* p, const float* F, long long f
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  k<<<grid, kMfmaThreads, lds, st>>>(F, fset, npix, p->pix_per_block, part, p->nblk, (int)p->ntrip, p->nb,
+  k<<<grid, kMfmaThreads, lds, st>>>(F, fset, npix, p->pix_per_block, part, p->nblk, (int)p->ntrip, p->nbc,
                                      pt_pairs, mt_ptile, mt_bins, mt_trip, wave_tiles,
                                      f16 ? fmax_bits : nullptr);
   return hipGetLastError();

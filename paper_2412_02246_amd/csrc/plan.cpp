@@ -149,10 +149,12 @@ WorkLayout work_layout(const abs_plan_s* p, int grids, int w_batched, int have_c
   if (!p->lv.empty()) {
     // the parent's Hermitian part and wmin slots, then each level's buffers
     WorkLayout w{};
-    w.nisets = have_counts ? 0 : ((w_batched && p->wmode != ABS_W_UNIT) ? grids : 1);
-    const int batch = grids * spg;
+    w.nisets = have_counts ? 0 : ((w_batched && p->wmode != ABS_W_UNIT) ? grids : 1) * p->nchan;
+    const int batch = grids * spg * p->nchan;
     w.ndsets = batch;
     w.nsets = batch + w.nisets;
+    w.npsets = batch / p->nchan;
+    w.nipsets = w.nisets / p->nchan;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     size_t off = 0;
     w.wmin = off;
@@ -170,10 +172,13 @@ WorkLayout work_layout(const abs_plan_s* p, int grids, int w_batched, int have_c
   WorkLayout w{};
   // spg data sets per grid (4 for complex input: see abs_estimate_complex), one weight set
   // per grid with batched weights, else one (none with cached counts)
-  w.nisets = have_counts ? 0 : ((w_batched && p->wmode != ABS_W_UNIT) ? grids : 1);
-  const int batch = grids * spg;
+  // multi-frequency: nchan data sets a grid and one weight set per channel
+  w.nisets = have_counts ? 0 : ((w_batched && p->wmode != ABS_W_UNIT) ? grids : 1) * p->nchan;
+  const int batch = grids * spg * p->nchan;
   w.ndsets = batch;
   w.nsets = batch + w.nisets;
+  w.npsets = batch / p->nchan;
+  w.nipsets = w.nisets / p->nchan;
   const int64_t n = p->n;
   w.zset = n * p->ncols;
   w.fset = (int64_t)p->nb * n * n;
@@ -191,9 +196,9 @@ WorkLayout work_layout(const abs_plan_s* p, int grids, int w_batched, int have_c
   w.fi = off;
   off = al(off + (size_t)w.nisets * w.fset64 * 8);
   w.part = off;
-  off = al(off + (size_t)batch * w.partset * 8);
+  off = al(off + (size_t)w.npsets * w.partset * 8);
   w.part64 = off;
-  off = al(off + (size_t)w.nisets * w.partset64 * 8);
+  off = al(off + (size_t)w.nipsets * w.partset64 * 8);
   w.fmax = off;
   off = al(off + (size_t)batch * p->nb * 4);
   // smallest non-zero ring-cell weight per data set, then per weight set (FP64 bits)
@@ -674,7 +679,7 @@ void order_rows(std::vector<std::pair<int, int>>& rows) {
 // MFMA tile, and all column tiles of a row tile share it (the kernel forms its operand once
 // and keeps it while the wave's consecutive tiles use the same rows).
 void build_mfma_tables(abs_plan_s* p) {
-  const int nb = p->nb;
+  const int nb = p->nbc;   // contraction bins: the rings, or the channel rings of a multi-frequency plan
   std::vector<std::vector<int>> cset(nb * nb);
   std::vector<int> tindex(nb * nb * nb, -1);     // [(j * nb + k) * nb + i]
   for (int64_t t = 0; t < p->ntrip; ++t) {
@@ -814,6 +819,7 @@ std::vector<RingRows> setup_rings(abs_plan_s* p) {
   p->ncols = acc;
   p->hmax = 0;
   for (int m = 0; m < nb; ++m) p->hmax = std::max(p->hmax, p->h[m]);
+  p->nbc = p->nchan * nb;
   return rows;
 }
 
@@ -909,8 +915,8 @@ void choose_levels(const abs_plan_s* p, std::vector<int>& sizes, std::vector<int
   std::vector<int> need(T);
   for (int t = 0; t < T; ++t) {
     const int* x = &p->trips[3 * t];
-    const int hs = p->h[x[0]] + p->h[x[1]] + p->h[x[2]];
-    const int hm = std::max(p->h[x[0]], std::max(p->h[x[1]], p->h[x[2]]));
+    const int h0 = p->h[x[0] % p->nb], h1 = p->h[x[1] % p->nb], h2 = p->h[x[2] % p->nb];
+    const int hs = h0 + h1 + h2, hm = std::max(h0, std::max(h1, h2));
     int m = 16;
     while ((hs >= m || 2 * hm >= m) && m <= n) m *= 2;
     need[t] = m;
@@ -941,8 +947,10 @@ void choose_levels(const abs_plan_s* p, std::vector<int>& sizes, std::vector<int
         if (lof[t] != L) continue;
         const int* x = &p->trips[3 * t];
         ++cnt;
-        K0 = std::min(K0, x[0]);
-        K1 = std::max(K1, x[2] + 1);
+        for (int q = 0; q < 3; ++q) {
+          K0 = std::min(K0, x[q] % p->nb);
+          K1 = std::max(K1, x[q] % p->nb + 1);
+        }
         ij.insert({x[0], x[1]});
         jk.insert({x[1], x[2]});
       }
@@ -950,7 +958,7 @@ void choose_levels(const abs_plan_s* p, std::vector<int>& sizes, std::vector<int
       remap[L] = (int)keep.size();
       keep.push_back(lv[L]);
       const double m2 = (double)lv[L] * lv[L];
-      cost += sets * m2 * (kFftCost * (K1 - K0) + (double)std::min(ij.size(), jk.size()) + 2.0 * cnt) +
+      cost += sets * m2 * (kFftCost * p->nchan * (K1 - K0) + (double)std::min(ij.size(), jk.size()) + 2.0 * cnt) +
               kLevelCost;
     }
     if (best < 0.0 || cost < best) {
@@ -971,12 +979,14 @@ abs_plan_s* make_level(const abs_plan_s* p, int m, const std::vector<int32_t>& t
   if (!q) return nullptr;
   q->is_level = true;
   int K0 = p->nb, K1 = 0;
-  for (int32_t t : tidx) {
-    K0 = std::min(K0, p->trips[3 * t]);
-    K1 = std::max(K1, p->trips[3 * t + 2] + 1);
-  }
+  for (int32_t t : tidx)
+    for (int c = 0; c < 3; ++c) {
+      K0 = std::min(K0, p->trips[3 * t + c] % p->nb);
+      K1 = std::max(K1, p->trips[3 * t + c] % p->nb + 1);
+    }
   q->n = m;
   q->nb = K1 - K0;
+  q->nchan = p->nchan;
   q->ring0 = K0;
   q->log2n = ilog2(m);
   q->du = p->du;
@@ -992,8 +1002,12 @@ abs_plan_s* make_level(const abs_plan_s* p, int m, const std::vector<int32_t>& t
   setup_rings(q);
   q->xc_hm = p->hmax;
   q->tmap = tidx;
+  // channel ring s = c nb + r of the parent is c nb' + (r - K0) here (the order is kept)
   for (int32_t t : tidx)
-    for (int c = 0; c < 3; ++c) q->trips.push_back(p->trips[3 * t + c] - K0);
+    for (int c = 0; c < 3; ++c) {
+      const int sidx = p->trips[3 * t + c];
+      q->trips.push_back((sidx / p->nb) * q->nb + (sidx % p->nb - K0));
+    }
   q->ntrip = (int64_t)tidx.size();
   q->npairs = count_pairs(q->trips);
   if (!setup_kernels(q)) {
@@ -1064,6 +1078,8 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
   if (d->precision < ABS_FP32 || d->precision > ABS_FP16X3) return ABS_ERR_INVALID;
   if (!(d->du > 0.0) || !std::isfinite(d->du)) return ABS_ERR_INVALID;
   if (d->levels < 0 || d->levels > n || (d->levels & (d->levels - 1))) return ABS_ERR_INVALID;
+  const int nchan = d->nchan < 1 ? 1 : d->nchan;
+  if (nchan * nb > kMaxBins) return ABS_ERR_INVALID;
   for (int m = 0; m <= nb; ++m)
     if (!std::isfinite(d->edges[m]) || d->edges[m] < 0.0) return ABS_ERR_INVALID;
   for (int m = 0; m < nb; ++m)
@@ -1084,6 +1100,7 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
   p->wmode = d->wmode;
   p->max_batch = d->max_batch;
   p->flags = d->flags;
+  p->nchan = nchan;
   p->max_ratio = d->levels != 0 ? d->levels
                  : d->precision == ABS_BF16X3 ? kDefaultLevelRatioBf16 : kDefaultLevelRatio;
   p->edges.assign(d->edges, d->edges + nb + 1);
@@ -1116,6 +1133,26 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
         p->trips.push_back(j);
         p->trips.push_back(k);
       }
+  // Multi-frequency plans: every non-decreasing triple of channel rings s = c nb + r whose
+  // rings, sorted, form a plan triplet (the estimator of Eq. 12 with the three fields taken
+  // at three channels, each unordered combination of (ring, channel) pairs once).
+  if (p->nchan > 1) {
+    std::set<std::tuple<int, int, int>> ok;
+    for (size_t t = 0; t + 2 < p->trips.size(); t += 3) ok.insert({p->trips[t], p->trips[t + 1], p->trips[t + 2]});
+    std::vector<int32_t> st;
+    const int B = p->nbc;
+    for (int s1 = 0; s1 < B; ++s1)
+      for (int s2 = s1; s2 < B; ++s2)
+        for (int s3 = s2; s3 < B; ++s3) {
+          int r[3] = {s1 % nb, s2 % nb, s3 % nb};
+          std::sort(r, r + 3);
+          if (!ok.count({r[0], r[1], r[2]})) continue;
+          st.push_back(s1);
+          st.push_back(s2);
+          st.push_back(s3);
+        }
+    p->trips.swap(st);
+  }
   p->ntrip = (int64_t)p->trips.size() / 3;
   if (p->ntrip == 0) {
     delete p;
@@ -1124,9 +1161,11 @@ abs_status abs_plan(const abs_plan_desc* d, abs_plan_t* out) {
   p->npairs = count_pairs(p->trips);
   p->labels.resize(5 * p->ntrip);
   for (int64_t t = 0; t < p->ntrip; ++t) {
-    const double l3 = 2 * kPi * p->du * p->radius[p->trips[3 * t]];
-    const double l2 = 2 * kPi * p->du * p->radius[p->trips[3 * t + 1]];
-    const double l1 = 2 * kPi * p->du * p->radius[p->trips[3 * t + 2]];
+    int r[3] = {p->trips[3 * t] % nb, p->trips[3 * t + 1] % nb, p->trips[3 * t + 2] % nb};
+    std::sort(r, r + 3);
+    const double l3 = 2 * kPi * p->du * p->radius[r[0]];
+    const double l2 = 2 * kPi * p->du * p->radius[r[1]];
+    const double l1 = 2 * kPi * p->du * p->radius[r[2]];
     double* L = &p->labels[5 * t];
     L[0] = l1;
     L[1] = l2;
@@ -1186,6 +1225,7 @@ void fill_info(const abs_plan_s* p, abs_plan_info* o) {
   o->mfma_depth = p->mfma_depth;
   o->nlevels = 1;
   o->ring0 = p->ring0;
+  o->nchan = p->nchan;
 }
 }  // namespace
 

@@ -29,28 +29,31 @@ class Plan:
     flags       ALLOW_WRAP | ALLOW_DC
     levels      largest n / m of a resolution level (1: evaluate every triplet at n;
                 0: the library's default)
+    nchan       channels of a multi-frequency plan (1: one channel); its triplets run over
+                channel rings s = c * nbins + r and each grid of a call is nchan channel
+                grids
     """
 
     def __init__(self, n, edges, du=1.0, norm=0.0, theta0=0.0, precision=L.FP32,
-                 wmode=L.W_UNIT, max_batch=1, flags=0, levels=0):
+                 wmode=L.W_UNIT, max_batch=1, flags=0, levels=0, nchan=1):
         lib = L.lib()
         e = np.ascontiguousarray(edges, dtype=np.float64)
         self._edges = e
         self._spec = (int(n), tuple(float(x) for x in e),
                       dict(du=float(du), norm=float(norm), theta0=float(theta0),
                            precision=int(precision), wmode=int(wmode), max_batch=int(max_batch),
-                           flags=int(flags), levels=int(levels)))
+                           flags=int(flags), levels=int(levels), nchan=int(nchan)))
         d = L.PlanDesc(n=int(n), nbins=len(e) - 1,
                        edges=e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                        du=float(du), norm=float(norm), theta0=float(theta0),
                        precision=int(precision), wmode=int(wmode), max_batch=int(max_batch),
-                       flags=int(flags), levels=int(levels))
+                       flags=int(flags), levels=int(levels), nchan=int(nchan))
         h = ctypes.c_void_p()
         L.check(lib.abs_plan(ctypes.byref(d), ctypes.byref(h)), "abs_plan")
         self.handle = h
         info = L.PlanInfo()
         L.check(lib.abs_plan_info_get(h, ctypes.byref(info)), "abs_plan_info_get")
-        self.n, self.nbins = info.n, info.nbins
+        self.n, self.nbins, self.nchan = info.n, info.nbins, info.nchan
         self.ntrip, self.npairs, self.ncols = info.ntrip, info.npairs, info.ncols
         self.plan_bytes, self.norm = info.plan_bytes, info.norm
         self.mfma_tiles = info.mfma_tiles
@@ -164,8 +167,9 @@ class Plan:
     def estimate(self, grids, w=None, w_batched=False, n_given=None, out=None, stream=None, work=None):
         """B (and N) for a batch of gridded visibilities.
 
-        grids: torch complex64 / complex128 [batch][n][n] (or [n][n]) on the plan's device
-        w:     torch float32 [n][n] or [batch][n][n] (w_batched), per the plan's wmode
+        grids: torch complex64 / complex128 [batch][n][n] (or [n][n]) on the plan's device;
+               [batch * nchan][n][n] for a multi-frequency plan (channels consecutive)
+        w:     torch float32 [n][n] or [batch * nchan][n][n] (w_batched), per the plan's wmode
         n_given: torch float64 [ntrip] counts from counts() for the same shared weights
         Returns (B, N), torch float64 [batch][ntrip].
         """
@@ -180,13 +184,13 @@ class Plan:
             raise TypeError("grids must be complex64 or complex128")
         if not grids.is_contiguous():
             raise ValueError("grids must be contiguous")
-        batch = grids.shape[0]
-        if tuple(grids.shape[1:]) != (self.n, self.n):
-            raise ValueError("grids must be [batch][%d][%d]" % (self.n, self.n))
+        if tuple(grids.shape[1:]) != (self.n, self.n) or grids.shape[0] % self.nchan:
+            raise ValueError("grids must be [batch * %d][%d][%d]" % (self.nchan, self.n, self.n))
+        batch = grids.shape[0] // self.nchan   # multi-frequency: nchan channel grids a grid
         if w is not None:
             if w.dtype != torch.float32 or not w.is_contiguous():
                 raise TypeError("w must be a contiguous float32 tensor")
-            want = (batch, self.n, self.n) if w_batched else (self.n, self.n)
+            want = (batch * self.nchan, self.n, self.n) if w_batched else (self.n, self.n)
             if tuple(w.shape) != want:
                 raise ValueError("w must have shape %s" % (want,))
         if n_given is not None and (n_given.dtype != torch.float64 or n_given.numel() != self.ntrip):

@@ -91,3 +91,13 @@ def test_zero_mean_gaussian():
     z = B.mean(0) / (B.std(0, ddof=1) / np.sqrt(R))
     assert np.median(np.abs(z)) <= 1.0
     assert np.abs(z).max() <= 4.5
+
+
+def test_validation_spectrum_values():
+    """Sec. 3's C_l = (l / l0)^-1 exp(-l^2 / (pi l0)^2) with l0 = 1000: C(l0) = exp(-1 / pi^2),
+    C(2 l0) = exp(-4 / pi^2) / 2, and the ratio of two small-l values is the power law's
+    times the Gaussian's."""
+    assert np.isclose(theory.cl_model(1000.0), np.exp(-1.0 / np.pi ** 2), rtol=1e-14)
+    assert np.isclose(theory.cl_model(2000.0), 0.5 * np.exp(-4.0 / np.pi ** 2), rtol=1e-14)
+    r = theory.cl_model(10.0) / theory.cl_model(20.0)
+    assert np.isclose(r, 2.0 * np.exp((400.0 - 100.0) / (np.pi * 1000.0) ** 2), rtol=1e-14)
