@@ -8,7 +8,7 @@ counts N_t from its own gridded counts.  Inputs are resident in HBM before timin
 
 The default line is the large-ensemble shapes (8192^2 grids, 64 log rings, 15,229
 triplets, realisations in batches of 8) in the plain FP32 form; it also carries, as
-extra keys, the same workload in the BF16x3 precision form, the 1024^2 / 20-ring
+extra keys, the same workload in the BF16x3 and FP16x3 precision forms, the 1024^2 / 20-ring
 single-channel workload, and the serving form's saturated rate and latencies.
 
 Prints one JSON line: grids/s, bin-triplets/s, the roofline of the dominant kernel
@@ -469,9 +469,13 @@ def measure(name, precision, plan, uv_d, vis_d, steps, warmup, log=sys.stderr):
                 "peak_nonpacked_valu": PEAK_VALU_NONPACKED / 1e12,
                 "frac_nonpacked_valu": achieved / PEAK_VALU_NONPACKED}
     else:
-        # 3 split MFMAs per 16 x 16 tile and pixel, each level's tiles over its m^2 pixels
-        issued = float(nsets) * sum(lv["mfma_tiles"] * lv["m"] ** 2 for lv in plan.levels) * 3 * 512
-        roof = {"kernel": "mfma_contract_kernel (%s triplet contraction)" % precision, "bound": "mfma",
+        # 3 split MFMAs per 16 x 16 tile and pixel, each level's tiles over its m^2 pixels,
+        # for the levels the plan runs on the matrix units (the others take the FP32 kernel,
+        # which has code parts of its own)
+        mf = [lv for lv in plan.levels if lv["contract"][0] == 0]
+        issued = float(nsets) * sum(lv["mfma_tiles"] * lv["m"] ** 2 for lv in mf) * 3 * 512
+        roof = {"kernel": "mfma_contract_kernel (%s triplet contraction; levels %s on the matrix units, the rest "
+                          "in the FP32 kernel)" % (precision, [lv["m"] for lv in mf]), "bound": "mfma",
                 "achieved": achieved / 1e12, "peak": PEAK_MFMA_16BIT / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_MFMA_16BIT, "traffic": traffic, "avg_ms": con_ms,
                 "flops_per_launch": flops, "flops_per_launch_at_n": flops_n,
@@ -548,7 +552,7 @@ def main():
     # touches the GPU
     jobs = [(name, a.precision, batch)]
     if extras:
-        jobs += [(name, "bf16x3", batch), ("mwa1024", "fp32", WORKLOADS["mwa1024"]["batch"])]
+        jobs += [(name, "bf16x3", batch), (name, "fp16x3", batch), ("mwa1024", "fp32", WORKLOADS["mwa1024"]["batch"])]
     t0 = time.perf_counter()
     plans, specs = [], []
     for wname, prec, b in jobs:
@@ -591,13 +595,14 @@ def main():
         "stages_hbm": res["stages_hbm"],
     }
     if extras:
-        p16 = plans[1].bind()
-        r16 = measure(name, "bf16x3", p16, uv_d, vis_d, a.steps, a.warmup)
-        p16.close()
-        p16._work = None
-        torch.cuda.empty_cache()
-        r16["speedup_vs_fp32"] = r16["grids_per_s"] / res["grids_per_s"]
-        out["precision_form_bf16x3"] = r16
+        for k, prec in ((1, "bf16x3"), (2, "fp16x3")):
+            pk = plans[k].bind()
+            rk = measure(name, prec, pk, uv_d, vis_d, a.steps, a.warmup)
+            pk.close()
+            pk._work = None
+            torch.cuda.empty_cache()
+            rk["speedup_vs_fp32"] = rk["grids_per_s"] / res["grids_per_s"]
+            out["precision_form_" + prec] = rk
     uv_h = vis_h = None
     if not a.no_cpu:
         uv_h = uv_d.cpu().numpy()
@@ -606,7 +611,7 @@ def main():
     torch.cuda.empty_cache()
     if extras:
         uv1, vis1 = inputs("mwa1024", WORKLOADS["mwa1024"]["batch"])
-        p1 = plans[2].bind()
+        p1 = plans[3].bind()
         r1 = measure("mwa1024", "fp32", p1, uv1, vis1, a.steps, a.warmup)
         r1["workload"] = WORKLOADS["mwa1024"]["desc"]
         p1.close()
@@ -614,7 +619,7 @@ def main():
         torch.cuda.empty_cache()
         out["mwa1024_fp32"] = r1
         # the serving form in a process of its own (as a server would run), one per precision
-        out["serving"] = {prec: serve_child(prec, a.requests, a.budget_gib) for prec in ("fp32", "bf16x3")}
+        out["serving"] = {prec: serve_child(prec, a.requests, a.budget_gib) for prec in ("fp32", "bf16x3", "fp16x3")}
     if not a.no_cpu:
         from oracle import plan as oplan   # noqa: F401  (oracle import only for the baseline)
         trips = A.Plan(n, edges).triplets

@@ -58,7 +58,9 @@ typedef enum abs_status {
   ABS_ERR_SCRATCH = 8   /* abs_estimate_noalloc: the call needs more than its static scratch */
 } abs_status;
 
-/* precision of the triplet contraction (the ring FFTs are always FP32) */
+/* precision of the triplet contraction (the ring FFTs are always FP32); the split forms run
+ * on the matrix units wherever the plan's cost model expects that to be faster than the
+ * FP32 kernel (see ABS_ALL_MFMA) */
 enum { ABS_FP32 = 0, ABS_BF16X3 = 1, ABS_FP16X3 = 2 };
 /* weight modes (Sec. 2, the paragraph after Eq. 10) */
 enum { ABS_W_UNIT = 0,      /* W = 1 on every ring cell                                */
@@ -73,6 +75,10 @@ enum { ABS_NEAREST = 0, ABS_GAUSS7 = 1 };
 #define ABS_ALLOW_DC 2u   /* accept edges[0] == 0, i.e. a ring holding g = 0 (tests) */
 #define ABS_EVERY_LEVEL 4u /* run every resolution level n/2 .. n/levels that holds a    */
                            /* triplet, instead of the set the cost model picks (tests) */
+#define ABS_ALL_MFMA 8u    /* precision forms: contract every level on the matrix units; */
+                           /* without it a level whose triplets fill few 16 x 16 tiles  */
+                           /* is contracted by the FP32 kernel (faster there, and more  */
+                           /* accurate)                                                 */
 
 typedef struct abs_plan_s* abs_plan_t;
 
@@ -89,7 +95,7 @@ typedef struct abs_plan_desc {
   int32_t precision;    /* ABS_FP32, ABS_BF16X3 or ABS_FP16X3                          */
   int32_t wmode;        /* ABS_W_UNIT, ABS_W_INV_COUNT or ABS_W_GIVEN                  */
   int32_t max_batch;    /* largest batch abs_estimate / abs_grid will be given (>= 1) */
-  uint32_t flags;       /* ABS_ALLOW_WRAP | ABS_ALLOW_DC | ABS_EVERY_LEVEL             */
+  uint32_t flags;       /* ABS_ALLOW_WRAP | ABS_ALLOW_DC | ABS_EVERY_LEVEL | ABS_ALL_MFMA */
   int32_t levels;       /* largest n / m of a resolution level: a power of two; 1 runs */
                         /* every triplet at n; 0 selects 4 (2 for ABS_BF16X3).  A     */
                         /* triplet i <= j <= k with h_i + h_j + h_k < m and 2 h_k < m  */

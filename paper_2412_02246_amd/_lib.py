@@ -13,7 +13,7 @@ W_UNIT, W_INV_COUNT, W_GIVEN = 0, 1, 2
 C64, C128 = 0, 1
 NEAREST, GAUSS7 = 0, 1
 STAGE_CONTRACT, STAGE_COLPASS, STAGE_ROWPASS, STAGE_GRID = 0, 1, 2, 3
-ALLOW_WRAP, ALLOW_DC, EVERY_LEVEL = 1, 2, 4
+ALLOW_WRAP, ALLOW_DC, EVERY_LEVEL, ALL_MFMA = 1, 2, 4, 8
 BEAM_NONE, BEAM_MWA, BEAM_GAUSS = 0, 1, 2
 
 

@@ -112,6 +112,10 @@ struct abs_plan_s {
   int mfma_groups = 0;           // workgroups (of 8 waves) per pixel block and set
   int mfma_tpw = 0;              // tiles per wave of the kernel variant the plan uses
   int mfma_depth = 1;            // chunks of loads in flight in that variant
+  // precision forms: whether this plan's data contraction runs on the matrix units; a plan
+  // (or level) whose triplets fill few tiles is cheaper in the FP32 VALU kernel, which is
+  // also more accurate, so it takes that one (see use_mfma_for)
+  bool use_mfma = false;
   // contraction kernel (compiled at run time for this triplet list)
   int ngroups = 0;               // wave groups of the FP32 kernel; one wave per group
   int ngroups64 = 0;             // wave groups of the FP64 kernel (weight fields)

@@ -232,15 +232,17 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int dtyp
         return ABS_ERR_DEVICE;
     prof_end(p, ABS_STAGE_COLPASS, st);
     // FP16 splits need a power-of-two scale per (grid, ring): the row pass records max |F|
-    if (p->precision == ABS_FP16X3)
-      for (const RunLevel& r : lv) {
+    // for the levels contracted on the matrix units
+    auto fp16_level = [&](const abs_plan_s* q) { return p->precision == ABS_FP16X3 && q->use_mfma; };
+    for (const RunLevel& r : lv)
+      if (fp16_level(r.q)) {
         const int cnt = batch * r.q->nb;
         fill_u32_kernel<<<(cnt + kBlock - 1) / kBlock, kBlock, 0, st>>>(
             reinterpret_cast<unsigned*>(r.base + r.wl->fmax), cnt, 0u);
       }
     prof_begin(p, ABS_STAGE_ROWPASS, st);
     for (const RunLevel& r : lv) {
-      unsigned* fmax = p->precision == ABS_FP16X3 ? reinterpret_cast<unsigned*>(r.base + r.wl->fmax) : nullptr;
+      unsigned* fmax = fp16_level(r.q) ? reinterpret_cast<unsigned*>(r.base + r.wl->fmax) : nullptr;
       if (launch_rowpass_f32(r.q, batch, reinterpret_cast<const float2*>(r.base + r.wl->zd), r.wl->zset,
                              reinterpret_cast<float*>(r.base + r.wl->fd), r.wl->fset, fmax, st) != hipSuccess)
         return ABS_ERR_DEVICE;
@@ -252,7 +254,7 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int dtyp
       const float* F = reinterpret_cast<const float*>(r.base + r.wl->fd);
       double* part = reinterpret_cast<double*>(r.base + r.wl->part);
       abs_status s;
-      if (p->precision == ABS_FP32) {
+      if (!q->use_mfma) {
         s = launch_contract(q, 0, q->waves, F, C * r.wl->fset, (long long)q->n * q->n, q->pix_per_block,
                             q->nblk, (int)q->ntrip, wl.npsets, part, st);
       } else {
@@ -289,7 +291,7 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int dtyp
 
 // Device tables of a run plan: partial positions and, for a level plan, its triplet map.
 const int* dev_pos32(const abs_plan_s* q) {
-  return q->precision == ABS_FP32 ? reinterpret_cast<const int*>(static_cast<const char*>(q->dev) + q->dl.pos32)
+  return !q->use_mfma ? reinterpret_cast<const int*>(static_cast<const char*>(q->dev) + q->dl.pos32)
                                   : nullptr;   // the precision form writes partials by triplet index
 }
 const int* dev_pos64(const abs_plan_s* q) {

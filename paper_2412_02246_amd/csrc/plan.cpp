@@ -575,7 +575,7 @@ bool build_jit_source(abs_plan_s* p) {
     }
   };
   // the FP32 kernel serves the FP32 data path; the weight fields always use FP64
-  if (p->precision == ABS_FP32) add(0, o32.ord, g32, w32, o32.jk, "float");
+  if (!p->use_mfma) add(0, o32.ord, g32, w32, o32.jk, "float");
   add(1, o64.ord, g64, w64, o64.jk, "double");
   return true;
 }
@@ -829,6 +829,27 @@ int64_t count_pairs(const std::vector<int32_t>& trips) {
   return (int64_t)pairs.size();
 }
 
+// Precision forms: run the data contraction on the matrix units only where that is
+// estimated to be faster than the FP32 VALU kernel.  Per pixel and set, modelled on the
+// 8192^2, 4096^2 and 1024^2 workloads' level kernels (one MI355X): the VALU kernel about
+// 4 + 0.45 bins + 0.015 (pairs + 2 triplets) ps, the MFMA kernel about 8 + 0.64 bins +
+// 2.13 tiles ps (each 16 x 16 tile three split products per chunk, operands staged for
+// every bin).  With few triplets per tile (the top levels, small plans) the VALU kernel
+// wins.  ABS_ALL_MFMA keeps every contraction on the matrix units.
+bool use_mfma_for(const abs_plan_s* p) {
+  if (p->precision == ABS_FP32) return false;
+  if (p->flags & ABS_ALL_MFMA) return true;
+  std::set<std::pair<int, int>> ij, jk;
+  for (int64_t t = 0; t < p->ntrip; ++t) {
+    ij.insert({p->trips[3 * t], p->trips[3 * t + 1]});
+    jk.insert({p->trips[3 * t + 1], p->trips[3 * t + 2]});
+  }
+  const double flops = (double)std::min(ij.size(), jk.size()) + 2.0 * (double)p->ntrip;
+  const double t32 = 4.0 + 0.45 * p->nbc + 0.015 * flops;
+  const double t16 = 8.0 + 0.64 * p->nbc + 2.13 * (double)p->mt_ptile.size();
+  return t16 < t32;
+}
+
 // FFT tiling, contraction pixel blocks, the device layout of the tables, the precision
 // form's tables and the contraction code of a plan whose rings and triplets are set.
 bool setup_kernels(abs_plan_s* p) {
@@ -890,6 +911,7 @@ bool setup_kernels(abs_plan_s* p) {
   p->dl.tmap = off;
   off = al(off + p->tmap.size() * 4);
   p->dl.total = off;
+  p->use_mfma = use_mfma_for(p);
   return build_jit_source(p);
 }
 

@@ -35,7 +35,7 @@ def _run(name, prec):
     import paper_2412_02246_amd as A
     n, e = PLANS[name]
     P = {"fp32": A.FP32, "bf16x3": A.BF16X3, "fp16x3": A.FP16X3}[prec]
-    p = A.Plan(n, e, wmode=A.W_INV_COUNT, precision=P, levels=LEVELS)
+    p = A.Plan(n, e, wmode=A.W_INV_COUNT, precision=P, levels=LEVELS, flags=A.ALL_MFMA if prec != "fp32" else 0)
     want = VARIANTS[name]
     if prec == "fp32":
         assert p.variants["contract"] == want["contract"]

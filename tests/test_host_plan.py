@@ -148,7 +148,7 @@ def test_code_variants_selected_by_each_plan():
     seen = {"contract": set(), "weight": set(), "mfma": set()}
     for name, (n, e) in PLANS.items():
         p = A.Plan(n, e, levels=LEVELS)
-        q = A.Plan(n, e, precision=A.BF16X3, levels=LEVELS)
+        q = A.Plan(n, e, precision=A.BF16X3, levels=LEVELS, flags=A.ALL_MFMA)
         got = dict(contract=p.variants["contract"], weight=p.variants["weight"], mfma=q.variants["mfma"])
         assert got == VARIANTS[name], (name, got)
         assert q.variants["contract"][0] == 0           # the precision form has no FP32 kernel

@@ -5,7 +5,8 @@ tiles per wave and loads in flight.  All are small enough for the oracle to eval
 triplet.  VARIANTS pins what each plan selects: (parts, jk, block, waves) for the FP32 and
 FP64 kernels, (tiles per wave, depth) for the precision form.  The plans are built with
 LEVELS = 1 (every triplet at the plan's own n), so that each variant runs at the size
-pinned here; resolution levels have tests of their own."""
+pinned here, and the precision forms with ABS_ALL_MFMA (every contraction on the matrix
+units); resolution levels and the per-level choice of kernel have tests of their own."""
 import numpy as np
 
 from oracle import plan as oplan
