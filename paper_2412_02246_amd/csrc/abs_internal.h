@@ -12,11 +12,15 @@
 namespace abs_impl {
 
 constexpr int kBlock = 256;          // threads per workgroup for most kernels here
-// Threads per column-pass workgroup: 4096-point columns use 512 (two transforms a block,
-// so a tile's outputs leave in 64-byte runs instead of 32: 4.7 -> 2.6 ms at 4096^2 x 16;
-// 8192-point columns stay at kBlock, 7.5 against 10.1 ms with 512); others kBlock.  The
-// host's column tiles hold as many columns as one workgroup transforms at once.
-constexpr int col_block(int log2n) { return log2n == 12 ? 512 : kBlock; }
+// Threads per column-pass workgroup (f32: FP32 data fields, else FP64 weight fields) and
+// the FFT engine's block, from which the threads per transform follow (Fft<n, engine>):
+// 4096-point columns use 512-thread workgroups with two 256-thread transforms (a tile's
+// outputs leave in 64-byte runs instead of 32: 4.7 -> 2.6 ms at 4096^2 x 16), and so do
+// FP32 8192-point columns, two transforms of 256 threads (two butterflies each) in 141 KB of
+// LDS; FP64 8192-point columns (278 KB for two) keep one transform a workgroup; others
+// kBlock.  The host's column tiles hold as many columns as one workgroup transforms at once.
+constexpr int col_block(int log2n, bool f32) { return log2n == 12 || (log2n == 13 && f32) ? 512 : kBlock; }
+constexpr int col_engine(int log2n) { return log2n == 12 ? 512 : kBlock; }
 constexpr int kMaxBins = 64;
 constexpr int kTilesPerWave = 12;    // MFMA output tiles owned by one wave (precision form)
 constexpr int kSmallTilesPerWave = 2;   // the same for small plans (kernel variant)
@@ -38,7 +42,7 @@ struct BinDev {
 
 // Offsets (bytes) of the tables inside the caller's plan memory.
 struct DevLayout {
-  size_t tw, tw64, bins, tiles;
+  size_t tw, tw64, bins, tiles, tiles64;
   size_t pt_pairs, mt_ptile, mt_bins, mt_trip, wave_tiles;   // precision-form tables
   size_t pos32, pos64;   // position of each triplet in the FP32 / FP64 kernel's partials
   size_t tmap;           // level plans: index of each of their triplets in the parent's list
@@ -101,8 +105,8 @@ struct abs_plan_s {
   std::vector<double> labels;    // 5 * ntrip
   int64_t ntrip = 0, npairs = 0;
   // FFT tiling
-  int ct = 0;                    // columns per column-pass block
-  std::vector<abs_impl::ColTile> tiles;
+  int ct = 0, ct64 = 0;          // columns per column-pass block (FP32 data, FP64 weights)
+  std::vector<abs_impl::ColTile> tiles, tiles64;
   // precision form: 16-pair row tiles, 16 x 16 MFMA tiles and their owner waves
   std::vector<int> pt_pairs;     // 2 * 16 per row tile: (j, k), padding rows (nb, nb)
   std::vector<int> mt_ptile;     // row tile of each MFMA tile

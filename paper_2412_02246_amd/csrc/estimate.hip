@@ -341,6 +341,7 @@ abs_status bind_tables(abs_plan_s* p, void* mem, hipStream_t st) {
     bins[m].zoff = p->zoff[m];
   }
   std::memcpy(img.data() + p->dl.tiles, p->tiles.data(), p->tiles.size() * sizeof(ColTile));
+  std::memcpy(img.data() + p->dl.tiles64, p->tiles64.data(), p->tiles64.size() * sizeof(ColTile));
   auto put = [&](size_t off, const std::vector<int>& v) {
     std::memcpy(img.data() + off, v.data(), v.size() * sizeof(int));
   };

@@ -236,17 +236,22 @@ herm_kernel(const GT* __restrict__ grids, const float* __restrict__ w, int w_bat
 // Column-pass twiddles: held in registers when a thread needs few (FP32), otherwise the
 // two-level LDS table.
 template <typename R, int LOG2N>
-constexpr bool col_tw_reg() { return sizeof(R) == 4 && Fft<LOG2N, col_block(LOG2N)>::NTW <= 32; }
+constexpr bool col_tw_reg() { return sizeof(R) == 4 && Fft<LOG2N, col_engine(LOG2N)>::NTW <= 32; }
+
+// Transforms per column-pass workgroup (the columns of one tile).
+template <typename R, int LOG2N>
+constexpr int col_transforms() { return col_block(LOG2N, sizeof(R) == 4) / Fft<LOG2N, col_engine(LOG2N)>::TG; }
 
 template <typename R, int LOG2N>
-__global__ void __launch_bounds__(col_block(LOG2N))
+__global__ void __launch_bounds__(col_block(LOG2N, sizeof(R) == 4))
 colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, int hm, int lc,
                      const ColTile* __restrict__ tiles, int ntiles, int tpb,
                      const BinDev* __restrict__ bins, const typename Cx<R>::T* __restrict__ tw,
                      typename Cx<R>::T* __restrict__ Z, long long zset) {
   using T = typename Cx<R>::T;
-  constexpr int CB = col_block(LOG2N);
-  using FF = Fft<LOG2N, CB>;
+  constexpr int CB = col_block(LOG2N, sizeof(R) == 4), EB = col_engine(LOG2N);
+  using FF = Fft<LOG2N, EB>;
+  constexpr int CG = col_transforms<R, LOG2N>();   // transforms (columns) per workgroup
   constexpr int n = FF::N, S = n / 16;
   constexpr bool DATA = sizeof(R) == 4;
   constexpr bool REG = col_tw_reg<R, LOG2N>();
@@ -254,10 +259,10 @@ colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, i
   const int g = threadIdx.x / FF::TG, t = threadIdx.x - g * FF::TG;
   T* buf = reinterpret_cast<T*>(lds_raw) + g * FF::L;
   const int set = blockIdx.y;
-  using TW = std::conditional_t<REG, Twiddles<R, LOG2N, true, CB>, TwiddlesSplit<R, LOG2N, CB>>;
+  using TW = std::conditional_t<REG, Twiddles<R, LOG2N, true, EB>, TwiddlesSplit<R, LOG2N, EB>>;
   TW twr;
   if constexpr (REG) twr.load(tw, t);
-  else twr.stage(tw, reinterpret_cast<T*>(lds_raw) + FF::G * FF::L, threadIdx.x, CB);   // the loop's first barrier publishes it
+  else twr.stage(tw, reinterpret_cast<T*>(lds_raw) + CG * FF::L, threadIdx.x, CB);   // the loop's first barrier publishes it
   for (int it = 0; it < tpb; ++it) {
     const int ti = blockIdx.x * tpb + it;
     if (ti >= ntiles) break;   // the same for the whole block
@@ -282,7 +287,7 @@ colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, i
       }
       return x;
     };
-    // outputs of the block's transforms gathered as stage[y * G + g] (over the FFT
+    // outputs of the block's transforms gathered as stage[y * CG + g] (over the FFT
     // buffers, once every transform has finished reading them)
     T* stage = reinterpret_cast<T*>(lds_raw);
     constexpr int PL = FF::NPASS - 1, NBL = FF::nb(PL), RPL = 1 << FF::lrp(PL), NSL = 1 << (4 * PL);
@@ -291,12 +296,12 @@ colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, i
     __syncthreads();   // the previous tile's stage has been written out
     int tl = t;   // hidden from loop-invariant code motion, as in the row pass
     asm volatile("" : "+v"(tl));
-    fft_passes<R, LOG2N, 0, CB>(buf, tl, tw, twr, in, out);
+    fft_passes<R, LOG2N, 0, EB>(buf, tl, tw, twr, in, out);
     __syncthreads();   // every transform has read its buffer
 #pragma unroll
     for (int j = 0; j < NBL; ++j)
 #pragma unroll
-      for (int q = 0; q < RPL; ++q) stage[(t + FF::TG * j + q * NSL) * FF::G + g] = res[j][q];
+      for (int q = 0; q < RPL; ++q) stage[(t + FF::TG * j + q * NSL) * CG + g] = res[j][q];
     __syncthreads();
     // row pair (2p, 2p + 1) of column gx is stored as P = a + i b and Q = conj a + i conj b
     // (a, b the two rows): the row pass takes P for gx >= 0 and Q for the mirrored
@@ -306,7 +311,7 @@ colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, i
     for (int e = threadIdx.x; e < n * nc; e += CB) {
       const int yb = e / run, rem = e - yb * run, c = rem >> 2, yi = rem & 3;
       const int y0 = 4 * yb + (yi & 2);
-      const T a = stage[y0 * FF::G + c], b = stage[(y0 + 1) * FF::G + c];
+      const T a = stage[y0 * CG + c], b = stage[(y0 + 1) * CG + c];
       zs[(long long)yb * 4 * cols + rem] =
           (yi & 1) ? Cx<R>::mk(a.x + b.y, -a.y + b.x) : Cx<R>::mk(a.x - b.y, a.y + b.x);
     }
@@ -344,22 +349,19 @@ template <typename R, int LOG2N>
 hipError_t launch_colpass_n(const abs_plan_s* p, int nsets, const typename HermT<sizeof(R) == 4>::T* xc,
                             typename Cx<R>::T* Z, long long zset, const typename Cx<R>::T* tw,
                             hipStream_t st) {
-  constexpr int CB = col_block(LOG2N);
-  using FF = Fft<LOG2N, CB>;
+  constexpr bool F32 = sizeof(R) == 4;
+  constexpr int CB = col_block(LOG2N, F32), EB = col_engine(LOG2N);
+  using FF = Fft<LOG2N, EB>;
   const char* base = static_cast<const char*>(p->dev);
   const BinDev* bins = reinterpret_cast<const BinDev*>(base + p->dl.bins);
-  const ColTile* tiles = reinterpret_cast<const ColTile*>(base + p->dl.tiles);
-  const int ntiles = (int)p->tiles.size();
+  const ColTile* tiles = reinterpret_cast<const ColTile*>(base + (F32 ? p->dl.tiles : p->dl.tiles64));
+  const int ntiles = (int)(F32 ? p->tiles.size() : p->tiles64.size());
   if (ntiles == 0) return hipSuccess;
+  if ((F32 ? p->ct : p->ct64) != col_transforms<R, LOG2N>()) return hipErrorInvalidValue;
   constexpr int tpb = col_tiles_per_block(LOG2N);
   const dim3 grid((unsigned)((ntiles + tpb - 1) / tpb), (unsigned)nsets);
-  size_t lds = (size_t)FF::G * FF::L * sizeof(typename Cx<R>::T) +
-               (col_tw_reg<R, LOG2N>() ? 0 : TwiddlesSplit<R, LOG2N, CB>::ENTRIES * sizeof(typename Cx<R>::T));
-  // FP32 8192-point columns: one block per CU.  Their outputs leave in 32-byte runs spread
-  // over the whole field, and a second block per CU makes the pass slower (8192^2 x 4:
-  // 9.1 ms with two blocks per CU, 7.3 ms with one); asking for more than half of the
-  // CU's 160 KB of LDS keeps a second block off.
-  if (LOG2N == 13 && sizeof(R) == 4) lds = std::max<size_t>(lds, 84 * 1024);
+  const size_t lds = (size_t)col_transforms<R, LOG2N>() * FF::L * sizeof(typename Cx<R>::T) +
+                     (col_tw_reg<R, LOG2N>() ? 0 : TwiddlesSplit<R, LOG2N, EB>::ENTRIES * sizeof(typename Cx<R>::T));
   auto k = colpass_fixed_kernel<R, LOG2N>;
   hipError_t e = allow_lds(k, lds);
   if (e != hipSuccess) return e;

@@ -855,15 +855,22 @@ bool use_mfma_for(const abs_plan_s* p) {
 bool setup_kernels(abs_plan_s* p) {
   const int n = p->n, nb = p->nb;
   // FFT tiling: a column-pass workgroup of col_block(log2 n) threads transforms ct columns
-  // of one ring at once, one transform per n/16 threads (at most the whole workgroup)
+  // of one ring at once, one transform per TG threads (n/16, or n/32 when n/16 exceeds the
+  // engine's block: two butterflies a thread)
   {
-    const int cb = col_block(p->log2n);
-    p->ct = cb / std::min(cb, std::max(1, n / 16));
+    const int eb = col_engine(p->log2n), n16 = std::max(1, n / 16);
+    const int tg = std::min(n16 > eb ? n16 / 2 : n16, eb);
+    p->ct = col_block(p->log2n, true) / tg;
+    p->ct64 = col_block(p->log2n, false) / tg;
   }
   p->tiles.clear();
-  for (int m = 0; m < nb; ++m)
+  p->tiles64.clear();
+  for (int m = 0; m < nb; ++m) {
     for (int g0 = 0; g0 < p->cols[m]; g0 += p->ct)
       p->tiles.push_back({m, g0, std::min(p->ct, p->cols[m] - g0), 0});
+    for (int g0 = 0; g0 < p->cols[m]; g0 += p->ct64)
+      p->tiles64.push_back({m, g0, std::min(p->ct64, p->cols[m] - g0), 0});
+  }
   const int64_t npix = (int64_t)n * n;
   p->pix_per_block = (int)std::min<int64_t>(16384, std::max<int64_t>(1024, npix / 64));
   p->nblk = (int)((npix + p->pix_per_block - 1) / p->pix_per_block);
@@ -893,6 +900,8 @@ bool setup_kernels(abs_plan_s* p) {
   off = al(off + (size_t)nb * sizeof(BinDev));
   p->dl.tiles = off;
   off = al(off + p->tiles.size() * sizeof(ColTile));
+  p->dl.tiles64 = off;
+  off = al(off + p->tiles64.size() * sizeof(ColTile));
   build_mfma_tables(p);
   p->dl.pt_pairs = off;
   off = al(off + p->pt_pairs.size() * 4);
