@@ -14,11 +14,12 @@ namespace abs_impl {
 constexpr int kBlock = 256;          // threads per workgroup for most kernels here
 // Threads per column-pass workgroup (f32: FP32 data fields, else FP64 weight fields) and
 // the FFT engine's block, from which the threads per transform follow (Fft<n, engine>):
-// 4096-point columns use 512-thread workgroups with two 256-thread transforms (a tile's
-// outputs leave in 64-byte runs instead of 32: 4.7 -> 2.6 ms at 4096^2 x 16), and so do
-// FP32 8192-point columns, two transforms of 256 threads (two butterflies each) in 141 KB of
-// LDS; FP64 8192-point columns (278 KB for two) keep one transform a workgroup; others
-// kBlock.  The host's column tiles hold as many columns as one workgroup transforms at once.
+// 4096-point columns run two 256-thread transforms in a 512-thread workgroup, so that a
+// tile's outputs leave in 64-byte runs instead of 32 (4.7 -> 2.6 ms at 4096^2 x 16; four
+// transforms in 1024 threads measured slower, 1.39 against 1.08 ms at 4096^2 x 16), and so
+// do FP32 8192-point columns, 256 threads a transform with two butterflies each, in 141 KB
+// of LDS (8.7 -> 5.6 ms at 8192^2 x 8); FP64 8192-point columns (278 KB for two) keep one
+// transform a workgroup; others kBlock (four 2048-point transforms in 512 threads: no gain).  The host's column tiles hold as many columns as one workgroup transforms at once.
 constexpr int col_block(int log2n, bool f32) { return log2n == 12 || (log2n == 13 && f32) ? 512 : kBlock; }
 constexpr int col_engine(int log2n) { return log2n == 12 ? 512 : kBlock; }
 constexpr int kMaxBins = 64;
