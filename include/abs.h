@@ -235,6 +235,66 @@ abs_status abs_grid(abs_plan_t plan, int64_t nvis, int32_t batch, const double* 
                     size_t work_bytes, float* grid, float* wsum, int64_t* dropped,
                     void* stream);
 
+/* Gridding of many batches of visibilities on one baseline set (the paper's simulations
+ * draw every realisation on one baseline distribution, Sec. 3), Eq. (9) with the nearest
+ * cell and unit weights: the baselines are sorted once (abs_grid_sort), the caller keeps
+ * its visibilities in the sorted slot order as records of the batch's values (slot-major),
+ * and every later gridding (abs_grid_sorted) reads each record once and writes each cell
+ * once.
+ *
+ * Slot order: the mirror pairs of cells (g, -g) in the order of their representative cell
+ * (rows 0 .. n/2 of the grid, row-major; in rows 0 and n/2 columns 0 .. n/2 only), and in
+ * each pair the visibilities whose nearest cell is g before those nearest to -g.  Within
+ * one cell the order is unspecified and may differ between sorts of the same baselines;
+ * the grids do not depend on it.
+ *
+ * Sizes for a plan (its n) and nvis baselines (nvis < 2^31): the baseline set, kept while
+ * it is used ((n/2 + 1) n x 8 + 4 bytes), and the scratch abs_grid_sort uses.  Either
+ * output pointer may be NULL.  Errors: ABS_ERR_INVALID. */
+abs_status abs_grid_sort_workspace(abs_plan_t plan, int64_t nvis, size_t* set_bytes, size_t* work_bytes);
+
+/* Sort nvis baselines (Eq. 9's nearest cell, as abs_grid: round half to even in FP64;
+ * baselines with any |g| component >= n/2 are dropped).
+ *   uv      device double [nvis][2]  (u, v) in wavelengths
+ *   set     device buffer of set_bytes: receives the run table of the set (int32 [(n/2 + 1)
+ *           n x 2 + 1]: entry 2 lc is where pair lc's slots start, 2 lc + 1 where its -g
+ *           slots start; the last entry is the number kept); owned by the caller
+ *   work    device scratch of work_bytes, free again once the call's work has run
+ *   perm    device int32 [nvis]: perm[k] = the index (into uv) of the baseline in slot k
+ *           for k < kept, -1 from kept on
+ *   wsum    device float [n][n]: N_g, the number of visibilities at g plus those at -g
+ *           (unit weights); may be NULL
+ *   kept    device int64 [1]: number of baselines kept (nvis minus those dropped); may be NULL
+ * Asynchronous on `stream`.  Errors: ABS_ERR_INVALID, ABS_ERR_UNBOUND, ABS_ERR_NOMEM,
+ * ABS_ERR_DEVICE. */
+abs_status abs_grid_sort(abs_plan_t plan, int64_t nvis, const double* uv, void* set, size_t set_bytes,
+                         void* work, size_t work_bytes, int32_t* perm, float* wsum, int64_t* kept,
+                         void* stream);
+
+/* Reorder visibilities into slot-order records once: out[k][b] = vis[b][perm[k]] for
+ * k < ld (0 where perm[k] is -1).
+ *   vis   device float [batch][nvis][2];  out  device float [ld][batch][2], ld <= nvis
+ *   perm  as abs_grid_sort returned it
+ * Asynchronous on `stream`.  Errors: ABS_ERR_INVALID, ABS_ERR_DEVICE. */
+abs_status abs_grid_permute(abs_plan_t plan, int64_t nvis, int32_t batch, const int32_t* perm, int64_t ld,
+                            const float* vis, float* out, void* stream);
+
+/* Eq. (9) on a sorted baseline set: the same grids abs_grid gives for the nearest cell
+ * and unit weights, bit for bit (both sum each pair of cells (g, -g) in 64-bit fixed point
+ * with a scale taken from that pair's own values).
+ *   set     the set from abs_grid_sort (any plan of the same n may use it)
+ *   batch   1 <= batch <= max_batch (x nchan)
+ *   ld      slots (records) in vis; slots from ld on are not read (give at least the kept
+ *           count, or their visibilities are left out)
+ *   vis     device float [ld][batch][2]: the batch's values of each slot, in slot order
+ *           (abs_grid_permute, or produced so)
+ *   grid    device float [batch][n][n][2]  V_g, overwritten
+ *   wsum    device float [n][n]  N_g of the slots read, overwritten; may be NULL
+ * Asynchronous on `stream`.  Errors: ABS_ERR_INVALID, ABS_ERR_UNBOUND, ABS_ERR_NOMEM,
+ * ABS_ERR_DEVICE. */
+abs_status abs_grid_sorted(abs_plan_t plan, const void* set, size_t set_bytes, int32_t batch, int64_t ld,
+                           const float* vis, float* grid, float* wsum, void* stream);
+
 /* The estimator, Eqs. (10)-(12), for `batch` gridded-visibility arrays.
  *   batch      1 <= batch <= max_batch
  *   dtype      ABS_C64 (float pairs) or ABS_C128 (double pairs, rounded to FP32 on load)

@@ -73,6 +73,10 @@ def lib():
         "abs_estimate_workspace": [_P, i32, i32, i32, ctypes.POINTER(sz)],
         "abs_grid_workspace": [_P, i64, i32, ctypes.POINTER(sz)],
         "abs_grid": [_P, i64, i32, _P, _P, _P, i32, _P, sz, _P, _P, _P, _P],
+        "abs_grid_sort_workspace": [_P, i64, ctypes.POINTER(sz), ctypes.POINTER(sz)],
+        "abs_grid_sort": [_P, i64, _P, _P, sz, _P, sz, _P, _P, _P, _P],
+        "abs_grid_permute": [_P, i64, i32, _P, i64, _P, _P, _P],
+        "abs_grid_sorted": [_P, _P, sz, i32, i64, _P, _P, _P, _P],
         "abs_estimate": [_P, i32, i32, _P, _P, i32, _P, _P, sz, _P, _P, _P],
         "abs_estimate_noalloc": [_P, i32, i32, _P, _P, i32, _P, _P, _P, _P],
         "abs_estimate_complex_workspace": [_P, i32, i32, i32, ctypes.POINTER(sz)],

@@ -20,6 +20,14 @@
 //            one lane group per cell streams the records of its cell and of its mirror
 //            cell (7 x 7 neighbouring cells for the Gaussian kernel).  16 realisations
 //            per pass, FP32 out.
+//
+// A baseline set gridded many times (the realisations of a simulation share one baseline
+// distribution, Sec. 3) is sorted once instead (abs_grid_sort): every visibility gets a
+// slot, the slots ordered by mirror pair of cells (g, -g) and within a pair the visibilities
+// nearest to g before those nearest to -g, and a table keeps where each pair's run starts.
+// The caller keeps its visibilities in slot order, as records of the batch's values
+// ([slot][batch], the layout the fill pass writes), and abs_grid_sorted is then the pair
+// gather alone: every record read once, every cell written once.
 #include <algorithm>
 
 #include "abs_internal.h"
@@ -70,6 +78,21 @@ __device__ __forceinline__ int nearest_cell(double2 U, double du, int n) {
   return (gy < 0 ? gy + n : gy) * n + (gx < 0 ? gx + n : gx);
 }
 
+// The pair of cells (g, -g) has one representative cell (iy, ix): rows 0 .. n/2, and in
+// rows 0 and n/2 only columns 0 .. n/2.  Pair index lc = iy * n + ix of the representative;
+// (n/2 + 1) n indices, some unused.  Sort key of a visibility with nearest cell c: 2 lc if c
+// is the representative of pair lc, 2 lc + 1 if c is its mirror; -1 for a dropped one.
+__device__ __forceinline__ int pair_key(int c, int n) {
+  if (c < 0) return -1;
+  const int half = n / 2;
+  const int iy = c / n, ix = c - iy * n;
+  if (iy <= half && !((iy == 0 || iy == half) && ix > half)) return 2 * c;
+  const int my = iy ? n - iy : 0, mx = ix ? n - ix : 0;
+  return 2 * (my * n + mx) + 1;
+}
+
+// KEY = false: counting-sort key = nearest cell (abs_grid); true: pair_key (abs_grid_sort)
+template <bool KEY>
 __global__ void __launch_bounds__(kBlock)
 grid_prep_kernel(int n, double du, long long nvis, const double2* __restrict__ uv,
                  const float* __restrict__ vw, int* __restrict__ cell, int* __restrict__ rank,
@@ -78,7 +101,7 @@ grid_prep_kernel(int n, double du, long long nvis, const double2* __restrict__ u
   unsigned long long ndrop = 0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nvis; i += stride) {
-    const int c = nearest_cell(uv[i], du, n);
+    const int c = KEY ? pair_key(nearest_cell(uv[i], du, n), n) : nearest_cell(uv[i], du, n);
     cell[i] = c;
     if (c < 0) {
       ++ndrop;
@@ -359,11 +382,15 @@ __device__ __forceinline__ PairCell<LPC> pair_cell(long long lc, int n) {
   return r;
 }
 
-template <int LPC, bool VEC>
+// KEYED = false: `start` holds each cell's run (abs_grid's counting sort by cell).  KEYED =
+// true: `start` is a sorted baseline set's table (runs by pair: entry 2 lc, the visibilities
+// nearest to g, then from entry 2 lc + 1 those nearest to -g), and records from `ld` on are
+// not read.
+template <int LPC, bool VEC, bool KEYED>
 __global__ void __launch_bounds__(kBlock)
 grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ sorted,
-                         const int* __restrict__ start, const GridScalars* sc,
-                         float2* __restrict__ grid, float* __restrict__ wsum) {
+                         const int* __restrict__ start, long long ld, float2* __restrict__ grid,
+                         float* __restrict__ wsum) {
   constexpr int PB = kBlock / LPC;   // pairs per block
   __shared__ float2 out_c[2 * LPC][PB + 1], out_m[2 * LPC][PB + 1];   // padded: rows 2q start in different banks
   const long long nn = (long long)n * n;
@@ -375,8 +402,6 @@ grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ so
   const int iy = (int)(c / n), ix = (int)(c - (long long)iy * n);
   const int gy = iy < half ? iy : iy - n, gx = ix < half ? ix : ix - n;
   const bool inside = pc.valid && gx > -half && gy > -half;   // the mirror is inside exactly then
-  // a cell adds at most 2 maxcnt terms (its own records and its mirror's)
-  const double sv = fixed_scale(__uint_as_float(sc->vmax_bits), 2ll * (long long)sc->maxcnt);
   const int bq = b0 + 2 * q;
   const bool has0 = bq < batch, has1 = bq + 1 < batch;
   auto load = [&](int p) -> float4 {
@@ -389,9 +414,8 @@ grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ so
       return make_float4(a.x, a.y, b.x, b.y);
     }
   };
-  // fixed-point sum of one cell's records, walked in chunks of kG with the next chunk's
-  // loads in flight
-  auto cell_sum = [&](int p0, int cnt, double* a) {
+  // walks one cell's records in chunks of kG with the next chunk's loads in flight
+  auto walk = [&](int p0, int cnt, auto&& use) {
     constexpr int kG = 4;
     float4 cur[kG], nxt[kG];
 #pragma unroll
@@ -401,36 +425,64 @@ grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ so
       for (int u = 0; u < kG; ++u)
         nxt[u] = i0 + kG + u < cnt ? load(p0 + i0 + kG + u) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-      for (int u = 0; u < kG; ++u) {   // entries past cnt are zero
-        a[0] += rint((double)cur[u].x * sv);
-        a[1] += rint((double)cur[u].y * sv);
-        a[2] += rint((double)cur[u].z * sv);
-        a[3] += rint((double)cur[u].w * sv);
-      }
+      for (int u = 0; u < kG; ++u) use(cur[u]);   // entries past cnt are zero
 #pragma unroll
       for (int u = 0; u < kG; ++u) cur[u] = nxt[u];
     }
   };
-  double sc4[4] = {0.0, 0.0, 0.0, 0.0}, sm4[4] = {0.0, 0.0, 0.0, 0.0};
-  int cd = 0, cm = 0;
-  if (inside) {
-    const int p0 = start[c];
+  int p0 = 0, cd = 0, q0 = 0, cm = 0;
+  if (inside && KEYED) {
+    // pair index = the representative's cell index c
+    const long long a = min((long long)start[2 * c], ld);
+    const long long h = max(a, min((long long)start[2 * c + 1], ld));
+    const long long e = max(h, min((long long)start[2 * c + 2], ld));
+    p0 = (int)a;
+    cd = (int)(h - a);
+    q0 = (int)h;
+    cm = m != c ? (int)(e - h) : cd;
+  } else if (inside) {
+    p0 = start[c];
     cd = start[c + 1] - p0;
-    cell_sum(p0, cd, sc4);
     if (m != c) {
-      const int q0 = start[m];
+      q0 = start[m];
       cm = start[m + 1] - q0;
-      cell_sum(q0, cm, sm4);
     } else {
       cm = cd;
-      for (int k = 0; k < 4; ++k) sm4[k] = sc4[k];
     }
   }
-  const double iv = 1.0 / sv;  // a power of two: exact
-  out_c[2 * q][kp] = make_float2((float)((sc4[0] + sm4[0]) * iv), (float)((sc4[1] - sm4[1]) * iv));
-  out_c[2 * q + 1][kp] = make_float2((float)((sc4[2] + sm4[2]) * iv), (float)((sc4[3] - sm4[3]) * iv));
-  out_m[2 * q][kp] = make_float2((float)((sm4[0] + sc4[0]) * iv), (float)((sm4[1] - sc4[1]) * iv));
-  out_m[2 * q + 1][kp] = make_float2((float)((sm4[2] + sc4[2]) * iv), (float)((sm4[3] - sc4[3]) * iv));
+  // the scale of each realisation's fixed-point sums comes from the pair's own records:
+  // their largest component, and the number of terms the cell sums add (cd + cm)
+  float mx0 = 0.f, mx1 = 0.f;
+  auto vmax = [&](float4 v) {
+    mx0 = fmaxf(mx0, fmaxf(fabsf(v.x), fabsf(v.y)));
+    mx1 = fmaxf(mx1, fmaxf(fabsf(v.z), fabsf(v.w)));
+  };
+  walk(p0, cd, vmax);
+  if (m != c) walk(q0, cm, vmax);
+  const double s0 = fixed_scale(mx0, (long long)cd + cm), s1 = fixed_scale(mx1, (long long)cd + cm);
+  double sc4[4] = {0.0, 0.0, 0.0, 0.0}, sm4[4] = {0.0, 0.0, 0.0, 0.0};
+  // the records again (now from the caches), summed
+  walk(p0, cd, [&](float4 v) {
+    sc4[0] += rint((double)v.x * s0);
+    sc4[1] += rint((double)v.y * s0);
+    sc4[2] += rint((double)v.z * s1);
+    sc4[3] += rint((double)v.w * s1);
+  });
+  if (m != c) {
+    walk(q0, cm, [&](float4 v) {
+      sm4[0] += rint((double)v.x * s0);
+      sm4[1] += rint((double)v.y * s0);
+      sm4[2] += rint((double)v.z * s1);
+      sm4[3] += rint((double)v.w * s1);
+    });
+  } else {
+    for (int k = 0; k < 4; ++k) sm4[k] = sc4[k];
+  }
+  const double i0 = 1.0 / s0, i1 = 1.0 / s1;  // powers of two: exact
+  out_c[2 * q][kp] = make_float2((float)((sc4[0] + sm4[0]) * i0), (float)((sc4[1] - sm4[1]) * i0));
+  out_c[2 * q + 1][kp] = make_float2((float)((sc4[2] + sm4[2]) * i1), (float)((sc4[3] - sm4[3]) * i1));
+  out_m[2 * q][kp] = make_float2((float)((sm4[0] + sc4[0]) * i0), (float)((sm4[1] - sc4[1]) * i0));
+  out_m[2 * q + 1][kp] = make_float2((float)((sm4[2] + sc4[2]) * i1), (float)((sm4[3] - sc4[3]) * i1));
   if (pc.valid && wsum != nullptr && b0 == 0 && q == 0) {
     wsum[c] = (float)(cd + cm);
     wsum[m] = (float)(cd + cm);
@@ -447,6 +499,94 @@ grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ so
     if (w.m != w.c) plane[w.m] = out_m[r][k];
   }
 }
+
+// ---- baseline sets sorted once (abs_grid_sort / abs_grid_sorted) --------------------------
+
+// Pair indices lc of a grid of side n: (n/2 + 1) n; the sort keys are twice that.
+__host__ __device__ inline long long pair_count(int n) { return (long long)(n / 2 + 1) * n; }
+
+// Slot of every kept visibility: perm[start[key] + rank] = i; slots from the kept count on
+// get -1, and the kept count is handed out.
+__global__ void __launch_bounds__(kBlock)
+grid_place_kernel(long long nvis, const int* __restrict__ key, const int* __restrict__ rank,
+                  const int* __restrict__ start, long long nkeys, int* __restrict__ perm,
+                  long long* __restrict__ kept) {
+  const long long total = start[nkeys];
+  if (kept && blockIdx.x == 0 && threadIdx.x == 0) *kept = total;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nvis; i += stride) {
+    const int k = key[i];
+    if (k >= 0) perm[start[k] + rank[i]] = (int)i;
+    if (i >= total) perm[i] = -1;
+  }
+}
+
+// out[k][b] = vis[b][perm[k]] (0 where perm[k] is -1), k < ld: consecutive threads write
+// consecutive values of the records.
+__global__ void __launch_bounds__(kBlock)
+grid_permute_kernel(long long nvis, int batch, const int* __restrict__ perm, long long ld,
+                    const float2* __restrict__ vis, float2* __restrict__ out) {
+  const long long total = ld * batch;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const long long k = e / batch, b = e - k * batch;
+    const int i = perm[k];
+    out[e] = (i >= 0 && i < nvis) ? vis[b * nvis + i] : make_float2(0.f, 0.f);
+  }
+}
+
+// The keyed pair gather for realisations b0 .. b0 + 2 lpc - 1 of `batch` (lanes per pair as
+// abs_grid picks them); batch = 0 writes only the counts.
+void launch_keyed_pairs(int n, int batch, int b0, int lpc, const float2* rec, const int* start, long long ld,
+                        float2* grid, float* wsum, hipStream_t st) {
+  const unsigned gp = (unsigned)((pair_count(n) * lpc + kBlock - 1) / kBlock);
+  const bool vec = (batch & 1) == 0;
+#define ABS_KPAIRS(LL, VV) \
+  grid_gather_pairs_kernel<LL, VV, true><<<gp, kBlock, 0, st>>>(n, batch, b0, rec, start, ld, grid, wsum)
+  switch (lpc * 2 + (vec ? 1 : 0)) {
+    case 2: ABS_KPAIRS(1, false); break;
+    case 3: ABS_KPAIRS(1, true); break;
+    case 4: ABS_KPAIRS(2, false); break;
+    case 5: ABS_KPAIRS(2, true); break;
+    case 8: ABS_KPAIRS(4, false); break;
+    case 9: ABS_KPAIRS(4, true); break;
+    case 16: ABS_KPAIRS(8, false); break;
+    default: ABS_KPAIRS(8, true); break;
+  }
+#undef ABS_KPAIRS
+}
+
+// lanes per cell: enough pairs of realisations for one pass of up to kRec of them
+int lanes_per_cell(int batch) {
+  const int nbc = std::min(batch, kRec);
+  return nbc <= 2 ? 1 : nbc <= 4 ? 2 : nbc <= 8 ? 4 : 8;
+}
+
+struct SortWork {
+  size_t sc, key, rank, cnt, tiles, total;
+};
+
+SortWork sort_layout(long long n, long long nvis) {
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const long long nkeys = 2 * pair_count((int)n);
+  const long long ntiles = (nkeys + kScanTile - 1) / kScanTile;
+  SortWork g{};
+  size_t off = 0;
+  g.sc = off;
+  off = al(off + sizeof(GridScalars));
+  g.key = off;
+  off = al(off + (size_t)nvis * 4);
+  g.rank = off;
+  off = al(off + (size_t)nvis * 4);
+  g.cnt = off;
+  off = al(off + (size_t)nkeys * 4);
+  g.tiles = off;
+  off = al(off + (size_t)ntiles * 4);
+  g.total = off;
+  return g;
+}
+
+size_t set_bytes_of(int n) { return (size_t)(2 * pair_count(n) + 1) * 4; }
 
 struct GridWork {
   size_t sc, cell, rank, cnt, start, tiles, list, sorted, total;
@@ -526,7 +666,7 @@ extern "C" abs_status abs_grid(abs_plan_t p, int64_t nvis, int32_t batch, const 
   prof_begin(p, ABS_STAGE_GRID, st);
   grid_clear_kernel<<<1024, kBlock, 0, st>>>(cnt, cells, sc);
   const unsigned gv = (unsigned)std::min<long long>(8192, std::max<long long>(1, (nvis + kBlock - 1) / kBlock));
-  if (nvis > 0) grid_prep_kernel<<<gv, kBlock, 0, st>>>(p->n, p->du, nvis, uvd, vis_w, cell, rank, cnt, sc);
+  if (nvis > 0) grid_prep_kernel<false><<<gv, kBlock, 0, st>>>(p->n, p->du, nvis, uvd, vis_w, cell, rank, cnt, sc);
   scan_tiles_kernel<<<ntiles, kBlock, 0, st>>>(cnt, cells, start, tsum, sc);
   scan_sums_kernel<<<1, kBlock, 0, st>>>(tsum, ntiles, start, cells, sc, reinterpret_cast<long long*>(dropped));
   scan_add_kernel<<<ntiles, kBlock, 0, st>>>(start, cells, tsum);
@@ -535,9 +675,7 @@ extern "C" abs_status abs_grid(abs_plan_t p, int64_t nvis, int32_t batch, const 
         nvis, batch, cell, start, rank, reinterpret_cast<const float2*>(vis), vis_w, lst, sorted, sc);
   const bool vec = (batch & 1) == 0;
   float2* g2 = reinterpret_cast<float2*>(grid);
-  // lanes per cell: enough pairs of realisations for one pass of up to kRec of them
-  const int nbc = std::min(batch, kRec);
-  const int lpc = nbc <= 2 ? 1 : nbc <= 4 ? 2 : nbc <= 8 ? 4 : 8;
+  const int lpc = lanes_per_cell(batch);
   const unsigned gc = (unsigned)((cells * lpc + kBlock - 1) / kBlock);
   for (int b0 = 0; b0 < batch; b0 += 2 * lpc) {
 #define ABS_GATHER(RR, LL, VV)                                                                  \
@@ -558,7 +696,7 @@ extern "C" abs_status abs_grid(abs_plan_t p, int64_t nvis, int32_t batch, const 
       // unit weights: one lane group per mirror pair of cells
       const unsigned gp = (unsigned)(((long long)(p->n / 2 + 1) * p->n * lpc + kBlock - 1) / kBlock);
 #define ABS_PAIRS(LL, VV)                                                                           \
-  grid_gather_pairs_kernel<LL, VV><<<gp, kBlock, 0, st>>>(p->n, batch, b0, sorted, start, sc, g2, wsum)
+  grid_gather_pairs_kernel<LL, VV, false><<<gp, kBlock, 0, st>>>(p->n, batch, b0, sorted, start, 0, g2, wsum)
       switch (lpc * 2 + (vec ? 1 : 0)) {
         case 2: ABS_PAIRS(1, false); break;
         case 3: ABS_PAIRS(1, true); break;
@@ -574,6 +712,86 @@ extern "C" abs_status abs_grid(abs_plan_t p, int64_t nvis, int32_t batch, const 
 #undef ABS_GATHER_L
 #undef ABS_GATHER
   }
+  prof_end(p, ABS_STAGE_GRID, st);
+  return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
+}
+
+extern "C" abs_status abs_grid_sort_workspace(abs_plan_t p, int64_t nvis, size_t* set_bytes,
+                                              size_t* work_bytes) {
+  if (!p || nvis < 0 || nvis > 0x7fffffffLL) return ABS_ERR_INVALID;
+  if (set_bytes) *set_bytes = set_bytes_of(p->n);
+  if (work_bytes) *work_bytes = sort_layout(p->n, nvis).total;
+  return ABS_OK;
+}
+
+extern "C" abs_status abs_grid_sort(abs_plan_t p, int64_t nvis, const double* uv, void* set,
+                                    size_t set_bytes, void* work, size_t work_bytes, int32_t* perm,
+                                    float* wsum, int64_t* kept, void* stream) {
+  if (!p) return ABS_ERR_INVALID;
+  if (!p->dev) return ABS_ERR_UNBOUND;
+  if (nvis < 0 || nvis > 0x7fffffffLL || !set || !work || (nvis > 0 && (!uv || !perm)))
+    return ABS_ERR_INVALID;
+  if ((reinterpret_cast<uintptr_t>(uv) | reinterpret_cast<uintptr_t>(set) |
+       reinterpret_cast<uintptr_t>(work)) & 15)
+    return ABS_ERR_INVALID;
+  const SortWork sl = sort_layout(p->n, nvis);
+  if (set_bytes < set_bytes_of(p->n) || work_bytes < sl.total) return ABS_ERR_NOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* wk = static_cast<char*>(work);
+  GridScalars* sc = reinterpret_cast<GridScalars*>(wk + sl.sc);
+  int* key = reinterpret_cast<int*>(wk + sl.key);
+  int* rank = reinterpret_cast<int*>(wk + sl.rank);
+  int* cnt = reinterpret_cast<int*>(wk + sl.cnt);
+  int* tsum = reinterpret_cast<int*>(wk + sl.tiles);
+  int* start = static_cast<int*>(set);
+  const long long npair = pair_count(p->n), nkeys = 2 * npair;
+  const int ntiles = (int)((nkeys + kScanTile - 1) / kScanTile);
+  const double2* uvd = reinterpret_cast<const double2*>(uv);
+  (void)hipGetLastError();
+  grid_clear_kernel<<<1024, kBlock, 0, st>>>(cnt, nkeys, sc);
+  const unsigned gv = (unsigned)std::min<long long>(8192, std::max<long long>(1, (nvis + kBlock - 1) / kBlock));
+  if (nvis > 0) grid_prep_kernel<true><<<gv, kBlock, 0, st>>>(p->n, p->du, nvis, uvd, nullptr, key, rank, cnt, sc);
+  scan_tiles_kernel<<<ntiles, kBlock, 0, st>>>(cnt, nkeys, start, tsum, sc);
+  scan_sums_kernel<<<1, kBlock, 0, st>>>(tsum, ntiles, start, nkeys, sc, nullptr);
+  scan_add_kernel<<<ntiles, kBlock, 0, st>>>(start, nkeys, tsum);
+  grid_place_kernel<<<gv, kBlock, 0, st>>>(nvis, key, rank, start, nkeys, perm, reinterpret_cast<long long*>(kept));
+  if (wsum) launch_keyed_pairs(p->n, 0, 0, 1, nullptr, start, (long long)nvis, nullptr, wsum, st);
+  return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
+}
+
+extern "C" abs_status abs_grid_permute(abs_plan_t p, int64_t nvis, int32_t batch, const int32_t* perm,
+                                       int64_t ld, const float* vis, float* out, void* stream) {
+  if (!p) return ABS_ERR_INVALID;
+  if (nvis < 0 || nvis > 0x7fffffffLL || ld < 0 || ld > nvis || batch < 1) return ABS_ERR_INVALID;
+  if (ld > 0 && (!perm || !vis || !out)) return ABS_ERR_INVALID;
+  if ((reinterpret_cast<uintptr_t>(vis) | reinterpret_cast<uintptr_t>(out)) & 7) return ABS_ERR_INVALID;
+  if (ld == 0) return ABS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  const long long total = ld * (long long)batch;
+  const unsigned g = (unsigned)std::min<long long>(16384, (total + kBlock - 1) / kBlock);
+  grid_permute_kernel<<<g, kBlock, 0, st>>>(nvis, batch, perm, ld, reinterpret_cast<const float2*>(vis),
+                                            reinterpret_cast<float2*>(out));
+  return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
+}
+
+extern "C" abs_status abs_grid_sorted(abs_plan_t p, const void* set, size_t set_bytes, int32_t batch,
+                                      int64_t ld, const float* vis, float* grid, float* wsum, void* stream) {
+  if (!p) return ABS_ERR_INVALID;
+  if (!p->dev) return ABS_ERR_UNBOUND;
+  if (batch < 1 || batch > p->max_batch * p->nchan || ld < 0 || ld > 0x7fffffffLL) return ABS_ERR_INVALID;
+  if (!set || !grid || (ld > 0 && !vis)) return ABS_ERR_INVALID;
+  if ((reinterpret_cast<uintptr_t>(set) | reinterpret_cast<uintptr_t>(vis) |
+       reinterpret_cast<uintptr_t>(grid)) & 15)
+    return ABS_ERR_INVALID;
+  if (set_bytes < set_bytes_of(p->n)) return ABS_ERR_NOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int lpc = lanes_per_cell(batch);
+  (void)hipGetLastError();
+  prof_begin(p, ABS_STAGE_GRID, st);
+  for (int b0 = 0; b0 < batch; b0 += 2 * lpc)
+    launch_keyed_pairs(p->n, batch, b0, lpc, reinterpret_cast<const float2*>(vis), static_cast<const int*>(set),
+                       (long long)ld, reinterpret_cast<float2*>(grid), b0 == 0 ? wsum : nullptr, st);
   prof_end(p, ABS_STAGE_GRID, st);
   return hipGetLastError() == hipSuccess ? ABS_OK : ABS_ERR_DEVICE;
 }

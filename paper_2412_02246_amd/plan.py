@@ -266,6 +266,52 @@ class Plan:
                                  _ptr(dropped), _stream(stream)), "abs_grid")
         return grid, wsum, dropped
 
+    def grid_sort(self, uv, stream=None):
+        """Sort a baseline set once (Eq. 9, nearest cell) for gridding many batches of
+        visibilities on it with grid_sorted.  uv: float64 [nvis][2] (wavelengths).  Returns
+        a BaselineSet (its perm, counts wsum and kept count; the run table stays on the
+        device)."""
+        import torch
+        if uv.dtype != torch.float64 or not uv.is_contiguous() or uv.dim() != 2 or uv.shape[1] != 2:
+            raise TypeError("uv must be contiguous float64 [nvis][2]")
+        nvis = uv.shape[0]
+        sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        L.check(L.lib().abs_grid_sort_workspace(self.handle, nvis, ctypes.byref(sb), ctypes.byref(wb)),
+                "abs_grid_sort_workspace")
+        dev = uv.device
+        table = torch.empty(sb.value, dtype=torch.uint8, device=dev)
+        work = torch.empty(max(wb.value, 256), dtype=torch.uint8, device=dev)
+        perm = torch.empty(max(nvis, 1), dtype=torch.int32, device=dev)
+        wsum = torch.empty((self.n, self.n), dtype=torch.float32, device=dev)
+        kept = torch.empty(1, dtype=torch.int64, device=dev)
+        L.check(L.lib().abs_grid_sort(self.handle, nvis, _ptr(uv), _ptr(table), table.numel(), _ptr(work),
+                                      work.numel(), _ptr(perm), _ptr(wsum), _ptr(kept), _stream(stream)),
+                "abs_grid_sort")
+        if stream is None:
+            torch.cuda.current_stream(dev).synchronize()
+        else:
+            stream.synchronize()
+        del work
+        return BaselineSet(self, table, perm[:nvis], wsum, int(kept.item()))
+
+    def grid_sorted(self, bset, vis, wsum=False, stream=None):
+        """Grid visibilities held in bset's slot order (Eq. 9, nearest cell, unit weights).
+        vis: complex64 [ld][batch] (each slot's values for the batch) with ld >= bset.kept.
+        Returns grid complex64 [batch][n][n], or (grid, wsum float32 [n][n]) with wsum=True."""
+        import torch
+        if vis.dim() == 1:
+            vis = vis.unsqueeze(1)
+        if vis.dtype != torch.complex64 or not vis.is_contiguous():
+            raise TypeError("vis must be contiguous complex64 [ld][batch]")
+        if bset.n != self.n:
+            raise ValueError("baseline set of a grid of side %d, plan has %d" % (bset.n, self.n))
+        ld, batch = vis.shape
+        grid = torch.empty((batch, self.n, self.n), dtype=torch.complex64, device=vis.device)
+        ws = torch.empty((self.n, self.n), dtype=torch.float32, device=vis.device) if wsum else None
+        L.check(L.lib().abs_grid_sorted(self.handle, _ptr(bset.table), bset.table.numel(), batch, ld,
+                                        _ptr(vis), _ptr(grid), _ptr(ws), _stream(stream)), "abs_grid_sorted")
+        return (grid, ws) if wsum else grid
+
     # -- after the estimator (Secs. 3-4) ------------------------------------------
     def rebin_table(self, l1_edges, nmu=5, nt=5):
         """Bin of every triplet (host int32 [ntrip], -1 outside the ell1 edges) and the
@@ -360,3 +406,29 @@ def simulate(sky, dtheta, uv, beam=L.BEAM_NONE, beam_param=0.0, q=1.0, stream=No
                                  nvis, _ptr(uv), _ptr(vis), ctypes.c_void_p(work.data_ptr() + off),
                                  work.numel() - off, _stream(stream)), "abs_simulate")
     return vis
+
+
+class BaselineSet:
+    """A baseline set sorted by Plan.grid_sort: ``perm`` (int32 [nvis], the baseline index of
+    each slot, -1 from ``kept`` on), ``wsum`` (N_g, float32 [n][n]), ``kept`` and the device
+    run table.  ``permute`` puts visibilities into slot order once."""
+
+    def __init__(self, plan, table, perm, wsum, kept):
+        self._plan = plan
+        self.n = plan.n
+        self.table, self.perm, self.wsum, self.kept = table, perm, wsum, kept
+        self.nvis = perm.numel()
+
+    def permute(self, vis, ld=None, stream=None):
+        """vis complex64 [batch][nvis] in baseline order -> records [ld][batch] in slot
+        order (ld = kept by default)."""
+        import torch
+        if vis.dim() == 1:
+            vis = vis.unsqueeze(0)
+        if vis.dtype != torch.complex64 or not vis.is_contiguous() or vis.shape[1] != self.nvis:
+            raise TypeError("vis must be contiguous complex64 [batch][%d]" % self.nvis)
+        ld = self.kept if ld is None else int(ld)
+        out = torch.empty((ld, vis.shape[0]), dtype=torch.complex64, device=vis.device)
+        L.check(L.lib().abs_grid_permute(self._plan.handle, self.nvis, vis.shape[0], _ptr(self.perm), ld,
+                                         _ptr(vis), _ptr(out), _stream(stream)), "abs_grid_permute")
+        return out
