@@ -280,8 +280,9 @@ abs_status abs_grid_permute(abs_plan_t plan, int64_t nvis, int32_t batch, const 
                             const float* vis, float* out, void* stream);
 
 /* Eq. (9) on a sorted baseline set: the same grids abs_grid gives for the nearest cell
- * and unit weights, bit for bit (both sum each pair of cells (g, -g) in 64-bit fixed point
- * with a scale taken from that pair's own values).
+ * and unit weights, bit for bit (both sum each pair of cells (g, -g) exactly, in FP64, or in
+ * 64-bit fixed point with a scale from that pair's own values when their magnitudes span
+ * too wide a range for that; neither depends on the order of the visibilities).
  *   set     the set from abs_grid_sort (any plan of the same n may use it)
  *   batch   1 <= batch <= max_batch (x nchan)
  *   ld      slots (records) in vis; slots from ld on are not read (give at least the kept

@@ -6,9 +6,9 @@
 //
 // The batch of realisations shares the baselines, so the visibilities are sorted by
 // their nearest cell once (counting sort) and every cell then gathers its own
-// contributions: no floating-point atomics, and the sums are accumulated as 64-bit
-// fixed-point integers with a power-of-two scale, so the result is independent of
-// the order inside each cell (bitwise reproducible).
+// contributions: no floating-point atomics, and every sum is exact (FP64 sums that no
+// rounding can touch, or 64-bit fixed-point integers with a power-of-two scale), so the
+// result is independent of the order inside each cell (bitwise reproducible).
 //   prep:    nearest cell per visibility, per-cell counts (the count before a
 //            visibility's own increment is its rank in its cell), largest w
 //   scan:    exclusive prefix sum of the counts (three kernels)
@@ -354,10 +354,10 @@ grid_gather_kernel(int n, double du, double pit2, int batch, int b0,
 }
 
 // Nearest cell, unit visibility weights: one group of LPC lanes per pair of mirror cells
-// (g, -g), reading each cell's records once.  With S_g the fixed-point sum of the records
-// whose nearest cell is g, the grid gets S_g + conj S_-g at g and S_-g + conj S_g at -g
-// (exact integer sums in FP64, so the results are bit for bit those of gathering both
-// lists at each cell); the weight sum is the record count of both cells.  Representatives:
+// (g, -g), reading each cell's records once.  With S_g the exact sum of the records whose
+// nearest cell is g, the grid gets S_g + conj S_-g at g and S_-g + conj S_g at -g (so the
+// results are bit for bit those of gathering both lists at each cell); the weight sum is
+// the record count of both cells.  Representatives:
 // rows 0 .. n/2 in order (|gy| ascending: the long lists of short baselines first), and in
 // rows 0 and n/2 only columns 0 .. n/2; row and column -n/2 receive nothing.
 // The block's results go out through LDS, one realisation plane at a time, so that each
@@ -450,36 +450,79 @@ grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ so
       cm = cd;
     }
   }
-  // the scale of each realisation's fixed-point sums comes from the pair's own records:
-  // their largest component, and the number of terms the cell sums add (cd + cm).  (Keeping
-  // a run's first records in registers for the second pass was slower at 8192^2 x 8: 2.86
-  // against 2.54 ms, from the lower occupancy its registers allow.)
-  float mx0 = 0.f, mx1 = 0.f;
-  auto vmax = [&](float4 v) {
-    mx0 = fmaxf(mx0, fmaxf(fabsf(v.x), fabsf(v.y)));
-    mx1 = fmaxf(mx1, fmaxf(fabsf(v.z), fabsf(v.w)));
+  // One pass sums the pair's records in plain FP64 and bounds their binary exponents.  A
+  // non-zero FP32 value x with biased exponent field a' and a = max(a', 1) is an integer
+  // multiple of 2^(a - 150) and |x| < 2^(a - 126); so when a realisation's terms (both
+  // cells, at most T = cd + cm per sum) satisfy ceil(log2 T) + amax - amin <= 29, every
+  // partial sum is a multiple of 2^(amin - 150) below 2^(53 + amin - 150) in magnitude and
+  // exact, in any order.  Otherwise (a far wider spread of magnitudes, or Inf / NaN) that
+  // realisation is summed again, from the caches, in 64-bit fixed point with the unit
+  // 2^(amax - 126 - 51 + lg): each term rounded to it, the sums exact and again
+  // order-independent.  Either way the result does not depend on the order of the
+  // records, and the decision depends on the values alone.
+  const long long terms = (long long)cd + cm;
+  int lg = 0;
+  while ((1ll << lg) < (terms > 0 ? terms : 1)) ++lg;
+  int amin0 = 255, amax0 = 0, amin1 = 255, amax1 = 0;
+  auto expo = [](float x, int& amin, int& amax) {
+    const unsigned u = __float_as_uint(x) & 0x7fffffffu;
+    if (u) {
+      const int a = max((int)(u >> 23), 1);
+      amin = min(amin, a);
+      amax = max(amax, a);
+    }
   };
-  walk(p0, cd, vmax);
-  if (m != c) walk(q0, cm, vmax);
-  const double s0 = fixed_scale(mx0, (long long)cd + cm), s1 = fixed_scale(mx1, (long long)cd + cm);
   double sc4[4] = {0.0, 0.0, 0.0, 0.0}, sm4[4] = {0.0, 0.0, 0.0, 0.0};
-  // the records again (now from the caches), summed
   walk(p0, cd, [&](float4 v) {
-    sc4[0] += rint((double)v.x * s0);
-    sc4[1] += rint((double)v.y * s0);
-    sc4[2] += rint((double)v.z * s1);
-    sc4[3] += rint((double)v.w * s1);
+    expo(v.x, amin0, amax0);
+    expo(v.y, amin0, amax0);
+    expo(v.z, amin1, amax1);
+    expo(v.w, amin1, amax1);
+    sc4[0] += (double)v.x;
+    sc4[1] += (double)v.y;
+    sc4[2] += (double)v.z;
+    sc4[3] += (double)v.w;
   });
   if (m != c) {
     walk(q0, cm, [&](float4 v) {
-      sm4[0] += rint((double)v.x * s0);
-      sm4[1] += rint((double)v.y * s0);
-      sm4[2] += rint((double)v.z * s1);
-      sm4[3] += rint((double)v.w * s1);
+      expo(v.x, amin0, amax0);
+      expo(v.y, amin0, amax0);
+      expo(v.z, amin1, amax1);
+      expo(v.w, amin1, amax1);
+      sm4[0] += (double)v.x;
+      sm4[1] += (double)v.y;
+      sm4[2] += (double)v.z;
+      sm4[3] += (double)v.w;
     });
-  } else {
-    for (int k = 0; k < 4; ++k) sm4[k] = sc4[k];
   }
+  const bool exact0 = amax0 == 0 || (amax0 < 255 && lg + amax0 - amin0 <= 29);
+  const bool exact1 = amax1 == 0 || (amax1 < 255 && lg + amax1 - amin1 <= 29);
+  double s0 = 1.0, s1 = 1.0;
+  if (!(exact0 && exact1)) {
+    // all four sums again: fixed point for the realisation(s) that need it, the plain
+    // (exact) sums for the other
+    if (!exact0) s0 = ldexp(1.0, 177 - min(amax0, 254) - lg);
+    if (!exact1) s1 = ldexp(1.0, 177 - min(amax1, 254) - lg);
+    auto t0 = [&](float x) { return exact0 ? (double)x : rint((double)x * s0); };
+    auto t1 = [&](float x) { return exact1 ? (double)x : rint((double)x * s1); };
+    for (int k = 0; k < 4; ++k) sc4[k] = sm4[k] = 0.0;
+    walk(p0, cd, [&](float4 v) {
+      sc4[0] += t0(v.x);
+      sc4[1] += t0(v.y);
+      sc4[2] += t1(v.z);
+      sc4[3] += t1(v.w);
+    });
+    if (m != c) {
+      walk(q0, cm, [&](float4 v) {
+        sm4[0] += t0(v.x);
+        sm4[1] += t0(v.y);
+        sm4[2] += t1(v.z);
+        sm4[3] += t1(v.w);
+      });
+    }
+  }
+  if (m == c)
+    for (int k = 0; k < 4; ++k) sm4[k] = sc4[k];
   const double i0 = 1.0 / s0, i1 = 1.0 / s1;  // powers of two: exact
   out_c[2 * q][kp] = make_float2((float)((sc4[0] + sm4[0]) * i0), (float)((sc4[1] - sm4[1]) * i0));
   out_c[2 * q + 1][kp] = make_float2((float)((sc4[2] + sm4[2]) * i1), (float)((sc4[3] - sm4[3]) * i1));

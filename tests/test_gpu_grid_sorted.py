@@ -78,9 +78,12 @@ def test_sorted_matches_oracle_and_abs_grid(batch):
         assert bset.kept == len(uv) - dro
 
 
-def test_sorted_is_independent_of_the_order_in_a_cell_and_of_padding():
-    """A second sort (its order inside a cell may differ), slots padded past the kept
-    count, and a plane cut short (only its slots are gridded)."""
+@pytest.mark.parametrize("tiny", [False, True])
+def test_sorted_is_independent_of_the_order_in_a_cell_and_of_padding(tiny):
+    """Every cell's run reversed, a second sort, slots padded past the kept count, and a
+    plane cut short (only its slots are gridded).  With `tiny`, every 53rd visibility is
+    scaled by 1e-12, so that the cells holding one sum values whose magnitudes span more
+    than an FP64 sum keeps exactly (the fixed-point form)."""
     A = _A()
     torch = _torch()
     n = 128
@@ -90,16 +93,25 @@ def test_sorted_is_independent_of_the_order_in_a_cell_and_of_padding():
     cells = rng.integers(-20, 21, (40, 2)).astype(np.float64)
     uv = cells[rng.integers(0, 40, 30000)] + rng.uniform(-0.45, 0.45, (30000, 2))
     vis = (rng.standard_normal((4, 30000)) + 1j * rng.standard_normal((4, 30000))).astype(np.complex64)
+    if tiny:
+        vis[:, ::53] *= np.float32(1e-12)
     uvt, vt = torch.from_numpy(uv).cuda(), torch.from_numpy(vis).cuda()
     s1, s2 = p.grid_sort(uvt), p.grid_sort(uvt)
     _check_set(s2, n, uv)
-    g1 = p.grid_sorted(s1, s1.permute(vt))
+    vs = s1.permute(vt)
+    g1 = p.grid_sorted(s1, vs)
+    # the same slots with every key's run reversed
+    keys = _slot_keys(n, uv)[s1.perm[:s1.kept].cpu().numpy()]
+    rev = np.lexsort((-np.arange(s1.kept), keys))
+    grev = p.grid_sorted(s1, vs[torch.from_numpy(rev).cuda()].contiguous())
     g2 = p.grid_sorted(s2, s2.permute(vt))
     gpad = p.grid_sorted(s1, s1.permute(vt, ld=len(uv)))
     cut = s1.kept // 3
     gcut, wcut = p.grid_sorted(s1, s1.permute(vt, ld=cut), wsum=True)
+    g0, _, _ = p.grid(uvt, vt)
     torch.cuda.synchronize()
-    assert torch.equal(g1, g2) and torch.equal(g1, gpad)
+    assert not np.array_equal(rev, np.arange(s1.kept))
+    assert torch.equal(g1, grev) and torch.equal(g1, g2) and torch.equal(g1, gpad) and torch.equal(g1, g0)
     sel = s1.perm[:cut].cpu().numpy()
     for b in range(4):
         go, wo, _ = ogrid.grid_visibilities(n, 1.0, uv, vis[b])
