@@ -12,6 +12,21 @@
 namespace abs_impl {
 
 constexpr int kBlock = 256;          // threads per workgroup for most kernels here
+
+// Workgroup i of a launch runs on XCD i % 8 (each XCD has its own L2).  xcd_block maps
+// it to a logical block so that every XCD takes runs of kXcdRun consecutive logical
+// blocks, interleaved with the other XCDs' runs: neighbouring blocks that write parts of
+// the same cache lines then do so through one L2.  The grid is padded to a multiple of
+// 8 kXcdRun blocks (xcd_grid); logical blocks past the real count return at once.
+constexpr unsigned kXcds = 8, kXcdRun = 8;
+__device__ __forceinline__ unsigned xcd_block(unsigned bid) {
+  const unsigned grp = bid / (kXcds * kXcdRun), r = bid - grp * (kXcds * kXcdRun);
+  return grp * (kXcds * kXcdRun) + (r % kXcds) * kXcdRun + r / kXcds;
+}
+inline unsigned xcd_grid(long long nblk) {
+  const long long g = (long long)kXcds * kXcdRun;
+  return (unsigned)((nblk + g - 1) / g * g);
+}
 // Threads per column-pass workgroup (f32: FP32 data fields, else FP64 weight fields) and
 // the FFT engine's block, from which the threads per transform follow (Fft<n, engine>):
 // 4096-point columns run two 256-thread transforms in a 512-thread workgroup, so that a

@@ -31,7 +31,14 @@
 namespace abs_impl {
 
 // Threads per row-pass workgroup: 8192-point rows use 512 (one radix-16 butterfly per
-// thread, half the registers of two, so more waves fit a SIMD); others kBlock.
+// thread, half the registers of two, so more waves fit a SIMD); others kBlock.  At 4096
+// and 8192 points a workgroup runs one transform at a time, so the row pairs 2q and 2q + 1,
+// whose inputs share each 32-byte group of the column pass's output, read it in turn and
+// the group comes from memory twice (counters: 18.8 GB read for 9.8 GB written at
+// 8192^2 x 8).  Measured alternatives: two transforms a workgroup read it once but ran
+// slower at 8192 points (1024 threads: row pass 24.2 against 22.3 ms) and were mixed at 4096
+// (512 threads: 9.17 against 8.97 ms at 8192^2 x 8, 2.30 against 2.40 ms at 4096^2 x 16);
+// loading the odd pair's inputs with the even pair's took 30-60 more registers a lane.
 constexpr int row_block(int log2n) { return log2n == 13 ? 512 : kBlock; }
 
 // Row pass with the compile-time engine.  blockIdx.x = ring m * blocks per ring + block,
@@ -263,8 +270,11 @@ colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, i
   TW twr;
   if constexpr (REG) twr.load(tw, t);
   else twr.stage(tw, reinterpret_cast<T*>(lds_raw) + CG * FF::L, threadIdx.x, CB);   // the loop's first barrier publishes it
+  // consecutive tiles (neighbouring columns of a ring, whose outputs share cache lines) in
+  // runs on one XCD
+  const int bx = (int)xcd_block(blockIdx.x);
   for (int it = 0; it < tpb; ++it) {
-    const int ti = blockIdx.x * tpb + it;
+    const int ti = bx * tpb + it;
     if (ti >= ntiles) break;   // the same for the whole block
     const ColTile tile = tiles[ti];
     const BinDev bin = bins[tile.m];
@@ -359,7 +369,7 @@ hipError_t launch_colpass_n(const abs_plan_s* p, int nsets, const typename HermT
   if (ntiles == 0) return hipSuccess;
   if ((F32 ? p->ct : p->ct64) != col_transforms<R, LOG2N>()) return hipErrorInvalidValue;
   constexpr int tpb = col_tiles_per_block(LOG2N);
-  const dim3 grid((unsigned)((ntiles + tpb - 1) / tpb), (unsigned)nsets);
+  const dim3 grid(xcd_grid((ntiles + tpb - 1) / tpb), (unsigned)nsets);
   const size_t lds = (size_t)col_transforms<R, LOG2N>() * FF::L * sizeof(typename Cx<R>::T) +
                      (col_tw_reg<R, LOG2N>() ? 0 : TwiddlesSplit<R, LOG2N, EB>::ENTRIES * sizeof(typename Cx<R>::T));
   auto k = colpass_fixed_kernel<R, LOG2N>;
