@@ -35,7 +35,8 @@ namespace abs_impl {
 // and 8192 points a workgroup runs one transform at a time, so the row pairs 2q and 2q + 1,
 // whose inputs share each 32-byte group of the column pass's output, read it in turn and
 // the group comes from memory twice (counters: 18.8 GB read for 9.8 GB written at
-// 8192^2 x 8).  Measured alternatives: two transforms a workgroup read it once but ran
+// 8192^2 x 8; the field stores below are non-temporal, which keeps most of those lines
+// for the second read).  Measured alternatives: two transforms a workgroup read it once but ran
 // slower at 8192 points (1024 threads: row pass 24.2 against 22.3 ms) and were mixed at 4096
 // (512 threads: 9.17 against 8.97 ms at 8192^2 x 8, 2.30 against 2.40 ms at 4096^2 x 16);
 // loading the odd pair's inputs with the even pair's took 30-60 more registers a lane.
@@ -111,9 +112,12 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
     };
     R* __restrict__ row0 = fs + (o0 >= 0 ? o0 : 0);
     R* __restrict__ row1 = fs + (o1 >= 0 ? o1 : 0);
+    // The fields are stored non-temporally: streamed past the L2, they no longer evict the
+    // column-pass lines whose other half the next row pair reads (8192^2 x 8: reads 18.8 ->
+    // 10.6 GB at 8192 points, 16.8 -> 11.6 GB at 4096; row pass 0.8 ms faster a step).
     auto out = [&](int k, int, int, T v) {
-      if (o0 >= 0) row0[k] = v.x;
-      if (o1 >= 0) row1[k] = v.y;
+      if (o0 >= 0) __builtin_nontemporal_store(v.x, &row0[k]);
+      if (o1 >= 0) __builtin_nontemporal_store(v.y, &row1[k]);
       if constexpr (FMAX)
         if (active) vmax = fmax(vmax, fmax(fabs(v.x), fabs(v.y)));
     };
