@@ -182,29 +182,62 @@ struct Twiddles<R, LOG2N, true, BLOCK> {
   }
 };
 
-// Twiddles from a two-level table in LDS (row passes, and column passes whose threads need
-// more twiddles than registers hold): w^a = hi[a / LO] lo[a % LO] with lo[c] = w^c (c < LO = min(64, N)) and
-// hi[b] = w^(LO b) (b < N / LO), both copied from the plan's table, so one complex
-// product (about one rounding more than the table entry) replaces a load from memory.
+// Twiddles from LDS tables (row passes, and column passes whose threads need more twiddles
+// than registers hold).  Pass 1, when it is radix 16, reads its twiddles straight from a
+// 16 x 15 table: thread t's butterflies there have m = t mod 16, so entry [m][r - 1] is
+// w^(r m 2^SH1) and the 15 reads of a butterfly take one base address and immediate
+// offsets, with no index arithmetic or product.  Pass 2, when it is radix 16 too and a
+// transform has a multiple of 256 threads, has m = t mod 256 = m0 + 16 m1, and its twiddle
+// w^(r m 2^SH2) (SH2 = SH1 - 4) is the product of w^(r m0 2^SH2), from a second 16 x 15
+// table, and w^(r m1 2^SH1), from the first.  (These tables take an 8192-point row transform
+// from 1362 to 1180 VALU instructions, the FFT passes being bound by VALU issue.)  Later
+// passes use a two-level table:
+// w^a = hi[a / LO] lo[a % LO] with lo[c] = w^c (c < LO = min(64, N)) and hi[b] = w^(LO b)
+// (b < N / LO), so one complex product (about one rounding more than the table entry)
+// replaces a load from memory.  All tables are copied from the plan's natural-order table.
 template <typename R, int LOG2N, int BLOCK = kBlock>
 struct TwiddlesSplit {
   using T = typename Cx<R>::T;
   using F = Fft<LOG2N, BLOCK>;
   static constexpr int LLO = LOG2N < 6 ? LOG2N : 6, LO = 1 << LLO;
-  static constexpr int ENTRIES = LO + F::N / LO;
-  const T* lo;   // LDS: lo[LO] then hi[N / LO]
-  // Copies the two tables from the natural-order table tw (N entries) into LDS at dst;
-  // the caller synchronises the block before the first get.
+  // pass 1 direct: radix 16 there, and m = (t + TG j) mod 16 = t mod 16 (TG a multiple of 16)
+  static constexpr bool P1 = F::NPASS > 1 && F::lrp(1) == 4 && F::TG % 16 == 0;
+  static constexpr bool P2 = P1 && F::NPASS > 2 && F::lrp(2) == 4 && F::TG % 256 == 0;
+  static constexpr int SH1 = LOG2N - 8;
+  static constexpr int N1 = P1 ? 16 * 15 : 0, N2 = P2 ? 16 * 15 : 0;
+  static constexpr int T1 = LO + F::N / LO, T2 = T1 + N1;   // offsets of the two tables
+  static constexpr int ENTRIES = T2 + N2;
+  const T* lo;   // LDS: lo[LO], hi[N / LO], then the pass-1 and pass-2 tables
+  // Copies the tables from the natural-order table tw (N entries) into LDS at dst; the
+  // caller synchronises the block before the first get.
   __device__ __forceinline__ void stage(const T* __restrict__ tw, T* dst, int tid, int nthreads) {
-    for (int e = tid; e < ENTRIES; e += nthreads) dst[e] = tw[e < LO ? e : (e - LO) * LO];
+    for (int e = tid; e < ENTRIES; e += nthreads) {
+      int src;
+      if (e < LO) {
+        src = e;
+      } else if (e < T1) {
+        src = (e - LO) * LO;
+      } else {
+        const int b = e < T2 ? T1 : T2;   // pass-1 table: 2^SH1 steps; pass-2 table: 2^(SH1 - 4)
+        const int m = (e - b) / 15, r = (e - b) - 15 * m + 1;
+        src = e < T2 ? (r * m) << (P1 ? SH1 : 0) : (r * m) << (P2 ? SH1 - 4 : 0);
+      }
+      dst[e] = tw[src];
+    }
     lo = dst;
   }
   template <int P>
   __device__ __forceinline__ T get(const T* __restrict__, int t, int j, int r) const {
     constexpr int LRP = F::lrp(P), LNS = 4 * P, SH = LOG2N - LNS - LRP;
-    const int m = (t + F::TG * j) & ((1 << LNS) - 1);
-    const int a = (r * m) << SH;   // < N
-    return cmul(lo[LO + (a >> LLO)], lo[a & (LO - 1)]);
+    if constexpr (P == 1 && P1) {
+      return lo[T1 + 15 * (t & 15) + r - 1];
+    } else if constexpr (P == 2 && P2) {
+      return cmul(lo[T2 + 15 * (t & 15) + r - 1], lo[T1 + 15 * ((t >> 4) & 15) + r - 1]);
+    } else {
+      const int m = (t + F::TG * j) & ((1 << LNS) - 1);
+      const int a = (r * m) << SH;   // < N
+      return cmul(lo[LO + (a >> LLO)], lo[a & (LO - 1)]);
+    }
   }
 };
 
