@@ -50,7 +50,8 @@ struct ColTile {
 
 // Per-ring constants on the device.
 struct BinDev {
-  double lo2, hi2;    // squared edges, compared against the exact integer |g|^2
+  int32_t d2lo, d2hi; // a cell is in the ring when d2lo <= |g|^2 < d2hi (the squared edges
+                      // lo2 <= |g|^2 < hi2 rounded up: |g|^2 is an integer)
   int32_t h;          // largest |gx| of any cell of the ring (columns 0..h are used)
   int32_t cols;       // h + 1, or 0 for a ring without lattice cells
   int64_t zoff;       // offset (complex elements) of the ring's column-pass output in one set

@@ -334,8 +334,11 @@ abs_status bind_tables(abs_plan_s* p, void* mem, hipStream_t st) {
   }
   BinDev* bins = reinterpret_cast<BinDev*>(img.data() + p->dl.bins);
   for (int m = 0; m < p->nb; ++m) {
-    bins[m].lo2 = p->lo2[m];
-    bins[m].hi2 = p->hi2[m];
+    // integer bounds: for an integer d, d >= x exactly when d >= ceil(x), and d < x
+    // exactly when d < ceil(x)
+    auto ibound = [](double x) { return (int32_t)std::min(std::max(std::ceil(x), 0.0), 2147483647.0); };
+    bins[m].d2lo = ibound(p->lo2[m]);
+    bins[m].d2hi = ibound(p->hi2[m]);
     bins[m].h = p->h[m];
     bins[m].cols = p->cols[m];
     bins[m].zoff = p->zoff[m];

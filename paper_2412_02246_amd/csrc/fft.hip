@@ -58,9 +58,10 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
   using FF = Fft<LOG2N, RB>;
   constexpr int n = FF::N;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const int g = threadIdx.x / FF::TG, t = threadIdx.x - g * FF::TG;
+  // g = 0 spelled out for one transform a workgroup, so the row offsets stay scalar
+  const int g = FF::G == 1 ? 0 : (int)threadIdx.x / FF::TG, t = threadIdx.x - g * FF::TG;
   T* buf = reinterpret_cast<T*>(lds_raw) + g * FF::L;
-  // The two-level twiddle table sits in LDS after the FFT buffers: at most 1.5 KB instead
+  // The twiddle tables sit in LDS after the FFT buffers: at most 5.4 KB (FP32) instead
   // of the full table (8 or 16 bytes per point), so more blocks fit a CU.
   TwiddlesSplit<R, LOG2N, RB> twr;
   twr.stage(tw, reinterpret_cast<T*>(lds_raw) + FF::G * FF::L, threadIdx.x, RB);
@@ -110,14 +111,19 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
       }
       return x;
     };
+    // One transform a workgroup (G = 1): `active` is the same for the whole workgroup, so an
+    // inactive iteration is skipped (no barrier is left half taken) and, for full fields,
+    // every row of an active pair is kept: the stores need no per-store test.
+    constexpr bool UNIFORM = FF::G == 1 && !HALF;
+    if (UNIFORM && !active) continue;
     R* __restrict__ row0 = fs + (o0 >= 0 ? o0 : 0);
     R* __restrict__ row1 = fs + (o1 >= 0 ? o1 : 0);
     // The fields are stored non-temporally: streamed past the L2, they no longer evict the
     // column-pass lines whose other half the next row pair reads (8192^2 x 8: reads 18.8 ->
     // 10.6 GB at 8192 points, 16.8 -> 11.6 GB at 4096; row pass 0.8 ms faster a step).
     auto out = [&](int k, int, int, T v) {
-      if (o0 >= 0) __builtin_nontemporal_store(v.x, &row0[k]);
-      if (o1 >= 0) __builtin_nontemporal_store(v.y, &row1[k]);
+      if (UNIFORM || o0 >= 0) __builtin_nontemporal_store(v.x, &row0[k]);
+      if (UNIFORM || o1 >= 0) __builtin_nontemporal_store(v.y, &row1[k]);
       if constexpr (FMAX)
         if (active) vmax = fmax(vmax, fmax(fabs(v.x), fabs(v.y)));
     };
@@ -127,6 +133,7 @@ rowpass_fixed_kernel(int iters, const BinDev* __restrict__ bins, const typename 
     // registers across the loop.
     int tl = t;
     asm volatile("" : "+v"(tl));
+    __builtin_assume(tl >= 0 && tl < FF::TG);   // its range survives the hiding
     fft_passes<R, LOG2N, 0, RB>(buf, tl, tw, twr, in, out);
   }
   if constexpr (FMAX) {
@@ -285,17 +292,20 @@ colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, i
     const bool active = g < tile.ncols;
     const int gx = tile.gx0 + (active ? g : 0);
     const int H = bin.h, cols = bin.cols;
-    const double lo2 = bin.lo2, hi2 = bin.hi2;
-    const auto* __restrict__ col = xc + ((long long)set * (hm + 1) + gx) * lc + hm;   // col[gy]
+    const int d2lo = bin.d2lo, d2hi = bin.d2hi;
+    // column gx of the Hermitian part: cell gy at col0[gy + hm] (a non-negative 32-bit index)
+    const auto* __restrict__ col0 = xc + ((long long)set * (hm + 1) + gx) * lc;
     auto in = [&](int k, int, int r) -> T {
       T x = Cx<R>::mk(R(0), R(0));
       if (active && (r * S <= H || (r + 1) * S - 1 >= n - H)) {
         const int gy = k <= H ? k : k - n;
         if (k <= H || k >= n - H) {
-          const double d2 = (double)((long long)gx * gx + (long long)gy * gy);
-          if (d2 >= lo2 && d2 < hi2) {
-            if constexpr (DATA) x = col[gy];
-            else x = Cx<R>::mk(col[gy], R(0));
+          // |g| <= n/2 in each component: 24-bit products (full-rate multiplies), 32-bit sum
+          const int d2 = __mul24(gx, gx) + __mul24(gy, gy);
+          if (d2 >= d2lo && d2 < d2hi) {
+            const unsigned iy = (unsigned)(gy + hm);
+            if constexpr (DATA) x = col0[iy];
+            else x = Cx<R>::mk(col0[iy], R(0));
           }
         }
       }
