@@ -565,7 +565,7 @@ def _dtype(precision):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build measures one GPU only (--gpus 1); %d GPUs is not supported"
+        print("bench.py: measures one GPU only (--gpus 1); %d GPUs is not supported"
               % a.gpus, file=sys.stderr)
         sys.exit(2)
     if a.workload == "serve":
