@@ -35,8 +35,10 @@ inline unsigned xcd_grid(long long nblk) {
 // do FP32 8192-point columns, 256 threads a transform with two butterflies each, in 141 KB
 // of LDS (8.7 -> 5.6 ms at 8192^2 x 8); FP64 8192-point columns (278 KB for two) keep one
 // transform a workgroup; others kBlock (four 2048-point transforms in 512 threads: no gain).  The host's column tiles hold as many columns as one workgroup transforms at once.
-constexpr int col_block(int log2n, bool f32) { return log2n == 12 || (log2n == 13 && f32) ? 512 : kBlock; }
-constexpr int col_engine(int log2n) { return log2n == 12 ? 512 : kBlock; }
+// FP64 8192-point columns take 512 threads a transform (one butterfly each): the LDS of one
+// transform (139 KB) leaves one workgroup per CU, so this doubles its waves.
+constexpr int col_block(int log2n, bool f32) { return log2n == 12 || log2n == 13 ? 512 : kBlock; }
+constexpr int col_engine(int log2n, bool f32) { return log2n == 12 || (log2n == 13 && !f32) ? 512 : kBlock; }
 constexpr int kMaxBins = 64;
 constexpr int kTilesPerWave = 12;    // MFMA output tiles owned by one wave (precision form)
 constexpr int kSmallTilesPerWave = 2;   // the same for small plans (kernel variant)

@@ -254,11 +254,11 @@ herm_kernel(const GT* __restrict__ grids, const float* __restrict__ w, int w_bat
 // Column-pass twiddles: held in registers when a thread needs few (FP32), otherwise the
 // two-level LDS table.
 template <typename R, int LOG2N>
-constexpr bool col_tw_reg() { return sizeof(R) == 4 && Fft<LOG2N, col_engine(LOG2N)>::NTW <= 32; }
+constexpr bool col_tw_reg() { return sizeof(R) == 4 && Fft<LOG2N, col_engine(LOG2N, true)>::NTW <= 32; }
 
 // Transforms per column-pass workgroup (the columns of one tile).
 template <typename R, int LOG2N>
-constexpr int col_transforms() { return col_block(LOG2N, sizeof(R) == 4) / Fft<LOG2N, col_engine(LOG2N)>::TG; }
+constexpr int col_transforms() { return col_block(LOG2N, sizeof(R) == 4) / Fft<LOG2N, col_engine(LOG2N, sizeof(R) == 4)>::TG; }
 
 template <typename R, int LOG2N>
 __global__ void __launch_bounds__(col_block(LOG2N, sizeof(R) == 4))
@@ -267,7 +267,7 @@ colpass_fixed_kernel(const typename HermT<sizeof(R) == 4>::T* __restrict__ xc, i
                      const BinDev* __restrict__ bins, const typename Cx<R>::T* __restrict__ tw,
                      typename Cx<R>::T* __restrict__ Z, long long zset) {
   using T = typename Cx<R>::T;
-  constexpr int CB = col_block(LOG2N, sizeof(R) == 4), EB = col_engine(LOG2N);
+  constexpr int CB = col_block(LOG2N, sizeof(R) == 4), EB = col_engine(LOG2N, sizeof(R) == 4);
   using FF = Fft<LOG2N, EB>;
   constexpr int CG = col_transforms<R, LOG2N>();   // transforms (columns) per workgroup
   constexpr int n = FF::N, S = n / 16;
@@ -374,7 +374,7 @@ hipError_t launch_colpass_n(const abs_plan_s* p, int nsets, const typename HermT
                             typename Cx<R>::T* Z, long long zset, const typename Cx<R>::T* tw,
                             hipStream_t st) {
   constexpr bool F32 = sizeof(R) == 4;
-  constexpr int CB = col_block(LOG2N, F32), EB = col_engine(LOG2N);
+  constexpr int CB = col_block(LOG2N, F32), EB = col_engine(LOG2N, F32);
   using FF = Fft<LOG2N, EB>;
   const char* base = static_cast<const char*>(p->dev);
   const BinDev* bins = reinterpret_cast<const BinDev*>(base + p->dl.bins);

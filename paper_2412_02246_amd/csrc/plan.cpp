@@ -858,10 +858,13 @@ bool setup_kernels(abs_plan_s* p) {
   // of one ring at once, one transform per TG threads (n/16, or n/32 when n/16 exceeds the
   // engine's block: two butterflies a thread)
   {
-    const int eb = col_engine(p->log2n), n16 = std::max(1, n / 16);
-    const int tg = std::min(n16 > eb ? n16 / 2 : n16, eb);
-    p->ct = col_block(p->log2n, true) / tg;
-    p->ct64 = col_block(p->log2n, false) / tg;
+    const int n16 = std::max(1, n / 16);
+    auto tg = [&](bool f32) {
+      const int eb = col_engine(p->log2n, f32);
+      return std::min(n16 > eb ? n16 / 2 : n16, eb);
+    };
+    p->ct = col_block(p->log2n, true) / tg(true);
+    p->ct64 = col_block(p->log2n, false) / tg(false);
   }
   p->tiles.clear();
   p->tiles64.clear();
