@@ -32,13 +32,14 @@ inline unsigned xcd_grid(long long nblk) {
 // 4096-point columns run two 256-thread transforms in a 512-thread workgroup, so that a
 // tile's outputs leave in 64-byte runs instead of 32 (4.7 -> 2.6 ms at 4096^2 x 16; four
 // transforms in 1024 threads measured slower, 1.39 against 1.08 ms at 4096^2 x 16), and so
-// do FP32 8192-point columns, 256 threads a transform with two butterflies each, in 141 KB
-// of LDS (8.7 -> 5.6 ms at 8192^2 x 8); FP64 8192-point columns (278 KB for two) keep one
-// transform a workgroup; others kBlock (four 2048-point transforms in 512 threads: no gain).  The host's column tiles hold as many columns as one workgroup transforms at once.
-// FP64 8192-point columns take 512 threads a transform (one butterfly each): the LDS of one
-// transform (139 KB) leaves one workgroup per CU, so this doubles its waves.
-constexpr int col_block(int log2n, bool f32) { return log2n == 12 || log2n == 13 ? 512 : kBlock; }
-constexpr int col_engine(int log2n, bool f32) { return log2n == 12 || (log2n == 13 && !f32) ? 512 : kBlock; }
+// do FP32 8192-point columns, two transforms in 141 KB of LDS (8.7 -> 5.6 ms at 8192^2 x 8;
+// one transform a workgroup, 32-byte runs: 7.6 ms).  8192-point transforms take 512 threads
+// (one butterfly each): their LDS leaves one workgroup per CU, so this doubles its waves
+// (FP32, 1024 threads: 5.22 -> 4.90 ms at 8192^2 x 8; FP64, one transform in 512 threads:
+// 1.29 -> 1.12 ms).  Others kBlock (four 2048-point transforms in 512 threads: no gain).
+// The host's column tiles hold as many columns as one workgroup transforms at once.
+constexpr int col_block(int log2n, bool f32) { return log2n == 13 && f32 ? 1024 : log2n == 12 || log2n == 13 ? 512 : kBlock; }
+constexpr int col_engine(int log2n, bool f32) { (void)f32; return log2n == 12 || log2n == 13 ? 512 : kBlock; }
 constexpr int kMaxBins = 64;
 constexpr int kTilesPerWave = 12;    // MFMA output tiles owned by one wave (precision form)
 constexpr int kSmallTilesPerWave = 2;   // the same for small plans (kernel variant)
