@@ -463,21 +463,21 @@ grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ so
   const long long terms = (long long)cd + cm;
   int lg = 0;
   while ((1ll << lg) < (terms > 0 ? terms : 1)) ++lg;
-  int amin0 = 255, amax0 = 0, amin1 = 255, amax1 = 0;
-  auto expo = [](float x, int& amin, int& amax) {
+  // the largest and smallest non-zero |x| of each realisation, as their bit patterns (which
+  // order like the magnitudes); u - 1 sends a zero to the largest unsigned value, out of the
+  // minimum
+  unsigned umin0 = ~0u, umax0 = 0u, umin1 = ~0u, umax1 = 0u;
+  auto expo = [](float x, unsigned& umin, unsigned& umax) {
     const unsigned u = __float_as_uint(x) & 0x7fffffffu;
-    if (u) {
-      const int a = max((int)(u >> 23), 1);
-      amin = min(amin, a);
-      amax = max(amax, a);
-    }
+    umax = max(umax, u);
+    umin = min(umin, u - 1u);
   };
   double sc4[4] = {0.0, 0.0, 0.0, 0.0}, sm4[4] = {0.0, 0.0, 0.0, 0.0};
   walk(p0, cd, [&](float4 v) {
-    expo(v.x, amin0, amax0);
-    expo(v.y, amin0, amax0);
-    expo(v.z, amin1, amax1);
-    expo(v.w, amin1, amax1);
+    expo(v.x, umin0, umax0);
+    expo(v.y, umin0, umax0);
+    expo(v.z, umin1, umax1);
+    expo(v.w, umin1, umax1);
     sc4[0] += (double)v.x;
     sc4[1] += (double)v.y;
     sc4[2] += (double)v.z;
@@ -485,16 +485,20 @@ grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ so
   });
   if (m != c) {
     walk(q0, cm, [&](float4 v) {
-      expo(v.x, amin0, amax0);
-      expo(v.y, amin0, amax0);
-      expo(v.z, amin1, amax1);
-      expo(v.w, amin1, amax1);
+      expo(v.x, umin0, umax0);
+      expo(v.y, umin0, umax0);
+      expo(v.z, umin1, umax1);
+      expo(v.w, umin1, umax1);
       sm4[0] += (double)v.x;
       sm4[1] += (double)v.y;
       sm4[2] += (double)v.z;
       sm4[3] += (double)v.w;
     });
   }
+  // a = max(exponent field, 1) of the largest and the smallest of them (0 / 255 when none)
+  const int amax0 = umax0 ? max((int)(umax0 >> 23), 1) : 0, amax1 = umax1 ? max((int)(umax1 >> 23), 1) : 0;
+  const int amin0 = umin0 != ~0u ? max((int)((umin0 + 1u) >> 23), 1) : 255;
+  const int amin1 = umin1 != ~0u ? max((int)((umin1 + 1u) >> 23), 1) : 255;
   const bool exact0 = amax0 == 0 || (amax0 < 255 && lg + amax0 - amin0 <= 29);
   const bool exact1 = amax1 == 0 || (amax1 < 255 && lg + amax1 - amin1 <= 29);
   double s0 = 1.0, s1 = 1.0;
