@@ -114,6 +114,16 @@ def test_workspace_sizes():
     assert (1 << 20) * (4 + 4 + 4 + 16) + 2 * n * n * 4 <= g < (1 << 20) * 28 + 2 * n * n * 4 + 8192
     with pytest.raises(A.AbsError):
         p.estimate_workspace(5)
+    # a sorted baseline set: the run table, (n/2 + 1) n pairs x 2 sides + 1 int32 entries;
+    # the sort's scratch: per baseline its key and rank, per key a count, plus the scan tiles
+    import ctypes
+    from paper_2412_02246_amd import _lib as L
+    sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.lib().abs_grid_sort_workspace(p.handle, 1 << 20, ctypes.byref(sb), ctypes.byref(wb)) == 0
+    keys = 2 * (n // 2 + 1) * n
+    assert sb.value == (keys + 1) * 4
+    assert (1 << 20) * 8 + keys * 4 <= wb.value < (1 << 20) * 8 + keys * 4 + 65536
+    assert L.lib().abs_grid_sort_workspace(p.handle, -1, ctypes.byref(sb), None) != 0
 
 
 def test_jit_parts_code_roundtrip_and_parallel_compile():
