@@ -12,7 +12,7 @@ gridding call (abs_grid, which sorts on every call) are timed once and reported 
 "baseline_set".
 
 The default line is the large-ensemble shapes (8192^2 grids, 64 log rings, 15,229
-triplets, realisations in batches of 8) in the plain FP32 form; it also carries, as
+triplets, realisations in batches of 16) in the plain FP32 form; it also carries, as
 extra keys, the same workload in the BF16x3 and FP16x3 precision forms, the 1024^2 / 20-ring
 single-channel workload, and the serving form's saturated rate and latencies.
 
@@ -41,10 +41,11 @@ WORKLOADS = {
     "mwa4096": dict(n=4096, nbins=32, lmin=4 * 46.0, lmax=4 * 1320.0, batch=16, cfg=2,
                     desc="MWA-shaped 4096x4096 c64 grids, 32 log rings 4x(46<=l<1320), INV_COUNT weights, "
                          "16 realisations a step"),
-    # large ensemble shapes: 8192^2, 64 log rings, edges x8 (realisations in batches of 8)
-    "mwa8192": dict(n=8192, nbins=64, lmin=8 * 46.0, lmax=8 * 1320.0, batch=8, cfg=4,
+    # large ensemble shapes: 8192^2, 64 log rings, edges x8 (realisations in batches of 16:
+    # about 195 GiB of estimator workspace, which amortises the weight fields over 16 grids)
+    "mwa8192": dict(n=8192, nbins=64, lmin=8 * 46.0, lmax=8 * 1320.0, batch=16, cfg=4,
                     desc="large ensemble: 8192x8192 c64 grids, 64 log rings 8x(46<=l<1320) (15229 triplets), "
-                         "realisations of one channel, 8 a step, INV_COUNT weights from the gridded counts"),
+                         "realisations of one channel, 16 a step, INV_COUNT weights from the gridded counts"),
     # multi-frequency form: 4 channels of the 1024^2 channel's geometry, 16 log rings; each
     # step grids and estimates 4 multi-frequency grids (16 channel grids), every channel
     # triplet (ring triplet x channel combination)
@@ -96,7 +97,7 @@ PEAK_HBM = 8.0e12
 # HBM bytes per launch of the timed contraction kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by a 1 GiB copy (2.0 x FETCH_SIZE + 1.0 x WRITE_SIZE), for the
 # kernels as they stand in this tree and the workload's default batch, summed over the level launches
-# (profiles/counters_mwa8192_batch8.md, profiles/counters_mwa4096_batch16.md); keyed by
+# (profiles/counters_mwa8192_batch16.md, profiles/counters_mwa4096_batch16.md); keyed by
 # (workload, precision).  A workload or precision without an entry reports null.
 MEASURED_TRAFFIC = {("mwa8192", "fp32"): 86.66e9, ("mwa4096", "fp32"): 19.07e9}
 

@@ -386,12 +386,17 @@ __device__ __forceinline__ PairCell<LPC> pair_cell(long long lc, int n) {
 // true: `start` is a sorted baseline set's table (runs by pair: entry 2 lc, the visibilities
 // nearest to g, then from entry 2 lc + 1 those nearest to -g), and records from `ld` on are
 // not read.
+// Threads a block of the pair gather: with 8 lanes a pair, 512 (64 pairs a block) keep the
+// runs each realisation plane receives at 64 cells (and 64 mirror cells).
+constexpr int pair_threads(int lpc) { return lpc == 8 ? 512 : kBlock; }
+
 template <int LPC, bool VEC, bool KEYED>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(pair_threads(LPC))
 grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ sorted,
                          const int* __restrict__ start, long long ld, float2* __restrict__ grid,
                          float* __restrict__ wsum) {
-  constexpr int PB = kBlock / LPC;   // pairs per block
+  constexpr int NTH = pair_threads(LPC);
+  constexpr int PB = NTH / LPC;   // pairs per block
   __shared__ float2 out_c[2 * LPC][PB + 1], out_m[2 * LPC][PB + 1];   // padded: rows 2q start in different banks
   const long long nn = (long long)n * n;
   const int half = n / 2;
@@ -538,7 +543,7 @@ grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ so
   }
   __syncthreads();
   // plane r of the pass, pair k: consecutive threads take consecutive pairs
-  for (int e = threadIdx.x; e < 2 * LPC * PB; e += kBlock) {
+  for (int e = threadIdx.x; e < 2 * LPC * PB; e += NTH) {
     const int r = e / PB, k = e - r * PB;
     if (b0 + r >= batch) continue;
     const PairCell<LPC> w = pair_cell<LPC>((long long)blockIdx.x * PB + k, n);
@@ -588,10 +593,11 @@ grid_permute_kernel(long long nvis, int batch, const int* __restrict__ perm, lon
 // abs_grid picks them); batch = 0 writes only the counts.
 void launch_keyed_pairs(int n, int batch, int b0, int lpc, const float2* rec, const int* start, long long ld,
                         float2* grid, float* wsum, hipStream_t st) {
-  const unsigned gp = (unsigned)((pair_count(n) * lpc + kBlock - 1) / kBlock);
+  const int nth = pair_threads(lpc);
+  const unsigned gp = (unsigned)((pair_count(n) * lpc + nth - 1) / nth);
   const bool vec = (batch & 1) == 0;
 #define ABS_KPAIRS(LL, VV) \
-  grid_gather_pairs_kernel<LL, VV, true><<<gp, kBlock, 0, st>>>(n, batch, b0, rec, start, ld, grid, wsum)
+  grid_gather_pairs_kernel<LL, VV, true><<<gp, nth, 0, st>>>(n, batch, b0, rec, start, ld, grid, wsum)
   switch (lpc * 2 + (vec ? 1 : 0)) {
     case 2: ABS_KPAIRS(1, false); break;
     case 3: ABS_KPAIRS(1, true); break;
@@ -743,9 +749,10 @@ extern "C" abs_status abs_grid(abs_plan_t p, int64_t nvis, int32_t batch, const 
       if (vec) { ABS_GATHER_L(0, true) } else { ABS_GATHER_L(0, false) }
     } else {
       // unit weights: one lane group per mirror pair of cells
-      const unsigned gp = (unsigned)(((long long)(p->n / 2 + 1) * p->n * lpc + kBlock - 1) / kBlock);
+      const int nth = pair_threads(lpc);
+      const unsigned gp = (unsigned)(((long long)(p->n / 2 + 1) * p->n * lpc + nth - 1) / nth);
 #define ABS_PAIRS(LL, VV)                                                                           \
-  grid_gather_pairs_kernel<LL, VV, false><<<gp, kBlock, 0, st>>>(p->n, batch, b0, sorted, start, 0, g2, wsum)
+  grid_gather_pairs_kernel<LL, VV, false><<<gp, nth, 0, st>>>(p->n, batch, b0, sorted, start, 0, g2, wsum)
       switch (lpc * 2 + (vec ? 1 : 0)) {
         case 2: ABS_PAIRS(1, false); break;
         case 3: ABS_PAIRS(1, true); break;

@@ -154,13 +154,13 @@ def test_sorted_argument_checks():
 
 
 def test_sorted_full_size_8192():
-    """8192^2 grid, 8192^2 MWA-shaped baselines, 8 realisations (the throughput workload's
-    launch): every cell bit for bit against abs_grid, and 64 cells (dense short baselines,
+    """8192^2 grid, 8192^2 MWA-shaped baselines, 16 realisations (the throughput workload's
+    launch: 8 lanes a pair, 512-thread blocks): every cell bit for bit against abs_grid, and 64 cells (dense short baselines,
     the band edges, both sides of the half plane) against the oracle over the visibilities
     that reach them."""
     A = _A()
     torch = _torch()
-    n, batch = 8192, 8
+    n, batch = 8192, 16
     e = oplan.log_edges(8 * 46 / (2 * np.pi), 8 * 1320 / (2 * np.pi), 64)
     # gridding uses only the plan's n, du and max_batch: a few rings keep its bind cheap
     p = A.Plan(n, e[:5], wmode=A.W_INV_COUNT, max_batch=batch, levels=1).bind()
