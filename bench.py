@@ -99,7 +99,7 @@ PEAK_HBM = 8.0e12
 # kernels as they stand in this tree and the workload's default batch, summed over the level launches
 # (profiles/counters_mwa8192_batch16.md, profiles/counters_mwa4096_batch16.md); keyed by
 # (workload, precision).  A workload or precision without an entry reports null.
-MEASURED_TRAFFIC = {("mwa8192", "fp32"): 86.66e9, ("mwa4096", "fp32"): 19.07e9}
+MEASURED_TRAFFIC = {("mwa8192", "fp32"): 167.92e9, ("mwa4096", "fp32"): 19.07e9}
 
 
 def edges_of(W):

@@ -386,16 +386,17 @@ __device__ __forceinline__ PairCell<LPC> pair_cell(long long lc, int n) {
 // true: `start` is a sorted baseline set's table (runs by pair: entry 2 lc, the visibilities
 // nearest to g, then from entry 2 lc + 1 those nearest to -g), and records from `ld` on are
 // not read.
-// Threads a block of the pair gather: with 8 lanes a pair, 512 (64 pairs a block) keep the
-// runs each realisation plane receives at 64 cells (and 64 mirror cells).
-constexpr int pair_threads(int lpc) { return lpc == 8 ? 512 : kBlock; }
+// Threads a block of the pair gather: kBlock, or 512 with 8 lanes a pair on grids of 8192^2
+// and more, where runs of 64 cells a realisation plane (not 32) write faster (16
+// realisations of 8192^2: 4.75 against 5.41 ms; at 4096^2 the 256-thread blocks are faster,
+// 1.07 against 1.25 ms).
+int pair_threads(int n, int lpc) { return lpc == 8 && n >= 8192 ? 512 : kBlock; }
 
-template <int LPC, bool VEC, bool KEYED>
-__global__ void __launch_bounds__(pair_threads(LPC))
+template <int LPC, bool VEC, bool KEYED, int NTH>
+__global__ void __launch_bounds__(NTH)
 grid_gather_pairs_kernel(int n, int batch, int b0, const float2* __restrict__ sorted,
                          const int* __restrict__ start, long long ld, float2* __restrict__ grid,
                          float* __restrict__ wsum) {
-  constexpr int NTH = pair_threads(LPC);
   constexpr int PB = NTH / LPC;   // pairs per block
   __shared__ float2 out_c[2 * LPC][PB + 1], out_m[2 * LPC][PB + 1];   // padded: rows 2q start in different banks
   const long long nn = (long long)n * n;
@@ -593,11 +594,12 @@ grid_permute_kernel(long long nvis, int batch, const int* __restrict__ perm, lon
 // abs_grid picks them); batch = 0 writes only the counts.
 void launch_keyed_pairs(int n, int batch, int b0, int lpc, const float2* rec, const int* start, long long ld,
                         float2* grid, float* wsum, hipStream_t st) {
-  const int nth = pair_threads(lpc);
+  const int nth = pair_threads(n, lpc);
   const unsigned gp = (unsigned)((pair_count(n) * lpc + nth - 1) / nth);
   const bool vec = (batch & 1) == 0;
-#define ABS_KPAIRS(LL, VV) \
-  grid_gather_pairs_kernel<LL, VV, true><<<gp, nth, 0, st>>>(n, batch, b0, rec, start, ld, grid, wsum)
+#define ABS_KPAIRS_T(LL, VV, TT) \
+  grid_gather_pairs_kernel<LL, VV, true, TT><<<gp, TT, 0, st>>>(n, batch, b0, rec, start, ld, grid, wsum)
+#define ABS_KPAIRS(LL, VV) ABS_KPAIRS_T(LL, VV, kBlock)
   switch (lpc * 2 + (vec ? 1 : 0)) {
     case 2: ABS_KPAIRS(1, false); break;
     case 3: ABS_KPAIRS(1, true); break;
@@ -605,10 +607,11 @@ void launch_keyed_pairs(int n, int batch, int b0, int lpc, const float2* rec, co
     case 5: ABS_KPAIRS(2, true); break;
     case 8: ABS_KPAIRS(4, false); break;
     case 9: ABS_KPAIRS(4, true); break;
-    case 16: ABS_KPAIRS(8, false); break;
-    default: ABS_KPAIRS(8, true); break;
+    case 16: if (nth == 512) ABS_KPAIRS_T(8, false, 512); else ABS_KPAIRS(8, false); break;
+    default: if (nth == 512) ABS_KPAIRS_T(8, true, 512); else ABS_KPAIRS(8, true); break;
   }
 #undef ABS_KPAIRS
+#undef ABS_KPAIRS_T
 }
 
 // lanes per cell: enough pairs of realisations for one pass of up to kRec of them
@@ -749,10 +752,11 @@ extern "C" abs_status abs_grid(abs_plan_t p, int64_t nvis, int32_t batch, const 
       if (vec) { ABS_GATHER_L(0, true) } else { ABS_GATHER_L(0, false) }
     } else {
       // unit weights: one lane group per mirror pair of cells
-      const int nth = pair_threads(lpc);
+      const int nth = pair_threads(p->n, lpc);
       const unsigned gp = (unsigned)(((long long)(p->n / 2 + 1) * p->n * lpc + nth - 1) / nth);
-#define ABS_PAIRS(LL, VV)                                                                           \
-  grid_gather_pairs_kernel<LL, VV, false><<<gp, nth, 0, st>>>(p->n, batch, b0, sorted, start, 0, g2, wsum)
+#define ABS_PAIRS_T(LL, VV, TT)                                                                       \
+  grid_gather_pairs_kernel<LL, VV, false, TT><<<gp, TT, 0, st>>>(p->n, batch, b0, sorted, start, 0, g2, wsum)
+#define ABS_PAIRS(LL, VV) ABS_PAIRS_T(LL, VV, kBlock)
       switch (lpc * 2 + (vec ? 1 : 0)) {
         case 2: ABS_PAIRS(1, false); break;
         case 3: ABS_PAIRS(1, true); break;
@@ -760,10 +764,11 @@ extern "C" abs_status abs_grid(abs_plan_t p, int64_t nvis, int32_t batch, const 
         case 5: ABS_PAIRS(2, true); break;
         case 8: ABS_PAIRS(4, false); break;
         case 9: ABS_PAIRS(4, true); break;
-        case 16: ABS_PAIRS(8, false); break;
-        default: ABS_PAIRS(8, true); break;
+        case 16: if (nth == 512) ABS_PAIRS_T(8, false, 512); else ABS_PAIRS(8, false); break;
+        default: if (nth == 512) ABS_PAIRS_T(8, true, 512); else ABS_PAIRS(8, true); break;
       }
 #undef ABS_PAIRS
+#undef ABS_PAIRS_T
     }
 #undef ABS_GATHER_L
 #undef ABS_GATHER
