@@ -155,9 +155,9 @@ def test_sorted_argument_checks():
 
 def test_sorted_full_size_8192():
     """8192^2 grid, 8192^2 MWA-shaped baselines, 16 realisations (the throughput workload's
-    launch: 8 lanes a pair, 512-thread blocks): every cell bit for bit against abs_grid, and 64 cells (dense short baselines,
-    the band edges, both sides of the half plane) against the oracle over the visibilities
-    that reach them."""
+    launch: 8 lanes a pair, 512-thread blocks): every cell bit for bit against abs_grid, and
+    64 cells (dense short baselines, the band edges, both sides of the half plane) against
+    the oracle over the visibilities that reach them."""
     A = _A()
     torch = _torch()
     n, batch = 8192, 16
