@@ -198,8 +198,10 @@ abs_status abs_plan_set_code(abs_plan_t plan, int32_t part, uint64_t key, const 
 
 /* Attach caller-owned device memory of at least plan_bytes bytes (256-byte aligned)
  * to the plan, upload its tables on `stream` and load the compiled kernel on the
- * current device.  The memory must outlive the plan's use.  Errors: ABS_ERR_INVALID,
- * ABS_ERR_NOMEM (bytes too small), ABS_ERR_JIT, ABS_ERR_DEVICE. */
+ * current device; also create, on that device, the plan's second stream (non-blocking,
+ * default priority) and two events, which abs_destroy releases.  The memory must outlive
+ * the plan's use.  Errors: ABS_ERR_INVALID, ABS_ERR_NOMEM (bytes too small), ABS_ERR_JIT,
+ * ABS_ERR_DEVICE. */
 abs_status abs_plan_bind(abs_plan_t plan, void* plan_mem, size_t bytes, void* stream);
 
 /* Device workspace needed by abs_estimate for `batch` grids, when the weights are
@@ -310,8 +312,12 @@ abs_status abs_grid_sorted(abs_plan_t plan, const void* set, size_t set_bytes, i
  *   work       device workspace of abs_estimate_workspace bytes
  *   B          device double [batch][ntrip]  B_t = S_t / (A N_t), overwritten
  *   N          device double [batch][ntrip]  N_t, overwritten; may be NULL
- * Asynchronous on `stream`.  Errors: ABS_ERR_INVALID, ABS_ERR_UNBOUND, ABS_ERR_NOMEM,
- * ABS_ERR_DEVICE. */
+ * Asynchronous on `stream`.  When the weight fields are computed (n_given NULL), they run
+ * on the plan's second stream, forked from `stream` after the call's first launch and
+ * joined back into it before the normalisation, so that they overlap the data fields;
+ * work queued on `stream` after the call sees the whole result.  Calls on one plan from
+ * several host threads at once must be serialised by the caller.  Errors: ABS_ERR_INVALID,
+ * ABS_ERR_UNBOUND, ABS_ERR_NOMEM, ABS_ERR_DEVICE. */
 abs_status abs_estimate(abs_plan_t plan, int32_t batch, int32_t dtype, const void* grids,
                         const float* w, int32_t w_batched, const double* n_given,
                         void* work, size_t work_bytes, double* B, double* N, void* stream);
@@ -449,7 +455,9 @@ abs_status abs_simulate(int32_t nsky, double dtheta, int32_t beam, double beam_p
 
 /* Timing hook: record the caller's HIP events (hipEvent_t passed as void*) on the
  * call's stream immediately before and after the launches of one stage in every later
- * abs_estimate / abs_counts / abs_grid call, until replaced (NULL clears a stage).
+ * abs_estimate / abs_counts / abs_grid call, until replaced (NULL clears a stage).  While
+ * a column- or row-pass hook is set, an estimate's weight fields run after its data fields
+ * on the call's stream (not beside them), so that those hooks time the stages alone.
  * Stages: ABS_STAGE_CONTRACT (triplet contraction), ABS_STAGE_COLPASS (column FFT
  * pass), ABS_STAGE_ROWPASS (row FFT pass), ABS_STAGE_GRID (gridding scatter).
  * The events must outlive those calls.  Errors: ABS_ERR_INVALID. */

@@ -177,6 +177,12 @@ struct abs_plan_s {
   abs_impl::DevLayout dl{};
   void* dev = nullptr;
   int device = -1;
+  // A second stream (default priority, created by abs_plan_bind on the plan's device) and
+  // two events: an estimate's weight sets run there beside its data sets, forked after
+  // the call's first launch on the caller's stream and joined before its normalisation.
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  int aux_device = -1;
   // timing hook: events recorded around one stage's launches (see abs_profile)
   hipEvent_t prof[4][2] = {};
 };
@@ -206,6 +212,8 @@ inline std::vector<const abs_plan_s*> run_plans(const abs_plan_s* p) {
 // there (nullptr when out of range).
 abs_plan_s* part_owner(abs_plan_s* p, int k, int* local);
 void destroy_plan(abs_plan_s* p);
+// Destroys the plan's second stream and its events (on the device they belong to).
+void release_aux(abs_plan_s* p);
 WorkLayout work_layout(const abs_plan_s* p, int grids, int w_batched, int have_counts, int spg = 1);
 void build_mfma_tables(abs_plan_s* p);
 // estimate.hip

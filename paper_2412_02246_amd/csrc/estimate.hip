@@ -207,7 +207,11 @@ std::vector<RunLevel> run_levels(const abs_plan_s* p, const WorkLayout& wl, char
 // the data sets first, weight sets after them.  The Hermitian part (and each set's
 // smallest ring-cell weight) is formed once for the plan; every level plan transforms its
 // own rings from it at its own size and contracts its own triplets.  Stages run one after
-// the other over all levels, so that the timing hooks bracket whole stages.
+// the other over all levels, so that the timing hooks bracket whole stages.  When a call
+// has both, the weight sets (which share nothing with the data sets but the cleared wmin
+// slots) run on the plan's second stream, forked from `st` after the clearing and joined
+// back into `st` at the end, so that their kernels overlap the data sets' ones (1024^2 x
+// 16: 0.744 -> 0.678 ms a step; 8192^2 x 16 within the run-to-run spread).
 // batch: data sets (spg per grid: 1, or 4 for complex input).
 abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int dtype, const void* grids,
                                    const float* w, int w_batched, char* work, hipStream_t st,
@@ -217,12 +221,34 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int dtyp
   // multi-frequency grid's nchan channel sets are one set of nbc channel rings
   const int batch = wl.ndsets, C = p->nchan;
   unsigned long long* wmin = reinterpret_cast<unsigned long long*>(work + wl.wmin);
+  // Hermitian parts: the data sets', then the weight sets'
   void* xc = work + wl.xc;
+  void* xcw = work + wl.xc + (size_t)batch * (size_t)(p->hmax + 1) * (size_t)(2 * p->hmax + 1) * 8;
   {
     const int cnt = batch + wl.nisets;
     fill_u64_kernel<<<(cnt + kBlock - 1) / kBlock, kBlock, 0, st>>>(wmin, cnt, kInfBits);
   }
-  if (batch > 0) {
+  auto weight_sets = [&](hipStream_t sw) -> abs_status {
+    if (launch_herm_weight(p, w, w_batched, wl.nisets, xcw, wmin + batch, sw, mod) != hipSuccess)
+      return ABS_ERR_DEVICE;
+    for (const RunLevel& r : lv)
+      if (launch_colpass_f64(r.q, wl.nisets, xcw, reinterpret_cast<double2*>(r.base + r.wl->zi), r.wl->zset,
+                             sw) != hipSuccess)
+        return ABS_ERR_DEVICE;
+    for (const RunLevel& r : lv)
+      if (launch_rowpass_f64(r.q, wl.nisets, reinterpret_cast<const double2*>(r.base + r.wl->zi), r.wl->zset,
+                             reinterpret_cast<double*>(r.base + r.wl->fi), r.wl->fset64, sw) != hipSuccess)
+        return ABS_ERR_DEVICE;
+    for (const RunLevel& r : lv) {
+      const abs_plan_s* q = r.q;
+      const abs_status s = launch_contract(q, 1, q->waves64, r.base + r.wl->fi, C * r.wl->fset64, q->npix64,
+                                           q->pix_per_block64, q->nblk64, (int)q->ntrip, wl.nipsets,
+                                           reinterpret_cast<double*>(r.base + r.wl->part64), sw);
+      if (s != ABS_OK) return s;
+    }
+    return ABS_OK;
+  };
+  auto data_sets = [&]() -> abs_status {
     prof_begin(p, ABS_STAGE_COLPASS, st);
     if (launch_herm_data(p, grids, dtype, w, w_batched, batch, xc, wmin, st, spg) != hipSuccess)
       return ABS_ERR_DEVICE;
@@ -266,27 +292,29 @@ abs_status run_fields_and_contract(abs_plan_s* p, const WorkLayout& wl, int dtyp
       if (s != ABS_OK) return s;
     }
     prof_end(p, ABS_STAGE_CONTRACT, st);
-  }
-  if (wl.nisets > 0) {
-    if (launch_herm_weight(p, w, w_batched, wl.nisets, xc, wmin + batch, st, mod) != hipSuccess)
+    return ABS_OK;
+  };
+  // the column- and row-pass timing hooks bracket those stages alone: with either set, the
+  // weight sets run after the data sets on `st`
+  const bool hooked = p->prof[ABS_STAGE_COLPASS][0] || p->prof[ABS_STAGE_COLPASS][1] ||
+                      p->prof[ABS_STAGE_ROWPASS][0] || p->prof[ABS_STAGE_ROWPASS][1];
+  if (batch > 0 && wl.nisets > 0 && p->aux != nullptr && !hooked) {
+    if (hipEventRecord(p->fork, st) != hipSuccess || hipStreamWaitEvent(p->aux, p->fork, 0) != hipSuccess)
       return ABS_ERR_DEVICE;
-    for (const RunLevel& r : lv)
-      if (launch_colpass_f64(r.q, wl.nisets, xc, reinterpret_cast<double2*>(r.base + r.wl->zi), r.wl->zset, st) !=
-          hipSuccess)
-        return ABS_ERR_DEVICE;
-    for (const RunLevel& r : lv)
-      if (launch_rowpass_f64(r.q, wl.nisets, reinterpret_cast<const double2*>(r.base + r.wl->zi), r.wl->zset,
-                             reinterpret_cast<double*>(r.base + r.wl->fi), r.wl->fset64, st) != hipSuccess)
-        return ABS_ERR_DEVICE;
-    for (const RunLevel& r : lv) {
-      const abs_plan_s* q = r.q;
-      const abs_status s = launch_contract(q, 1, q->waves64, r.base + r.wl->fi, C * r.wl->fset64, q->npix64,
-                                           q->pix_per_block64, q->nblk64, (int)q->ntrip, wl.nipsets,
-                                           reinterpret_cast<double*>(r.base + r.wl->part64), st);
-      if (s != ABS_OK) return s;
-    }
+    const abs_status sw = weight_sets(p->aux);
+    const bool recorded = hipEventRecord(p->join, p->aux) == hipSuccess;
+    const abs_status sd = data_sets();
+    // joined also after a failed launch, so that `st` does not run ahead of queued work
+    const bool joined = recorded && hipStreamWaitEvent(st, p->join, 0) == hipSuccess;
+    if (sd != ABS_OK) return sd;
+    if (sw != ABS_OK) return sw;
+    return joined ? ABS_OK : ABS_ERR_DEVICE;
   }
-  return ABS_OK;
+  if (batch > 0) {
+    const abs_status sd = data_sets();
+    if (sd != ABS_OK) return sd;
+  }
+  return wl.nisets > 0 ? weight_sets(st) : ABS_OK;
 }
 
 // Device tables of a run plan: partial positions and, for a level plan, its triplet map.
@@ -384,6 +412,18 @@ abs_status abs_plan_bind(abs_plan_t p, void* mem, size_t bytes, void* stream) {
     const abs_status s = bind_tables(q, static_cast<char*>(mem) + q->dev_off, st);
     if (s != ABS_OK) return s;
     q->device = dev;
+  }
+  // the second stream and events of the weight sets, on this device (default priority)
+  if (p->aux_device != dev) {
+    release_aux(p);
+    if (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->join, hipEventDisableTiming) != hipSuccess) {
+      p->aux_device = dev;
+      release_aux(p);
+      return ABS_ERR_DEVICE;
+    }
+    p->aux_device = dev;
   }
   p->dev = mem;
   p->device = dev;

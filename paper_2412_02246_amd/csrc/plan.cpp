@@ -160,7 +160,7 @@ WorkLayout work_layout(const abs_plan_s* p, int grids, int w_batched, int have_c
     w.wmin = off;
     off = al(off + (size_t)(batch + w.nisets) * 8);
     w.xc = off;
-    off = al(off + (size_t)std::max(batch, w.nisets) * (size_t)(p->hmax + 1) * (size_t)(2 * p->hmax + 1) * 8);
+    off = al(off + (size_t)(batch + w.nisets) * (size_t)(p->hmax + 1) * (size_t)(2 * p->hmax + 1) * 8);
     for (const abs_plan_s* q : p->lv) {
       w.lv.push_back(work_layout(q, grids, w_batched, have_counts, spg));
       w.lvbase.push_back(off);
@@ -207,10 +207,11 @@ WorkLayout work_layout(const abs_plan_s* p, int grids, int w_batched, int have_c
   w.wmin = off;
   if (!level) off = al(off + (size_t)(batch + w.nisets) * 8);
   // column-major Hermitian part for the column pass: 8 bytes per cell (FP32 complex for
-  // the data sets, FP64 real for the weight sets), reused by both in turn
+  // the data sets, FP64 real for the weight sets, which follow the data sets: the two run
+  // concurrently)
   w.xc = off;
   if (!level)
-    off = al(off + (size_t)std::max(batch, w.nisets) * (size_t)(p->hmax + 1) * (size_t)(2 * p->hmax + 1) * 8);
+    off = al(off + (size_t)(batch + w.nisets) * (size_t)(p->hmax + 1) * (size_t)(2 * p->hmax + 1) * 8);
   w.total = off;
   return w;
 }
@@ -1063,6 +1064,20 @@ abs_plan_s* part_owner(abs_plan_s* p, int k, int* local) {
   return nullptr;
 }
 
+void release_aux(abs_plan_s* p) {
+  if (!p->aux && !p->fork && !p->join) return;
+  int cur = -1;
+  const bool other = hipGetDevice(&cur) == hipSuccess && p->aux_device >= 0 && cur != p->aux_device;
+  if (other) (void)hipSetDevice(p->aux_device);
+  if (p->aux) (void)hipStreamDestroy(p->aux);
+  if (p->fork) (void)hipEventDestroy(p->fork);
+  if (p->join) (void)hipEventDestroy(p->join);
+  if (other) (void)hipSetDevice(cur);
+  p->aux = nullptr;
+  p->fork = p->join = nullptr;
+  p->aux_device = -1;
+}
+
 void destroy_plan(abs_plan_s* p) {
   if (!p) return;
   bool loaded = false;
@@ -1077,6 +1092,7 @@ void destroy_plan(abs_plan_s* p) {
         if (c.module) (void)hipModuleUnload(c.module);
     if (other) (void)hipSetDevice(cur);
   }
+  release_aux(p);
   for (abs_plan_s* q : p->lv) delete q;
   delete p;
 }
